@@ -1,0 +1,95 @@
+"""Pins for H|psi> (Eq. 1 on the Fourier grid), the KB term and the bounds."""
+import numpy as np
+import scipy.linalg as sla
+
+from oracle.grid import Grid
+from oracle.hamiltonian import Hamiltonian, Projectors, kinetic
+from paper_2601_21005_amd import systems
+
+
+def test_dense_h_symmetric(tiny12):
+    s, H = tiny12
+    A = H.dense()
+    assert np.max(np.abs(A - A.T)) < 1e-12 * np.max(np.abs(A))
+
+
+def test_plane_waves_are_kinetic_eigenvectors():
+    g = Grid(12, 10, 8, h=0.6)
+    H = Hamiltonian(g, np.zeros(g.N))
+    r = g.coords()
+    L = np.array(g.L)
+    for m in [(0, 0, 0), (1, 0, 0), (2, -3, 1), (-6, 5, -4)]:   # incl. Nyquist
+        k = 2 * np.pi * np.array(m) / L
+        psi = np.exp(1j * r @ k)
+        out = H.apply(psi)
+        # (-6, ...) is the Nyquist index along x: exp(+-i k x) coincide on
+        # the grid and T is even, so the eigenvalue is unchanged
+        expect = 0.5 * np.dot(k, k)
+        assert np.allclose(out, expect * psi, atol=1e-11)
+
+
+def test_gaussian_laplacian_closed_form():
+    g = Grid(32, h=0.5)
+    H = Hamiltonian(g, np.zeros(g.N))
+    r = g.coords()
+    c = np.array(g.L) / 2 + np.array([0.13, -0.21, 0.05])
+    s = 1.2
+    d2 = np.sum(g.min_image(r - c) ** 2, axis=1)
+    f = np.exp(-d2 / (2 * s * s))
+    # -1/2 lap exp(-r^2/2s^2) = -1/2 f (r^2/s^4 - 3/s^2)
+    expect = -0.5 * f * (d2 / s ** 4 - 3.0 / s ** 2)
+    assert np.max(np.abs(H.apply(f) - expect)) < 1e-8
+
+
+def test_kinetic_cutoff_clips():
+    g = Grid(16, h=0.5)
+    T = kinetic(g, 5.0)
+    T0 = kinetic(g)
+    assert np.all(T <= 5.0) and np.allclose(T[T0 <= 5.0], T0[T0 <= 5.0])
+    assert np.isclose(T0.max(), 1.5 * (np.pi / 0.5) ** 2)
+
+
+def test_projector_shape_and_normalisation(tiny12):
+    s, H = tiny12
+    P = H.kb
+    g = H.grid
+    B = P.B.toarray()
+    assert np.allclose(g.dV * np.sum(B * B, axis=0), 1.0)
+    r = g.coords()
+    # s projector radial about its atom; p_x odd in x about its atom
+    d0 = g.min_image(r - s.projectors.pos[0])
+    rad = np.sqrt(np.sum(d0 ** 2, axis=1))
+    nz = B[:, 0] != 0
+    assert np.all(B[nz, 0] > 0)
+    order = np.argsort(rad[nz])
+    assert np.all(np.diff(B[nz, 0][order]) <= 1e-15)
+    d1 = g.min_image(r - s.projectors.pos[1])
+    nz1 = B[:, 1] != 0
+    assert np.all(np.sign(B[nz1, 1]) == np.sign(d1[nz1, 0]))
+    # cut radius respected
+    assert np.max(rad[nz]) <= 3.0 * 0.75 + 1e-12
+
+
+def test_nonlocal_matches_dense_sum(tiny8):
+    s, H = tiny8
+    g = H.grid
+    B = H.kb.B.toarray()
+    Vnl = g.dV * B @ np.diag(H.kb.ekb) @ B.T
+    psi = np.random.default_rng(1).standard_normal((3, g.N))
+    assert np.allclose(H.kb.apply(psi), psi @ Vnl.T, atol=1e-12)
+
+
+def test_bounds_enclose_spectrum(tiny12, tiny12_eig):
+    s, H = tiny12
+    e, _ = tiny12_eig
+    lo, hi = H.bounds(pad=0.0)
+    assert lo <= e.min() + 1e-10 and e.max() <= hi + 1e-10
+    S = H.kb.gram()
+    lam = sla.eigvalsh(S).max()
+    assert lam <= np.max(np.sum(np.abs(S), axis=1)) + 1e-12
+
+
+def test_cluster_projector_count_and_occupation():
+    s = systems.si35h36()
+    assert s.projectors.nproj == 35 * 4 + 36
+    assert s.n_occ == 88

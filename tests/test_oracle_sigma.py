@@ -1,0 +1,145 @@
+"""Pins for the per-sample Sigma_c(t) estimator (Eq. 4, Eq. 5), the
+exchange X, and the stochastic traces behind them."""
+import numpy as np
+
+from closed_forms import casida, uR_closed, zeta_closed
+from oracle import chebyshev as cheb
+from oracle import rng
+from oracle.sigma import SGWParams, exchange, sample_sigma
+from oracle.sroi import XiBasis
+from oracle.tdh import hartree
+from oracle.timeorder import time_order
+
+
+def _params(H, e, n_occ, **kw):
+    emin, emax = H.bounds()
+    mu = 0.5 * (e[n_occ - 1] + e[n_occ])
+    beta = 10.0
+    ncoef = cheb.suggested_ncoef(mu, beta, emin, emax, tol=1e-12, nmax=8192)
+    base = dict(seed=77, n_zeta=1, n_eta=4, n_tau=16, dt=0.2, m_sub=8, mu=mu,
+                beta=beta, ncoef=ncoef, emin=emin, emax=emax, mode="exact",
+                n_xi=64, f_g=0.125)
+    base.update(kw)
+    return SGWParams(**base)
+
+
+def test_sigma_sample_matches_closed_form(tiny8, tiny8_eig):
+    """Deterministic-eta limit: the oracle's exact-mode Sigma_i(t) equals the
+    closed form built from the eigenpairs (zeta^+-) and Casida (u^R), with
+    the same discrete time ordering applied to the closed-form u^R."""
+    s, H = tiny8
+    e, V = tiny8_eig
+    g = H.grid
+    n_occ = s.n_occ
+    p = _params(H, e, n_occ)
+    phi = V[n_occ - 1]
+    zb = rng.white_noise(5, rng.ZETA, 0, 0, g.N, g.dV)
+    sig, X, parts = sample_sigma(H, phi, p, 0, return_parts=True, zb=zb,
+                                 eta_det=V[:n_occ], eta_weight=2.0)
+    t = p.dt * np.arange(p.n_tau + 1)
+    f = cheb.fermi(e, p.mu, p.beta)
+    zp, zm = zeta_closed(g, e, V, f, zb, t)
+    assert np.max(np.abs(parts["zps"] - zp)) < 1e-10 * np.max(np.abs(zp))
+    assert np.max(np.abs(parts["zms"] - zm)) < 1e-10 * np.max(np.abs(zm))
+    Om, Vn = casida(g, e, V, n_occ)
+    uR = uR_closed(g, Om, Vn, phi, zb, t)
+    u = time_order(uR.T).T
+    sp = g.dV * np.sum(phi * zp * u, axis=1)
+    sm = g.dV * np.sum(phi * zm * u, axis=1)
+    ref = np.concatenate([sm[1:][::-1], [0.5 * (sp[0] + sm[0])], sp[1:]])
+    assert np.max(np.abs(sig - ref)) < 2e-3 * np.max(np.abs(ref))
+    # Sigma(t) of a real H: the -t half is the backward (occupied) branch
+    assert np.max(np.abs(ref)) > 0
+
+
+def test_complete_basis_gives_g0w0(tiny8, tiny8_eig):
+    """Summing the single-sample closed form over the complete grid basis
+    zeta-bar = e_k / sqrt(dV) gives the deterministic G0W0 form
+    Sigma_c(t > 0) = -i sum_{a,n} (1 - f_a) (phi phi_a | V_n)^2
+    e^{-i (e_a + Omega_n) t}  (continuous time ordering of u^R)."""
+    s, H = tiny8
+    e, V = tiny8_eig
+    g = H.grid
+    n_occ = s.n_occ
+    phi = V[n_occ - 1]
+    f = cheb.fermi(e, 0.5 * (e[1] + e[2]), 10.0)
+    Om, Vn = casida(g, e, V, n_occ)
+    t = 0.37
+    M = g.dV * (phi[None, :] * V) @ Vn.T              # (phi phi_a | V_n)
+    g0w0 = -1j * np.sum((1 - f)[:, None] * M ** 2 * np.exp(-1j * (e[:, None] + Om[None, :]) * t))
+    # closed-form single sample, continuous TO: u = -i sum_n e^{-i W t} V_n <V_n|phi zb>
+    tot = 0.0
+    for k in range(g.N):
+        zb = np.zeros(g.N)
+        zb[k] = 1 / np.sqrt(g.dV)
+        zp, _ = zeta_closed(g, e, V, f, zb, np.array([t]))
+        amp = g.dV * Vn @ (phi * zb)
+        u = -1j * (np.exp(-1j * Om * t) * amp) @ Vn
+        tot += g.dV * np.sum(phi * zp[0] * u)
+    assert abs(tot - g0w0) < 1e-10 * abs(g0w0)
+
+
+def test_exchange_complete_basis(tiny8, tiny8_eig):
+    """Sum over the complete eta-bar basis of the sROI exchange estimator =
+    -sum_k f_k^2 (phi phi_k | v | phi phi_k)."""
+    s, H = tiny8
+    e, V = tiny8_eig
+    g = H.grid
+    phi = V[s.n_occ - 1]
+    emin, emax = H.bounds()
+    mu, beta = 0.5 * (e[1] + e[2]), 10.0
+    N = cheb.suggested_ncoef(mu, beta, emin, emax, tol=1e-12, nmax=8192)
+    a = cheb.fermi_coefficients(mu, beta, emin, emax, N)
+    eta = cheb.apply_series(H, a, emin, emax, np.eye(g.N) / np.sqrt(g.dV))
+    Xsum = exchange(g, phi, eta) * g.N
+    f = cheb.fermi(e, mu, beta)
+    pp = phi[None, :] * V
+    ref = -np.sum(f ** 2 * g.dV * np.sum(pp * hartree(g, pp), axis=1))
+    assert abs(Xsum - ref) < 1e-9 * abs(ref)
+
+
+def test_hutchinson_trace(tiny8, tiny8_eig):
+    """mean <zeta-bar|F(H)|zeta-bar> -> Tr F(H) for +-1/sqrt(dV) noise."""
+    s, H = tiny8
+    e, V = tiny8_eig
+    g = H.grid
+    f = cheb.fermi(e, 0.5 * (e[1] + e[2]), 10.0)
+    vals = []
+    for i in range(3000):
+        z = rng.white_noise(21, rng.ZETA, i, 0, g.N, g.dV)
+        c = g.dV * V @ z
+        vals.append(np.sum(f * c * c))
+    vals = np.array(vals)
+    assert abs(vals.mean() - f.sum()) < 4 * vals.std() / np.sqrt(vals.size)
+
+
+def test_xi_mode_assembly_and_unbiasedness(tiny8, tiny8_eig):
+    s, H = tiny8
+    e, V = tiny8_eig
+    g = H.grid
+    p = _params(H, e, s.n_occ, n_tau=6, m_sub=2, mode="xi")
+    phi = V[s.n_occ - 1]
+    sig_x, X, px = sample_sigma(H, phi, p, 3, return_parts=True)
+    from dataclasses import replace
+    sig_e, X2, pe = sample_sigma(H, phi, replace(p, mode="exact"), 3, return_parts=True)
+    assert X == X2
+    # same random numbers: the xi-mode result is the xi contraction of the
+    # exact-mode fields
+    xi = XiBasis(p.seed, 3, g.N, p.n_xi, p.f_g, g.dV)
+    c = time_order(np.array([xi.overlaps(u) for u in pe["uR"]]).T)
+    dp = np.array([xi.overlaps(phi * z) for z in pe["zps"]]).T
+    assert np.allclose(np.sum(c * dp, axis=0)[1:], sig_x[p.n_tau + 1:], rtol=1e-12, atol=1e-14)
+    # averaging the xi contraction over xi sets recovers the exact mode
+    acc = []
+    for sd in range(400):
+        xi = XiBasis(1000 + sd, 0, g.N, p.n_xi, p.f_g, g.dV)
+        c = time_order(np.array([xi.overlaps(u) for u in pe["uR"]]).T)
+        dp = np.array([xi.overlaps(phi * z) for z in pe["zps"]]).T
+        acc.append(np.sum(c * dp, axis=0)[1:])
+    acc = np.array(acc)
+    m = acc.mean(axis=0)
+    se_r = acc.real.std(axis=0) / np.sqrt(len(acc))
+    se_i = acc.imag.std(axis=0) / np.sqrt(len(acc))
+    ref = sig_e[p.n_tau + 1:]
+    assert np.all(np.abs(m.real - ref.real) < 4.5 * se_r)
+    assert np.all(np.abs(m.imag - ref.imag) < 4.5 * se_i)
