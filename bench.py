@@ -1,0 +1,223 @@
+#!/usr/bin/env python3
+"""Benchmark of the sGW/sROI hot path on one MI355X.
+
+Workload: the Si35H36-shaped cluster on a 64^3 grid (h = 0.5 bohr, kinetic
+cutoff 28 Ha), local Gaussian pseudopotentials plus s/p Kleinman-Bylander
+projectors (176 projectors, 88 occupied states), N_eta = 64 stochastic
+occupied orbitals per Monte Carlo sample, TDH linear response over 400 steps
+of dt = 0.05 a.u., N_xi = 10000 sparse functions at f_g = 0.003, Fermi
+filter with mu mid-gap and beta = 28 / gap, complex FP32 bulk arithmetic.
+
+One step = the whole hot path (white noise, filter, TDH with xi overlaps,
+time ordering, zeta propagation, contraction) for a batch of samples, through
+sgw_sigma_estimate.  The QP energy of the HOMO and its per-sample spread give
+GPU-seconds per QP energy at +-0.03 eV.  Printed as one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HA_EV = 27.211386245988
+METRIC = ("GPU-s per QP energy at +/-0.03 eV (plain vs chosen); "
+          "Hpsi Gpt*vec/s vs HBM roofline")
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per (grid point x complex vector) of the dominant kernel,
+# the inverse xy-plane pass carrying the Chebyshev update: the real FP32
+# filter term reads v_n, v_{n-1}, acc and writes v_{n+1}, acc (20 B per real
+# vector), two real vectors per complex vector -> 40 B.
+CHEB_ALGO_BYTES = 40.0
+# H psi in complex FP32: read psi, write H psi
+HPSI_ALGO_BYTES = 16.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--batch", type=int, default=8, help="samples per step")
+    ap.add_argument("--n-tau", type=int, default=400)
+    ap.add_argument("--n-eta", type=int, default=64)
+    ap.add_argument("--quick", action="store_true", help="short functional run")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-terms", type=int, default=6,
+                    help="filter terms timed for the CPU baseline sample")
+    return ap.parse_args()
+
+
+def suggested_ncoef(sgw, mu, beta, emin, emax, tol):
+    import numpy as np
+    for nmax in (2048, 4096, 8192, 16384, 32768):
+        a = sgw.sgw_fermi_coefficients(mu, beta, emin, emax, nmax)
+        tail = np.cumsum(np.abs(a[::-1]))[::-1]
+        ok = np.nonzero(tail < tol)[0]
+        if ok.size and ok[0] < nmax // 2:
+            return int(ok[0])
+    raise RuntimeError("filter too long")
+
+
+def cpu_baseline(system, phi, p, n_terms, ncoef):
+    """Time the FP64 oracle on a bounded sample of one Monte Carlo sample:
+    n_terms filter terms on its 65 real vectors, 2 TDH substeps on its
+    2 x 64 orbitals and 2 zeta propagation steps; scale each to the full
+    counts (ncoef terms, n_tau steps)."""
+    import numpy as np
+    from oracle import chebyshev as cheb
+    from oracle.grid import Grid
+    from oracle.hamiltonian import Hamiltonian, Projectors
+    from oracle.tdh import TDH, hartree
+    from oracle import rng
+    workers = os.cpu_count()
+    g = Grid(system.grid.n, h=system.grid.h, workers=workers)
+    pr = system.projectors
+    P = Projectors(g, pr.pos, pr.atom_of, pr.l, pr.m, pr.rc, pr.ekb, pr.rcut_over_rc)
+    H = Hamiltonian(g, system.v_loc, P, system.ecut)
+    zb = rng.white_noise(p["seed"], rng.ZETA, 0, 0, g.N, g.dV)
+    eb = np.stack([rng.white_noise(p["seed"], rng.ETA, 0, l, g.N, g.dV)
+                   for l in range(p["n_eta"])])
+    x = np.vstack([zb[None], eb])
+    a = cheb.fermi_coefficients(p["mu"], p["beta"], p["emin"], p["emax"], n_terms)
+    t0 = time.perf_counter()
+    cheb.apply_series(H, a, p["emin"], p["emax"], x)
+    t_filter = (time.perf_counter() - t0) / max(1, n_terms - 1) * (ncoef - 1)
+    tdh = TDH(H, p["dt"] / p["m_sub"], 2.0 / p["n_eta"])
+    st = tdh.start(eb[:p["n_eta"]], hartree(g, phi * zb))
+    t0 = time.perf_counter()
+    for _ in range(2):
+        st = tdh.substep(*st)
+    t_tdh = (time.perf_counter() - t0) / 2 * p["n_tau"] * p["m_sub"]
+    b = cheb.propagator_coefficients(p["emin"], p["emax"], p["dt"])
+    z = np.vstack([zb, zb]).astype(np.complex128)
+    t0 = time.perf_counter()
+    for _ in range(2):
+        z = cheb.apply_series(H, b, p["emin"], p["emax"], z)
+    t_zeta = (time.perf_counter() - t0) / 2 * p["n_tau"]
+    total = t_filter + t_tdh + t_zeta
+    sample = (f"one Monte Carlo sample extrapolated from {n_terms} filter terms "
+              f"(x {ncoef}), 2 TDH substeps (x {p['n_tau'] * p['m_sub']}) and 2 zeta "
+              f"steps (x {p['n_tau']}); FP64 numpy/scipy oracle, scipy.fft workers = "
+              f"{workers}")
+    return total, dict(filter=t_filter, tdh=t_tdh, zeta=t_zeta), workers, sample
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported "
+              "(samples are independent; see the sharding note in DESIGN.md)",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2601_21005_amd import ksinput, sgw, systems
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    torch.cuda.set_device(0)
+    if args.quick:
+        args.n_tau, args.n_eta, args.batch = 20, 8, 2
+
+    s = systems.si35h36()
+    dV = s.grid.h ** 3
+    ctx = sgw.Context(s.grid.n, s.grid.h, s.v_loc, s.projectors, precision=sgw.SGW_C64,
+                      ecut=s.ecut, max_nvec=256)
+    emin, emax = ctx.bounds(0.01)
+    ev, phis, res = ksinput.lowest_states(ctx, s.n_occ + 1, emin, emax, dV)
+    homo, lumo = float(ev[s.n_occ - 1]), float(ev[s.n_occ])
+    gap = lumo - homo
+    phi = phis[s.n_occ - 1].cpu().numpy()
+    mu, beta = 0.5 * (homo + lumo), 28.0 / gap
+    ncoef = suggested_ncoef(sgw, mu, beta, emin, emax, 1e-7)
+    if args.quick:
+        ncoef = min(ncoef, 400)
+    p = dict(seed=1002, n_eta=args.n_eta, n_tau=args.n_tau, dt=0.05, m_sub=1, mu=mu,
+             beta=beta, ncoef=ncoef, emin=emin, emax=emax, n_xi=10000, f_g=0.003, mode=0)
+    B = args.batch
+
+    for w in range(args.warmup):
+        ctx.sigma_estimate(phi, n_zeta=B, first_sample=w * B, **p)
+    torch.cuda.synchronize()
+    ctx.kernel_timer(True)
+    sigs, xs, phases = [], [], np.zeros(6)
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        sig, x, ms = ctx.sigma_estimate(phi, n_zeta=B, first_sample=(args.warmup + k) * B, **p)
+        sigs.append(sig)
+        xs.append(x)
+        phases += ms
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t0
+    ctx.kernel_timer(False)
+    k_ms, k_launch, k_pts = ctx.kernel_timer_read()
+
+    sig = np.concatenate(sigs)
+    x = np.concatenate(xs)
+    nsamp = sig.shape[0]
+    gam = 3.0 / (p["n_tau"] * p["dt"])
+    eg, el, Z = sgw.sgw_qp_solve(sig.mean(0), p["dt"], gam, homo, x.mean())
+    re_i = np.array([sgw.sgw_sigma_omega(si, p["dt"], gam, eg)[0].real for si in sig])
+    sigma1 = Z * np.std(x + re_i, ddof=1) * HA_EV
+    err = sigma1 / np.sqrt(nsamp)
+    t_sample = t_total / nsamp
+    gpu_s_per_qp = t_sample * (sigma1 / 0.03) ** 2
+
+    # H psi throughput (local + KB), batch of 256 complex FP32 vectors
+    nv, reps = 256, 20
+    xh = torch.randn((nv, s.grid.N), dtype=torch.complex64, device="cuda")
+    yh = torch.empty_like(xh)
+    ctx.apply_H(xh, yh)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        ctx.apply_H(xh, yh)
+    torch.cuda.synchronize()
+    hpsi_rate = nv * reps * s.grid.N / (time.perf_counter() - t1)
+
+    achieved = CHEB_ALGO_BYTES * k_pts / (k_ms * 1e-3) / 1e9 if k_ms > 0 else None
+    line = {
+        "metric": METRIC,
+        "value": gpu_s_per_qp,
+        "unit": "GPU-s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * t_total / args.steps,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64",
+        "data": "synthetic",
+        "config": {"workload": "Si35H36-shaped cluster, 64^3 grid h=0.5, KB s/p "
+                               "projectors, N_eta=64, TDH 400 x 0.05 au, N_xi=10000, "
+                               "f_g=0.003, Fermi filter beta=28/gap, complex FP32",
+                   "samples_per_step": B, "n_tau": p["n_tau"], "n_eta": p["n_eta"],
+                   "ncoef": ncoef, "quick": bool(args.quick)},
+        "qp": {"eps_ks_homo_eV": homo * HA_EV, "gap_eV": gap * HA_EV,
+               "eqp_homo_eV": eg * HA_EV, "eqp_lin_eV": el * HA_EV, "Z": Z,
+               "stat_err_eV": err, "sigma1_eV": sigma1, "samples": nsamp,
+               "gpu_s_per_sample": t_sample},
+        "hpsi_gptvec_per_s": hpsi_rate / 1e9,
+        "hpsi_algo_roofline_frac": hpsi_rate * HPSI_ALGO_BYTES / (HBM_PEAK_GBS * 1e9),
+        "phase_ms": {"filter": phases[0], "tdh": phases[1], "time_order": phases[2],
+                     "zeta_contract": phases[3], "other": phases[4], "total": phases[5]},
+        "roofline": {"bound": "hbm", "kernel": "k_plane<float,64,64,PLANE_INV_CHEB>",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS if achieved else None,
+                     "traffic": None, "launches": k_launch,
+                     "avg_launch_us": 1e3 * k_ms / k_launch if k_launch else None},
+    }
+    if not args.no_cpu_baseline:
+        tcpu, parts, cores, sample = cpu_baseline(s, phi, p, args.cpu_terms, ncoef)
+        line["cpu_baseline"] = {"value": tcpu * (sigma1 / 0.03) ** 2, "unit": "CPU-s",
+                                "cores": cores, "kind": "oracle", "sample": sample,
+                                "seconds_per_sample": tcpu, "parts_s": parts}
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,258 @@
+/*
+ * sgw.h -- C ABI of the MI355X stochastic-GW hot-path library (libsgw).
+ *
+ * The library applies the Kohn-Sham Hamiltonian of Eq. (1) on a periodic
+ * real-space grid to large batches of stochastic orbitals and runs the three
+ * loops built on it in arXiv 2601.21005 (StochasticGW-GPU): the Chebyshev
+ * occupied-space filter of Eq. (3), the time-dependent-Hartree linear
+ * response that builds W (Sec. 2.1, first phase), and the propagation of the
+ * stochastic Green's-function orbitals of Eq. (4) with the sROI contraction
+ * of Eq. (5); Eq. (6) and Eq. (7) give the QP energy.
+ *
+ * Conventions shared by every call
+ *  - Units are Hartree atomic units.
+ *  - Grid: points r = h (ix, iy, iz), flat index ix + nx (iy + ny iz),
+ *    periodic box of nx h x ny h x nz h bohr.  <f|g> = h^3 sum conj(f) g.
+ *  - Precision SGW_C128: device vectors are interleaved complex double
+ *    (16 B per point); SGW_C64 and SGW_C64_BF16KB: interleaved complex float
+ *    (8 B per point).  Real fields (densities, potentials) are double resp.
+ *    float.
+ *  - A batch of nvec device vectors is nvec consecutive blocks of ld >= N_g
+ *    complex elements (N_g = nx ny nz); pointers are caller-owned HIP device
+ *    pointers, 16-byte aligned.  Host pointers are marked "host".
+ *  - Every call enqueues its work on the context's stream; calls that return
+ *    host results synchronise that stream before returning.
+ *  - Errors are returned as sgw_status; nothing aborts or throws across the
+ *    ABI.  sgw_last_error() gives the message of the last failing call made
+ *    on that context (or of the last failing sgw_create in this thread).
+ *  - One context per stream; calls on one context must not overlap.
+ */
+#ifndef SGW_H
+#define SGW_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sgw_ctx sgw_ctx;
+
+typedef enum {
+  SGW_OK = 0,
+  SGW_EINVAL = -1,        /* invalid argument (size, pointer, non-finite input) */
+  SGW_ENOMEM = -2,        /* device or host allocation failed */
+  SGW_EHIP = -3,          /* a HIP runtime call failed */
+  SGW_EDIVERGED = -4,     /* a Chebyshev recurrence grew: bounds too narrow */
+  SGW_ENOROOT = -5,       /* the QP equation has no root in the search window */
+  SGW_EUNSUPPORTED = -6   /* grid size or option not built into this library */
+} sgw_status;
+
+typedef enum {
+  SGW_C128 = 0,           /* complex double throughout */
+  SGW_C64 = 1,            /* complex float; FP64 coefficients and sums */
+  SGW_C64_BF16KB = 2      /* as SGW_C64 (BF16 projector GEMMs: not built yet) */
+} sgw_precision;
+
+/* Grid (Eq. 1 on a Fourier grid, Sec. 2.2).  ecut > 0 clips the kinetic
+ * energy T(k) = |k|^2/2 at ecut (Sec. 3: "energy cutoff ... to the kinetic
+ * energy operator"); ecut <= 0 leaves it unclipped.  Each of nx, ny, nz must
+ * be one of the built FFT lengths (8, 12, 16, 24, 32, 40, 48, 56, 64, 80,
+ * 96, 112, 128) with nx == ny, and nx*ny*sizeof(complex) small enough for one
+ * xy plane to fit in LDS; otherwise SGW_EUNSUPPORTED. */
+typedef struct {
+  int32_t nx, ny, nz;
+  double h;               /* grid spacing, bohr */
+  double ecut;            /* kinetic cutoff, Ha (<= 0: none) */
+} sgw_grid;
+
+/* Kleinman-Bylander projectors (the separable non-local pseudopotential part
+ * whose neighbouring spheres overlap, Sec. 3).  Projector p sits on atom
+ * a(p) (CSR: projectors proj_begin[a] .. proj_begin[a+1]-1 belong to atom a)
+ * with angular channel l in {0, 1} and component m (l = 1: 0 = x, 1 = y,
+ * 2 = z):
+ *     beta_p(r) = N_p Y_lm(d) exp(-|d|^2 / (2 rc^2)),  |d| <= rcut_over_rc rc,
+ *     Y_00 = 1, Y_1m = d_m,  d = minimum-image r - R_a,
+ * N_p normalising <beta_p|beta_p> = 1 on the grid, and
+ *     V_NL = sum_p |beta_p> ekb_p <beta_p|.
+ * All arrays are host arrays, copied by sgw_create. */
+typedef struct {
+  int32_t natom;
+  const double *pos;          /* host [natom][3], bohr */
+  const int32_t *proj_begin;  /* host [natom + 1] */
+  const int32_t *l;           /* host [nproj] */
+  const int32_t *m;           /* host [nproj] */
+  const double *rc;           /* host [nproj], bohr */
+  const double *ekb;          /* host [nproj], Ha */
+  double rcut_over_rc;        /* support radius in units of rc (> 0) */
+} sgw_projectors;
+
+/* Create a context: H = T + V_loc + V_NL on the grid (Eq. 1).  v_loc is a
+ * host [N_g] array (Ha, x fastest) holding the whole local potential;
+ * projectors may be NULL (local-only H).  hip_stream is a hipStream_t (NULL
+ * = the null stream).  max_nvec bounds the batch of the vector-level calls
+ * (sgw_apply_H, sgw_fermi_filter, sgw_cheb_propagate process larger batches
+ * in chunks of max_nvec); the context's scratch is sized from it.  All host
+ * inputs are copied.  On failure *out is NULL and the message is available
+ * from sgw_last_error(NULL). */
+sgw_status sgw_create(const sgw_grid *grid, const double *v_loc,
+                      const sgw_projectors *projectors, sgw_precision prec,
+                      void *hip_stream, int64_t max_nvec, sgw_ctx **out);
+
+/* Release every resource of the context (NULL is ignored). */
+void sgw_destroy(sgw_ctx *ctx);
+
+/* Message of the last failing call on ctx (ctx = NULL: last failing
+ * sgw_create of the calling thread).  Valid until the next call. */
+const char *sgw_last_error(const sgw_ctx *ctx);
+
+/* Rigorous spectral interval of H (Weyl): [min V + lo, T_max + max V + hi]
+ * where [lo, hi] encloses spec(V_NL) by the Gershgorin bound of the
+ * projector Gram matrix, widened by pad times its width on each side.  The
+ * paper finds the interval by shifted power iteration (Sec. 2.1); any
+ * enclosing interval serves the Chebyshev maps that follow. */
+sgw_status sgw_bounds(sgw_ctx *ctx, double pad, double *emin, double *emax);
+
+/* hpsi[v] = H psi[v] for v < nvec (Eq. 1; Sec. 2.2: FFT pair for the
+ * kinetic term, potential diagonal in r).  psi and hpsi are device batches
+ * with leading dimension ld; they must not overlap. */
+sgw_status sgw_apply_H(sgw_ctx *ctx, const void *psi, void *hpsi,
+                       int64_t nvec, int64_t ld);
+
+/* Chebyshev coefficients of the Fermi filter F(E) = 1/(1 + e^{beta(E-mu)})
+ * on [emin, emax] (Eq. 3 with the step smoothed), by Chebyshev-Gauss
+ * quadrature on M = 4 ncoef nodes:
+ *   a_n = (2 - delta_n0)/M sum_j F(c + R cos t_j) cos(n t_j),
+ *   t_j = pi (j + 1/2)/M, c = (emax+emin)/2, R = (emax-emin)/2.
+ * coef: host [ncoef] output.  Pure host computation. */
+sgw_status sgw_fermi_coefficients(double mu, double beta, double emin,
+                                  double emax, int32_t ncoef, double *coef);
+
+/* In place: v[k] <- sum_{n<ncoef} coef[n] T_n((H - c)/R) v[k] (Eq. 3) for
+ * k < nvec, by the three-term recurrence.  The filter is real, so complex
+ * vectors may carry two real orbitals each (real and imaginary parts).
+ * coef: host [ncoef].  [emin, emax] must enclose spec(H); a recurrence that
+ * grows anyway returns SGW_EDIVERGED (v is then undefined). */
+sgw_status sgw_fermi_filter(sgw_ctx *ctx, void *v, int64_t nvec, int64_t ld,
+                            const double *coef, int32_t ncoef, double emin,
+                            double emax);
+
+/* Coefficients b_n of exp(-i H tau) = sum_n b_n T_n((H - c)/R) (Jacobi-Anger
+ * expansion, b_n = e^{-i c tau} (2 - delta_n0) (-i)^n J_n(R tau)), truncated
+ * at the first n > R|tau| with |J_n(R|tau|)| < tol.  J_n by Miller's backward
+ * recurrence.  coef: host [max_terms][2] (re, im); *nterms receives the count
+ * (SGW_EINVAL if it exceeds max_terms).  Pure host computation. */
+sgw_status sgw_propagator_coefficients(double emin, double emax, double tau,
+                                       double tol, int32_t max_terms,
+                                       double *coef, int32_t *nterms);
+
+/* In place: psi[k] <- exp(-i H dt)^nsteps psi[k] (the propagator of the
+ * zeta orbitals, Sec. 2.1 second phase), one Chebyshev series per step with
+ * the coefficients of sgw_propagator_coefficients(emin, emax, dt, tol). */
+sgw_status sgw_cheb_propagate(sgw_ctx *ctx, void *psi, int64_t nvec,
+                              int64_t ld, double dt, int32_t nsteps,
+                              double emin, double emax, double tol);
+
+/* Linear-response TDH state for nsample Monte Carlo samples (Sec. 2.1 first
+ * phase; Sec. 2.3 packs the unperturbed and perturbed copies together).
+ * Device arrays, caller-owned:
+ *   psi  [nsample][2][neta][N_g] complex: copy 0 = eta_l(t), copy 1 = the
+ *        tangent delta-eta_l(t) of the perturbed copy (lambda -> 0 limit of
+ *        (eta^lambda - eta)/lambda);
+ *   v    [nsample][N_g] real: V(t) = V_loc + v_H[n(t)] - v_H[n(0)];
+ *   u    [nsample][N_g] real: u^R(t) = v_H[delta n(t)];
+ *   vh0  [nsample][N_g] real: v_H[n(0)];
+ * with n = weight sum_l |eta_l|^2, delta n = weight sum_l 2 Re(conj(eta_l)
+ * delta-eta_l) and v_H[rho] = F^{-1}[4 pi/|k|^2 F[rho]] (k = 0 dropped). */
+typedef struct {
+  int32_t nsample;
+  int32_t neta;
+  double weight;
+  void *psi;
+  void *v;
+  void *u;
+  void *vh0;
+} sgw_tdh_state;
+
+/* Start the response: given eta(0) in copy 0 of psi and the kick potential
+ * dv (device [nsample][N_g] real, dv_i = v_H[phi zeta-bar_i]), set
+ * delta-eta(0) = -i dv eta(0), vh0 = v_H[n(0)], v = V_loc, u = v_H[delta
+ * n(0)] (= 0). */
+sgw_status sgw_tdh_init(sgw_ctx *ctx, sgw_tdh_state *st, const void *dv);
+
+/* Advance the state by nsub Strang substeps of length dt_sub:
+ *   exp(-i V(t) tau/2), exp(-i V_NL tau/2), F^-1 exp(-i T tau) F,
+ *   exp(-i V_NL tau/2), densities -> V(t+tau), u^R(t+tau),
+ *   exp(-i V(t+tau) tau/2),
+ * where the local half steps act on the tangent copy as
+ *   delta-eta <- exp(-i V a)(delta-eta - i a u^R eta)   (a = tau/2)
+ * (the exact tangent of the finite-lambda step). */
+sgw_status sgw_tdh_step(sgw_ctx *ctx, sgw_tdh_state *st, int32_t nsub,
+                        double dt_sub);
+
+/* Parameters of one stochastic Sigma_c(t) estimate (Sec. 2.1, Table 2). */
+typedef struct {
+  uint64_t seed;          /* counter-based RNG seed (SplitMix64 streams) */
+  int32_t first_sample;   /* global index of the first Monte Carlo sample */
+  int32_t n_zeta;         /* number of samples in this call */
+  int32_t n_eta;          /* stochastic occupied orbitals per sample (even) */
+  int32_t n_tau;          /* output time steps on each side of t = 0 */
+  double dt;              /* output time step, a.u. */
+  int32_t m_sub;          /* TDH Strang substeps per output step */
+  double mu, beta;        /* Fermi filter */
+  int32_t ncoef;          /* filter length */
+  double emin, emax;      /* spectral interval for every Chebyshev map */
+  int32_t n_xi;           /* sparse stochastic functions per sample */
+  double f_g;             /* grid fraction of each xi (segments of 32) */
+  int32_t mode;           /* 0: sparse xi basis; 1: exact (full-grid u) */
+  double prop_tol;        /* Jacobi-Anger truncation of the zeta propagator */
+  int32_t n_ft;           /* time-ordering FFT length (0: smallest power of
+                             two >= 4 (n_tau + 1)) */
+  int32_t batch;          /* samples resident on the device at once (0: all) */
+} sgw_sigma_params;
+
+/* Per-sample Sigma_c,i(t_j), j = -n_tau..n_tau, and exchange X_i for the
+ * orbital phi (host [N_g] real, <phi|phi> = 1), following Sec. 2.1:
+ * white noise -> filter (Eq. 3) -> TDH response u^R in the xi basis ->
+ * time ordering -> zeta^+ forward / occupied part backward (Eq. 4) ->
+ * contraction (Eq. 5).  sigma_t: host [n_zeta][2 n_tau + 1][2] (re, im);
+ * x: host [n_zeta]; phase_ms: nullable host [6] receiving the device time
+ * of the phases (filter, tdh, time order, zeta, contraction, total).
+ * Requires N_g to be a multiple of 32 in xi mode. */
+sgw_status sgw_sigma_estimate(sgw_ctx *ctx, const sgw_sigma_params *params,
+                              const double *phi, double *sigma_t, double *x,
+                              double *phase_ms);
+
+/* QP energy from the sample-mean Sigma_c(t_j) (host [2 n_tau + 1][2]):
+ *   Sigma(w) = dt sum_j w_j e^{-gamma^2 t_j^2/2} e^{i w t_j} Sigma(t_j)
+ * (Eq. 7, trapezoid weights), Z = 1/(1 - d Re Sigma/dw (eps_ks)),
+ * eps_lin = eps_ks + Z (x + Re Sigma(eps_ks) - vxc), and the graphical root
+ * of eps_ks + x + Re Sigma(w) - vxc - w (Eq. 6) nearest eps_lin (1 mHa scan
+ * outwards to +-2 Ha, bisection to 1e-10 Ha).  SGW_ENOROOT if none. */
+sgw_status sgw_qp_solve(const double *sigma_t, int32_t n_tau, double dt,
+                        double gamma, double eps_ks, double x, double vxc,
+                        double *eqp_graphical, double *eqp_linear, double *z);
+
+/* Damped Fourier transform of Eq. (7) on the trapezoid rule:
+ *   Sigma(w_k) = dt sum_j w_j e^{-gamma^2 t_j^2/2} e^{i w_k t_j} Sigma(t_j),
+ * t_j = j dt, j = -n_tau..n_tau, w_j = 1/2 at the ends.  sigma_t: host
+ * [2 n_tau + 1][2]; omega: host [n_omega]; out: host [n_omega][2]. */
+sgw_status sgw_sigma_omega(const double *sigma_t, int32_t n_tau, double dt, double gamma,
+                           const double *omega, int32_t n_omega, double *out);
+
+/* Launch timer of the dominant kernel: the inverse xy-plane FFT pass that
+ * carries the Chebyshev-recurrence epilogue (Eq. 3 filter and the zeta
+ * propagator).  enable != 0: from now on every launch of that pass on the
+ * context's stream is bracketed by a pair of HIP events; enable = 0 stops
+ * it.  sgw_kernel_timer_read synchronises the stream and returns the summed
+ * event time (ms), the number of timed launches and the number of grid
+ * points x vectors they processed, then resets the counters. */
+sgw_status sgw_kernel_timer(sgw_ctx *ctx, int32_t enable);
+sgw_status sgw_kernel_timer_read(sgw_ctx *ctx, double *total_ms, int64_t *launches,
+                                 int64_t *points);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SGW_H */

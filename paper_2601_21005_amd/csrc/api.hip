@@ -1,0 +1,726 @@
+// C ABI of libsgw (include/sgw.h): context set-up, H|psi>, the Chebyshev
+// filter and propagator, the TDH response and the full Sigma_c(t) estimate.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "common.h"
+#include "kernels.h"
+#include "rng.h"
+
+using namespace sgw;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+template <typename F> sgw_status guarded(sgw_ctx *ctx, F &&f) {
+  try {
+    f();
+    return SGW_OK;
+  } catch (const Error &e) {
+    if (ctx) ctx->err = e.msg;
+    else g_create_error = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    if (ctx) ctx->err = "host allocation failed";
+    else g_create_error = "host allocation failed";
+    return SGW_ENOMEM;
+  } catch (const std::exception &e) {
+    if (ctx) ctx->err = e.what();
+    else g_create_error = e.what();
+    return SGW_EINVAL;
+  }
+}
+
+// upload host doubles as the working real type
+void upload_real(sgw_ctx *ctx, DevBuf &b, const double *src, size_t n) {
+  b.ensure(n * ctx->rsize());
+  if (ctx->dbl) {
+    SGW_HIP(hipMemcpy(b.p, src, n * 8, hipMemcpyHostToDevice));
+  } else {
+    std::vector<float> f(src, src + n);
+    SGW_HIP(hipMemcpy(b.p, f.data(), n * 4, hipMemcpyHostToDevice));
+  }
+}
+
+void upload_cplx(sgw_ctx *ctx, DevBuf &b, const double *re_im, size_t n) {
+  upload_real(ctx, b, re_im, 2 * n);
+}
+
+template <typename T> void upload(DevBuf &b, const T *src, size_t n) {
+  b.ensure(n * sizeof(T));
+  SGW_HIP(hipMemcpy(b.p, src, n * sizeof(T), hipMemcpyHostToDevice));
+}
+
+std::vector<double> fftfreq_k2(int n, double h) {
+  std::vector<double> k2(n);
+  const double L = n * h;
+  for (int i = 0; i < n; ++i) {
+    const int m = (i <= (n - 1) / 2) ? i : i - n;
+    const double k = 2.0 * M_PI * m / L;
+    k2[i] = k * k;
+  }
+  return k2;
+}
+
+void check_ptr(const void *p, const char *what) {
+  SGW_REQUIRE(p != nullptr, SGW_EINVAL, std::string(what) + " is NULL");
+  SGW_REQUIRE(((uintptr_t)p & 15) == 0, SGW_EINVAL, std::string(what) + " is not 16-byte aligned");
+}
+
+// ---------------------------------------------------------------- Chebyshev
+// out = sum_n coef_n T_n(H~) v0 over nvec vectors (ld = N) with the fused
+// recurrence; v0 and w1 are overwritten.  coef interleaved (re, im).
+// Returns the vector holding v_last (for the norm check).
+void *cheb_series(sgw_ctx *ctx, void *v0, void *w1, void *acc, void *tmp, int64_t nvec,
+                  const std::vector<double> &coef, double emin, double emax) {
+  const int nc = (int)coef.size() / 2;
+  const int64_t N = ctx->N;
+  const double c = 0.5 * (emax + emin), R = 0.5 * (emax - emin), invR = 1.0 / R;
+  launch_scale_copy(ctx, v0, N, acc, N, nvec, coef[0], coef[1]);
+  void *cur = v0, *old = w1;
+  void *kbC = nullptr;
+  if (ctx->has_kb) kbC = ctx->buf("kbC", ctx->csize() * ctx->kb.nproj * nvec).p;
+  for (int k = 0; k + 1 < nc; ++k) {
+    const bool first = (k == 0);
+    const double s2 = first ? 1.0 : 2.0;
+    const double br = coef[2 * (k + 1)], bi = coef[2 * (k + 1) + 1];
+    if (ctx->has_kb) kb_gather_e(ctx, cur, nvec, N, kbC);
+    EpiArgs e;
+    e.x = cur;
+    e.vold = old;
+    e.acc = acc;
+    e.vloc = ctx->d_vloc.p;
+    e.c = c;
+    e.invR = invR;
+    e.coef_re = br;
+    e.coef_im = bi;
+    e.first = first ? 1 : 0;
+    e.scale2 = s2;
+    fft3d_apply(ctx, cur, tmp, nullptr, nvec, N, MUL_KIN, 0.0, PLANE_INV_CHEB, e);
+    if (ctx->has_kb)
+      kb_scatter(ctx, kbC, nvec, old, N, s2 * invR, 0.0, acc, br * s2 * invR, bi * s2 * invR);
+    std::swap(cur, old);
+  }
+  return cur;
+}
+
+// ||v_last|| <= ||v_0|| when spec(H~) lies in [-1, 1]; growth means the
+// interval did not enclose the spectrum.
+void check_growth(sgw_ctx *ctx, const std::vector<double> &n0, const void *vlast, int64_t nvec) {
+  DevBuf &d = ctx->buf("norm_out", sizeof(double) * nvec);
+  launch_norm2(ctx, vlast, ctx->N, nvec, d.as<double>());
+  std::vector<double> n1(nvec);
+  SGW_HIP(hipMemcpyAsync(n1.data(), d.p, sizeof(double) * nvec, hipMemcpyDeviceToHost,
+                         ctx->stream));
+  SGW_HIP(hipStreamSynchronize(ctx->stream));
+  for (int64_t v = 0; v < nvec; ++v)
+    if (!std::isfinite(n1[v]) || n1[v] > 1.02 * n0[v] + 1e-300)
+      throw Error{SGW_EDIVERGED, "Chebyshev recurrence grew: [emin, emax] does not enclose spec(H)"};
+}
+
+std::vector<double> norms_of(sgw_ctx *ctx, const void *x, int64_t nvec) {
+  DevBuf &d = ctx->buf("norm_in", sizeof(double) * nvec);
+  launch_norm2(ctx, x, ctx->N, nvec, d.as<double>());
+  std::vector<double> n(nvec);
+  SGW_HIP(hipMemcpyAsync(n.data(), d.p, sizeof(double) * nvec, hipMemcpyDeviceToHost,
+                         ctx->stream));
+  SGW_HIP(hipStreamSynchronize(ctx->stream));
+  return n;
+}
+
+void check_interval(double emin, double emax) {
+  SGW_REQUIRE(std::isfinite(emin) && std::isfinite(emax) && emax > emin, SGW_EINVAL,
+              "spectral interval must satisfy emin < emax");
+}
+
+// ---------------------------------------------------------------- TDH
+const void *kb_exp_matrix(sgw_ctx *ctx, double tau) {
+  // cache the device matrix per tau
+  char key[64];
+  std::snprintf(key, sizeof key, "kbexp_%.17g", tau);
+  auto it = ctx->scratch.find(key);
+  if (it != ctx->scratch.end()) return it->second->p;
+  std::vector<double> K;
+  kb_exponential_matrix(ctx, tau, K);
+  DevBuf &b = ctx->buf(key, ctx->csize() * K.size() / 2);
+  upload_cplx(ctx, b, K.data(), K.size() / 2);
+  return b.p;
+}
+
+void kb_exp_apply(sgw_ctx *ctx, void *psi, int64_t nvec, double tau) {
+  const void *K = kb_exp_matrix(ctx, tau);
+  void *C = ctx->buf("kbC", ctx->csize() * ctx->kb.nproj * nvec).p;
+  void *C2 = ctx->buf("kbC2", ctx->csize() * ctx->kb.nproj * nvec).p;
+  kb_gather(ctx, psi, nvec, ctx->N, C);
+  kb_mix_dense(ctx, K, C, C2, nvec);
+  kb_scatter(ctx, C2, nvec, psi, ctx->N, 1.0, 0.0, nullptr, 0.0, 0.0);
+}
+
+// Poisson of S complex fields rho (ld = N): POISSON -> v, u; SPLIT -> r0, r1
+void poisson(sgw_ctx *ctx, const void *rho, int64_t S, PlaneMode mode, void *r0, void *r1,
+             const void *vh0) {
+  void *tmp = ctx->buf("poisson_tmp", ctx->csize() * ctx->N * S).p;
+  EpiArgs e;
+  e.vloc = ctx->d_vloc.p;
+  e.r0 = r0;
+  e.r1 = r1;
+  e.vh0 = vh0;
+  fft3d_apply(ctx, rho, tmp, nullptr, S, ctx->N, MUL_COUL, 0.0, mode, e);
+}
+
+// One or more Strang substeps; the local half steps of consecutive substeps
+// are merged (a = tau).  `open`: the state is synchronised at entry (first
+// half step a = tau/2); `close`: apply the closing half step.
+void tdh_substeps(sgw_ctx *ctx, sgw_tdh_state *st, int nsub, double tau, bool open,
+                  bool close) {
+  const int64_t S = st->nsample, nv = 2 * (int64_t)st->nsample * st->neta;
+  void *tmp = ctx->buf("tdh_tmp", ctx->csize() * ctx->N * nv).p;
+  void *rho = ctx->buf("tdh_rho", ctx->csize() * ctx->N * S).p;
+  for (int k = 0; k < nsub; ++k) {
+    launch_tdh_local(ctx, st->psi, st->v, st->u, st->nsample, st->neta,
+                     (k == 0 && open) ? 0.5 * tau : tau);
+    if (ctx->has_kb) kb_exp_apply(ctx, st->psi, nv, 0.5 * tau);
+    fft3d_apply(ctx, st->psi, tmp, st->psi, nv, ctx->N, MUL_PROP, tau, PLANE_INV_STORE,
+                EpiArgs());
+    if (ctx->has_kb) kb_exp_apply(ctx, st->psi, nv, 0.5 * tau);
+    launch_tdh_density(ctx, st->psi, rho, st->nsample, st->neta, st->weight);
+    poisson(ctx, rho, S, PLANE_INV_POISSON, st->v, st->u, st->vh0);
+  }
+  if (close) launch_tdh_local(ctx, st->psi, st->v, st->u, st->nsample, st->neta, 0.5 * tau);
+}
+
+void tdh_start(sgw_ctx *ctx, sgw_tdh_state *st, const void *dv) {
+  const int64_t S = st->nsample;
+  void *rho = ctx->buf("tdh_rho", ctx->csize() * ctx->N * S).p;
+  launch_tdh_tangent(ctx, st->psi, dv, st->nsample, st->neta);
+  launch_bcast_real(ctx, ctx->d_vloc.p, st->v, st->nsample);
+  launch_tdh_density(ctx, st->psi, rho, st->nsample, st->neta, st->weight);
+  poisson(ctx, rho, S, PLANE_INV_SPLIT, st->vh0, st->u, nullptr);
+}
+
+void check_state(sgw_ctx *ctx, const sgw_tdh_state *st) {
+  SGW_REQUIRE(st != nullptr, SGW_EINVAL, "state is NULL");
+  SGW_REQUIRE(st->nsample > 0 && st->neta > 0, SGW_EINVAL, "state: nsample, neta must be > 0");
+  SGW_REQUIRE(std::isfinite(st->weight), SGW_EINVAL, "state: weight not finite");
+  check_ptr(st->psi, "state.psi");
+  check_ptr(st->v, "state.v");
+  check_ptr(st->u, "state.u");
+  check_ptr(st->vh0, "state.vh0");
+  (void)ctx;
+}
+
+int next_pow2(int n) {
+  int p = 1;
+  while (p < n) p *= 2;
+  return p;
+}
+
+}  // namespace
+
+// =================================================================== ABI
+extern "C" {
+
+const char *sgw_last_error(const sgw_ctx *ctx) {
+  return ctx ? ctx->err.c_str() : g_create_error.c_str();
+}
+
+sgw_status sgw_create(const sgw_grid *grid, const double *v_loc, const sgw_projectors *proj,
+                      sgw_precision prec, void *hip_stream, int64_t max_nvec, sgw_ctx **out) {
+  if (out) *out = nullptr;
+  sgw_ctx *ctx = nullptr;
+  sgw_status st = guarded(nullptr, [&] {
+    SGW_REQUIRE(out != nullptr, SGW_EINVAL, "out is NULL");
+    SGW_REQUIRE(grid != nullptr && v_loc != nullptr, SGW_EINVAL, "grid or v_loc is NULL");
+    SGW_REQUIRE(prec == SGW_C128 || prec == SGW_C64 || prec == SGW_C64_BF16KB, SGW_EINVAL,
+                "unknown precision");
+    SGW_REQUIRE(grid->nx > 0 && grid->ny > 0 && grid->nz > 0, SGW_EINVAL, "grid sizes must be > 0");
+    SGW_REQUIRE(grid->h > 0 && std::isfinite(grid->h), SGW_EINVAL, "grid spacing must be > 0");
+    SGW_REQUIRE(std::isfinite(grid->ecut), SGW_EINVAL, "ecut not finite");
+    SGW_REQUIRE(max_nvec > 0, SGW_EINVAL, "max_nvec must be > 0");
+    const bool dbl = prec == SGW_C128;
+    SGW_REQUIRE(fft_size_supported(grid->nx, dbl) && fft_size_supported(grid->ny, dbl) &&
+                    fft_size_supported(grid->nz, dbl),
+                SGW_EUNSUPPORTED, "grid size not built into this library");
+    SGW_REQUIRE(grid->nx == grid->ny, SGW_EUNSUPPORTED, "nx must equal ny");
+    std::unique_ptr<sgw_ctx> c(new sgw_ctx());
+    c->nx = grid->nx; c->ny = grid->ny; c->nz = grid->nz;
+    c->N = (int64_t)c->nx * c->ny * c->nz;
+    c->h = grid->h;
+    c->dV = grid->h * grid->h * grid->h;
+    c->ecut = grid->ecut > 0 ? grid->ecut : 0.0;
+    c->prec = prec;
+    c->dbl = dbl;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    c->max_nvec = max_nvec;
+    c->vloc.assign(v_loc, v_loc + c->N);
+    for (double v : c->vloc) SGW_REQUIRE(std::isfinite(v), SGW_EINVAL, "v_loc has a non-finite value");
+    c->vmin = *std::min_element(c->vloc.begin(), c->vloc.end());
+    c->vmax = *std::max_element(c->vloc.begin(), c->vloc.end());
+    // k tables and twiddles (FP64 on the host, stored in the working type)
+    std::vector<double> k2, tw;
+    double kmax2 = 0;
+    const int ns[3] = {c->nx, c->ny, c->nz};
+    for (int ax = 0; ax < 3; ++ax) {
+      auto a = fftfreq_k2(ns[ax], c->h);
+      kmax2 += *std::max_element(a.begin(), a.end());
+      k2.insert(k2.end(), a.begin(), a.end());
+      for (int j = 0; j < ns[ax]; ++j) {
+        tw.push_back(std::cos(2.0 * M_PI * j / ns[ax]));
+        tw.push_back(-std::sin(2.0 * M_PI * j / ns[ax]));
+      }
+    }
+    c->tmax = 0.5 * kmax2;
+    if (c->ecut > 0) c->tmax = std::min(c->tmax, c->ecut);
+    upload_real(c.get(), c->d_k2, k2.data(), k2.size());
+    upload_real(c.get(), c->d_tw, tw.data(), tw.size());
+    upload_real(c.get(), c->d_vloc, c->vloc.data(), c->N);
+    if (proj) {
+      build_kb(c.get(), proj);
+      c->has_kb = true;
+      upload(c->d_kb_tile_base, c->kb.tile_base.data(), c->kb.tile_base.size());
+      upload(c->d_kb_tile_off, c->kb.tile_off.data(), c->kb.tile_off.size());
+      upload(c->d_kb_entry_proj, c->kb.entry_proj.data(), c->kb.entry_proj.size());
+      upload(c->d_kb_proj_off, c->kb.proj_off.data(), c->kb.proj_off.size());
+      upload(c->d_kb_proj_entries, c->kb.proj_entries.data(), c->kb.proj_entries.size());
+      upload(c->d_kb_ekb, c->kb.ekb.data(), c->kb.ekb.size());
+      upload_real(c.get(), c->d_kb_beta, c->kb.beta.data(), c->kb.beta.size());
+    }
+    ctx = c.release();
+  });
+  if (st == SGW_OK) *out = ctx;
+  return st;
+}
+
+void sgw_destroy(sgw_ctx *ctx) { delete ctx; }
+
+sgw_status sgw_bounds(sgw_ctx *ctx, double pad, double *emin, double *emax) {
+  if (!ctx) return SGW_EINVAL;
+  return guarded(ctx, [&] {
+    SGW_REQUIRE(emin && emax, SGW_EINVAL, "emin/emax NULL");
+    SGW_REQUIRE(pad >= 0 && std::isfinite(pad), SGW_EINVAL, "pad must be >= 0");
+    double lo = 0, hi = 0;
+    if (ctx->has_kb) {
+      const double s = kb_lambda_bound(ctx);
+      const double emn = *std::min_element(ctx->kb.ekb.begin(), ctx->kb.ekb.end());
+      const double emx = *std::max_element(ctx->kb.ekb.begin(), ctx->kb.ekb.end());
+      lo = std::min(0.0, emn) * s;
+      hi = std::max(0.0, emx) * s;
+    }
+    const double a = ctx->vmin + lo, b = ctx->tmax + ctx->vmax + hi;
+    const double w = b - a;
+    *emin = a - pad * w;
+    *emax = b + pad * w;
+  });
+}
+
+sgw_status sgw_apply_H(sgw_ctx *ctx, const void *psi, void *hpsi, int64_t nvec, int64_t ld) {
+  if (!ctx) return SGW_EINVAL;
+  return guarded(ctx, [&] {
+    SGW_REQUIRE(nvec >= 0 && ld >= ctx->N, SGW_EINVAL, "nvec < 0 or ld < N");
+    if (nvec == 0) return;
+    check_ptr(psi, "psi");
+    check_ptr(hpsi, "hpsi");
+    SGW_REQUIRE(psi != hpsi, SGW_EINVAL, "psi and hpsi must not overlap");
+    const int64_t chunk = ctx->max_nvec;
+    void *tmp = ctx->buf("tmp", ctx->csize() * ctx->N * chunk).p;
+    for (int64_t v0 = 0; v0 < nvec; v0 += chunk) {
+      const int64_t nv = std::min(chunk, nvec - v0);
+      const char *x = static_cast<const char *>(psi) + v0 * ld * ctx->csize();
+      char *y = static_cast<char *>(hpsi) + v0 * ld * ctx->csize();
+      void *kbC = nullptr;
+      if (ctx->has_kb) {
+        kbC = ctx->buf("kbC", ctx->csize() * ctx->kb.nproj * nv).p;
+        kb_gather_e(ctx, x, nv, ld, kbC);
+      }
+      EpiArgs e;
+      e.x = x;
+      e.vloc = ctx->d_vloc.p;
+      fft3d_apply(ctx, x, tmp, y, nv, ld, MUL_KIN, 0.0, PLANE_INV_HPSI, e);
+      if (ctx->has_kb) kb_scatter(ctx, kbC, nv, y, ld, 1.0, 0.0, nullptr, 0.0, 0.0);
+    }
+  });
+}
+
+sgw_status sgw_fermi_coefficients(double mu, double beta, double emin, double emax,
+                                  int32_t ncoef, double *coef) {
+  try {
+    if (!coef || ncoef <= 0 || !std::isfinite(mu) || !std::isfinite(beta) ||
+        !(emax > emin) || !std::isfinite(emin) || !std::isfinite(emax))
+      return SGW_EINVAL;
+    fermi_coefficients(mu, beta, emin, emax, ncoef, coef);
+    return SGW_OK;
+  } catch (...) {
+    return SGW_ENOMEM;
+  }
+}
+
+sgw_status sgw_propagator_coefficients(double emin, double emax, double tau, double tol,
+                                       int32_t max_terms, double *coef, int32_t *nterms) {
+  try {
+    if (!coef || !nterms || !(emax > emin) || !std::isfinite(tau) || !(tol > 0))
+      return SGW_EINVAL;
+    std::vector<double> b;
+    const int nt = propagator_coefficients(emin, emax, tau, tol, b);
+    *nterms = nt;
+    if (nt > max_terms) return SGW_EINVAL;
+    std::memcpy(coef, b.data(), sizeof(double) * b.size());
+    return SGW_OK;
+  } catch (const Error &e) {
+    return e.code;
+  } catch (...) {
+    return SGW_ENOMEM;
+  }
+}
+
+sgw_status sgw_fermi_filter(sgw_ctx *ctx, void *v, int64_t nvec, int64_t ld, const double *coef,
+                            int32_t ncoef, double emin, double emax) {
+  if (!ctx) return SGW_EINVAL;
+  return guarded(ctx, [&] {
+    SGW_REQUIRE(nvec >= 0 && ld >= ctx->N, SGW_EINVAL, "nvec < 0 or ld < N");
+    SGW_REQUIRE(coef != nullptr && ncoef > 0, SGW_EINVAL, "no coefficients");
+    check_interval(emin, emax);
+    if (nvec == 0) return;
+    check_ptr(v, "v");
+    std::vector<double> c(2 * ncoef, 0.0);
+    for (int i = 0; i < ncoef; ++i) {
+      SGW_REQUIRE(std::isfinite(coef[i]), SGW_EINVAL, "coefficient not finite");
+      c[2 * i] = coef[i];
+    }
+    const int64_t chunk = ctx->max_nvec;
+    const size_t bytes = ctx->csize() * ctx->N * chunk;
+    void *A = ctx->buf("cheb_a", bytes).p, *B = ctx->buf("cheb_b", bytes).p;
+    void *acc = ctx->buf("cheb_acc", bytes).p, *tmp = ctx->buf("tmp", bytes).p;
+    for (int64_t v0 = 0; v0 < nvec; v0 += chunk) {
+      const int64_t nv = std::min(chunk, nvec - v0);
+      char *x = static_cast<char *>(v) + v0 * ld * ctx->csize();
+      launch_copy(ctx, x, ld, A, ctx->N, nv);
+      const auto n0 = norms_of(ctx, A, nv);
+      void *last = cheb_series(ctx, A, B, acc, tmp, nv, c, emin, emax);
+      check_growth(ctx, n0, last, nv);
+      launch_copy(ctx, acc, ctx->N, x, ld, nv);
+    }
+  });
+}
+
+sgw_status sgw_cheb_propagate(sgw_ctx *ctx, void *psi, int64_t nvec, int64_t ld, double dt,
+                              int32_t nsteps, double emin, double emax, double tol) {
+  if (!ctx) return SGW_EINVAL;
+  return guarded(ctx, [&] {
+    SGW_REQUIRE(nvec >= 0 && ld >= ctx->N && nsteps >= 0, SGW_EINVAL, "bad sizes");
+    SGW_REQUIRE(std::isfinite(dt) && tol > 0, SGW_EINVAL, "bad dt or tol");
+    check_interval(emin, emax);
+    if (nvec == 0 || nsteps == 0) return;
+    check_ptr(psi, "psi");
+    std::vector<double> b;
+    propagator_coefficients(emin, emax, dt, tol, b);
+    const int64_t chunk = ctx->max_nvec;
+    const size_t bytes = ctx->csize() * ctx->N * chunk;
+    void *bufs[3] = {ctx->buf("cheb_a", bytes).p, ctx->buf("cheb_b", bytes).p,
+                     ctx->buf("cheb_acc", bytes).p};
+    void *tmp = ctx->buf("tmp", bytes).p;
+    for (int64_t v0 = 0; v0 < nvec; v0 += chunk) {
+      const int64_t nv = std::min(chunk, nvec - v0);
+      char *x = static_cast<char *>(psi) + v0 * ld * ctx->csize();
+      void *cur = bufs[0], *w = bufs[1], *acc = bufs[2];
+      launch_copy(ctx, x, ld, cur, ctx->N, nv);
+      const auto n0 = norms_of(ctx, cur, nv);
+      for (int s = 0; s < nsteps; ++s) {
+        cheb_series(ctx, cur, w, acc, tmp, nv, b, emin, emax);
+        std::swap(cur, acc);
+      }
+      // unitary: the norm is conserved
+      check_growth(ctx, n0, cur, nv);
+      launch_copy(ctx, cur, ctx->N, x, ld, nv);
+    }
+  });
+}
+
+sgw_status sgw_tdh_init(sgw_ctx *ctx, sgw_tdh_state *st, const void *dv) {
+  if (!ctx) return SGW_EINVAL;
+  return guarded(ctx, [&] {
+    check_state(ctx, st);
+    check_ptr(dv, "dv");
+    tdh_start(ctx, st, dv);
+  });
+}
+
+sgw_status sgw_tdh_step(sgw_ctx *ctx, sgw_tdh_state *st, int32_t nsub, double dt_sub) {
+  if (!ctx) return SGW_EINVAL;
+  return guarded(ctx, [&] {
+    check_state(ctx, st);
+    SGW_REQUIRE(nsub >= 0 && std::isfinite(dt_sub), SGW_EINVAL, "bad nsub or dt_sub");
+    if (nsub == 0) return;
+    tdh_substeps(ctx, st, nsub, dt_sub, true, true);
+  });
+}
+
+sgw_status sgw_qp_solve(const double *sigma_t, int32_t n_tau, double dt, double gamma,
+                        double eps_ks, double x, double vxc, double *eqp_graphical,
+                        double *eqp_linear, double *z) {
+  if (!sigma_t || n_tau < 1 || !(dt > 0) || !(gamma >= 0) || !eqp_graphical || !eqp_linear || !z)
+    return SGW_EINVAL;
+  for (int i = 0; i < 2 * (2 * n_tau + 1); ++i)
+    if (!std::isfinite(sigma_t[i])) return SGW_EINVAL;
+  const int r = qp_solve(sigma_t, n_tau, dt, gamma, eps_ks, x, vxc, eqp_graphical, eqp_linear, z);
+  return r == 0 ? SGW_OK : SGW_ENOROOT;
+}
+
+sgw_status sgw_sigma_omega(const double *sigma_t, int32_t n_tau, double dt, double gamma,
+                           const double *omega, int32_t n_omega, double *out) {
+  if (!sigma_t || !omega || !out || n_tau < 1 || n_omega < 0 || !(dt > 0) || !(gamma >= 0))
+    return SGW_EINVAL;
+  for (int k = 0; k < n_omega; ++k) {
+    double re = 0, im = 0;
+    for (int j = -n_tau; j <= n_tau; ++j) {
+      const double t = dt * j;
+      const double wt = dt * ((j == -n_tau || j == n_tau) ? 0.5 : 1.0) *
+                        std::exp(-0.5 * gamma * gamma * t * t);
+      const double sr = sigma_t[2 * (j + n_tau)], si = sigma_t[2 * (j + n_tau) + 1];
+      const double cs = std::cos(omega[k] * t), sn = std::sin(omega[k] * t);
+      re += wt * (cs * sr - sn * si);
+      im += wt * (cs * si + sn * sr);
+    }
+    out[2 * k] = re;
+    out[2 * k + 1] = im;
+  }
+  return SGW_OK;
+}
+
+sgw_status sgw_kernel_timer(sgw_ctx *ctx, int32_t enable) {
+  if (!ctx) return SGW_EINVAL;
+  return guarded(ctx, [&] { ctx->ktimer = enable != 0; });
+}
+
+sgw_status sgw_kernel_timer_read(sgw_ctx *ctx, double *total_ms, int64_t *launches,
+                                 int64_t *points) {
+  if (!ctx) return SGW_EINVAL;
+  return guarded(ctx, [&] {
+    SGW_REQUIRE(total_ms && launches && points, SGW_EINVAL, "NULL output");
+    SGW_HIP(hipStreamSynchronize(ctx->stream));
+    double ms = 0;
+    for (int64_t i = 0; i < ctx->kt_used; ++i) {
+      float t = 0;
+      SGW_HIP(hipEventElapsedTime(&t, ctx->kt_events[2 * i], ctx->kt_events[2 * i + 1]));
+      ms += t;
+    }
+    *total_ms = ms;
+    *launches = ctx->kt_used;
+    *points = ctx->kt_points;
+    ctx->kt_used = 0;
+    ctx->kt_points = 0;
+  });
+}
+
+// ------------------------------------------------------------------ Sigma
+sgw_status sgw_sigma_estimate(sgw_ctx *ctx, const sgw_sigma_params *P, const double *phi,
+                              double *sigma_t, double *x_out, double *phase_ms) {
+  if (!ctx) return SGW_EINVAL;
+  return guarded(ctx, [&] {
+    SGW_REQUIRE(P && phi && sigma_t && x_out, SGW_EINVAL, "NULL argument");
+    const int64_t N = ctx->N;
+    SGW_REQUIRE(P->n_zeta > 0 && P->first_sample >= 0, SGW_EINVAL, "n_zeta must be > 0");
+    SGW_REQUIRE(P->n_eta > 0 && P->n_eta % 2 == 0, SGW_EINVAL, "n_eta must be even and > 0");
+    SGW_REQUIRE(P->first_sample + P->n_zeta < (1 << 20) && P->n_eta < (1 << 20), SGW_EINVAL,
+                "sample or eta index beyond the RNG stream range");
+    SGW_REQUIRE(P->n_tau >= 1 && P->m_sub >= 1 && P->dt > 0 && std::isfinite(P->dt), SGW_EINVAL,
+                "bad time grid");
+    SGW_REQUIRE(P->ncoef >= 1 && std::isfinite(P->mu) && std::isfinite(P->beta), SGW_EINVAL,
+                "bad filter");
+    SGW_REQUIRE(P->mode == 0 || P->mode == 1, SGW_EINVAL, "mode must be 0 or 1");
+    SGW_REQUIRE(P->prop_tol > 0, SGW_EINVAL, "prop_tol must be > 0");
+    check_interval(P->emin, P->emax);
+    const bool xi = P->mode == 0;
+    if (xi) {
+      SGW_REQUIRE(N % 32 == 0, SGW_EINVAL, "xi mode needs N_g divisible by 32");
+      SGW_REQUIRE(P->n_xi >= 1 && P->f_g > 0 && P->f_g <= 1, SGW_EINVAL, "bad n_xi or f_g");
+    }
+    for (int64_t r = 0; r < N; ++r) SGW_REQUIRE(std::isfinite(phi[r]), SGW_EINVAL, "phi not finite");
+    const int nt1 = P->n_tau + 1;
+    const int nft = P->n_ft > 0 ? P->n_ft : next_pow2(4 * nt1);
+    SGW_REQUIRE(nft >= 2 * nt1, SGW_EINVAL, "n_ft < 2 (n_tau + 1)");
+    const int Sb = P->batch > 0 ? std::min(P->batch, P->n_zeta) : P->n_zeta;
+    const int neta = P->n_eta;
+    const size_t cs = ctx->csize(), rs = ctx->rsize();
+
+    // coefficients
+    std::vector<double> a(P->ncoef), fc(2 * P->ncoef, 0.0), pb;
+    fermi_coefficients(P->mu, P->beta, P->emin, P->emax, P->ncoef, a.data());
+    for (int i = 0; i < P->ncoef; ++i) fc[2 * i] = a[i];
+    propagator_coefficients(P->emin, P->emax, P->dt, P->prop_tol, pb);
+    // time-ordering twiddles
+    std::vector<double> tw(2 * nft);
+    for (int j = 0; j < nft; ++j) {
+      tw[2 * j] = std::cos(2.0 * M_PI * j / nft);
+      tw[2 * j + 1] = -std::sin(2.0 * M_PI * j / nft);
+    }
+    DevBuf &d_tw = ctx->buf("to_tw", cs * nft);
+    upload_cplx(ctx, d_tw, tw.data(), nft);
+    DevBuf &d_phi = ctx->buf("phi", rs * N);
+    upload_real(ctx, d_phi, phi, N);
+    const int nseg = xi ? std::max(1, (int)std::floor(P->f_g * N / 32.0 + 0.5)) : 0;
+    SGW_REQUIRE(!xi || nseg <= N / 32, SGW_EINVAL, "f_g too large");
+    const double amp = xi ? 1.0 / std::sqrt(P->n_xi * (32.0 * nseg / N) * ctx->dV) : 0.0;
+    const int64_t n_inner = xi ? P->n_xi : N;
+
+    hipEvent_t ev[7];
+    for (auto &e : ev) SGW_HIP(hipEventCreate(&e));
+    double ph[6] = {0, 0, 0, 0, 0, 0};
+    struct EvGuard { hipEvent_t *e; ~EvGuard() { for (int i = 0; i < 7; ++i) (void)hipEventDestroy(e[i]); } } eg{ev};
+
+    for (int b0 = 0; b0 < P->n_zeta; b0 += Sb) {
+      const int S = std::min(Sb, P->n_zeta - b0);
+      const int64_t nr = (int64_t)S * (1 + neta), nc = (nr + 1) / 2;
+      SGW_HIP(hipEventRecord(ev[0], ctx->stream));
+      // 1. white noise keys (zeta-bar, then eta-bar_l, per sample)
+      std::vector<uint64_t> keys(nr), ksup(S), ksign(S);
+      for (int s = 0; s < S; ++s) {
+        const uint64_t g = (uint64_t)(P->first_sample + b0 + s);
+        keys[(int64_t)s * (1 + neta)] = rng_key(P->seed, rng_stream(RNG_ZETA, g, 0));
+        for (int l = 0; l < neta; ++l)
+          keys[(int64_t)s * (1 + neta) + 1 + l] = rng_key(P->seed, rng_stream(RNG_ETA, g, l));
+        ksup[s] = rng_key(P->seed, rng_stream(RNG_XI_SUPPORT, g, 0));
+        ksign[s] = rng_key(P->seed, rng_stream(RNG_XI_SIGN, g, 0));
+      }
+      DevBuf &d_keys = ctx->buf("keys", sizeof(uint64_t) * nr);
+      SGW_HIP(hipMemcpyAsync(d_keys.p, keys.data(), sizeof(uint64_t) * nr, hipMemcpyHostToDevice, ctx->stream));
+      DevBuf &d_ksup = ctx->buf("ksup", sizeof(uint64_t) * S);
+      DevBuf &d_ksign = ctx->buf("ksign", sizeof(uint64_t) * S);
+      SGW_HIP(hipMemcpyAsync(d_ksup.p, ksup.data(), sizeof(uint64_t) * S, hipMemcpyHostToDevice, ctx->stream));
+      SGW_HIP(hipMemcpyAsync(d_ksign.p, ksign.data(), sizeof(uint64_t) * S, hipMemcpyHostToDevice, ctx->stream));
+      const size_t fbytes = cs * N * nc;
+      void *F0 = ctx->buf("f_a", fbytes).p, *F1 = ctx->buf("f_b", fbytes).p;
+      void *FA = ctx->buf("f_acc", fbytes).p, *FT = ctx->buf("f_tmp", fbytes).p;
+      launch_fill_noise(ctx, d_keys.as<uint64_t>(), nr, F0);
+      SGW_HIP(hipEventRecord(ev[1], ctx->stream));
+      // 2. filter, Eq. (3)
+      void *last = cheb_series(ctx, F0, F1, FA, FT, nc, fc, P->emin, P->emax);
+      SGW_HIP(hipEventRecord(ev[2], ctx->stream));
+      {
+        // ||T_n(H~) x|| <= ||x|| = sqrt(2 N) per complex vector of +-1/sqrt(dV)
+        DevBuf &d = ctx->buf("norm_out", sizeof(double) * nc);
+        launch_norm2(ctx, last, N, nc, d.as<double>());
+        std::vector<double> n1(nc);
+        SGW_HIP(hipMemcpyAsync(n1.data(), d.p, sizeof(double) * nc, hipMemcpyDeviceToHost, ctx->stream));
+        SGW_HIP(hipStreamSynchronize(ctx->stream));
+        const double bound = 1.02 * 2.0 * (double)N / ctx->dV;
+        for (double v : n1)
+          SGW_REQUIRE(std::isfinite(v) && v <= bound, SGW_EDIVERGED,
+                      "filter recurrence grew: [emin, emax] does not enclose spec(H)");
+      }
+      // 3. unpack, kick potential, exchange, TDH start
+      void *psi = ctx->buf("tdh_psi", cs * N * 2 * neta * S).p;
+      void *zeta = ctx->buf("zeta", cs * N * 2 * S).p;
+      void *kick = ctx->buf("kick", cs * N * S).p;
+      UnpackArgs ua;
+      ua.filt = FA; ua.keys = d_keys.as<uint64_t>(); ua.phi = d_phi.p; ua.psi = psi;
+      ua.zeta = zeta; ua.kick = kick; ua.xsrc = F0; ua.S = S; ua.neta = neta;
+      launch_unpack(ctx, ua);
+      void *dv = ctx->buf("dv", rs * N * S).p;
+      poisson(ctx, kick, S, PLANE_INV_SPLIT, dv, nullptr, nullptr);
+      const int64_t nxf = (int64_t)S * neta / 2;
+      fft3d_apply(ctx, F0, FT, F1, nxf, N, MUL_COUL, 0.0, PLANE_INV_STORE, EpiArgs());
+      DevBuf &d_xd = ctx->buf("xdots", sizeof(double) * nxf);
+      launch_redot(ctx, F0, F1, N, nxf, d_xd.as<double>());
+      std::vector<double> xd(nxf);
+      SGW_HIP(hipMemcpyAsync(xd.data(), d_xd.p, sizeof(double) * nxf, hipMemcpyDeviceToHost, ctx->stream));
+      sgw_tdh_state st;
+      st.nsample = S; st.neta = neta; st.weight = 2.0 / neta; st.psi = psi;
+      st.v = ctx->buf("tdh_v", rs * N * S).p;
+      st.u = ctx->buf("tdh_u", rs * N * S).p;
+      st.vh0 = ctx->buf("tdh_vh0", rs * N * S).p;
+      tdh_start(ctx, &st, dv);
+      int *blocks = nullptr;
+      void *cR = nullptr;
+      if (xi) {
+        blocks = ctx->buf("xi_blocks", sizeof(int) * (size_t)S * P->n_xi * nseg).as<int>();
+        launch_xi_supports(ctx, d_ksup.as<uint64_t>(), S, P->n_xi, nseg, blocks);
+        cR = ctx->buf("xi_cR", rs * (size_t)S * nt1 * P->n_xi).p;
+        launch_xi_real(ctx, st.u, blocks, d_ksign.as<uint64_t>(), S, P->n_xi, nseg, amp * ctx->dV,
+                       cR, (int64_t)nt1 * P->n_xi, 0);
+      } else {
+        cR = ctx->buf("U", rs * (size_t)S * nt1 * N).p;
+        SGW_HIP(hipMemcpy2DAsync(cR, rs * N * nt1, st.u, rs * N, rs * N, S, hipMemcpyDeviceToDevice, ctx->stream));
+      }
+      SGW_HIP(hipEventRecord(ev[3], ctx->stream));
+      // 4. TDH response, stored at the output steps
+      const double tau = P->dt / P->m_sub;
+      for (int j = 1; j < nt1; ++j) {
+        tdh_substeps(ctx, &st, P->m_sub, tau, j == 1, false);
+        if (xi)
+          launch_xi_real(ctx, st.u, blocks, d_ksign.as<uint64_t>(), S, P->n_xi, nseg,
+                         amp * ctx->dV, cR, (int64_t)nt1 * P->n_xi, (int64_t)j * P->n_xi);
+        else
+          SGW_HIP(hipMemcpy2DAsync(static_cast<char *>(cR) + rs * N * j, rs * N * nt1, st.u, rs * N,
+                                   rs * N, S, hipMemcpyDeviceToDevice, ctx->stream));
+      }
+      SGW_HIP(hipEventRecord(ev[4], ctx->stream));
+      // 5. time ordering
+      void *cto = ctx->buf("cTO", cs * (size_t)S * nt1 * n_inner).p;
+      SGW_REQUIRE(launch_time_order(ctx, cR, cto, (int64_t)S * n_inner, n_inner, nt1, nft, d_tw.p),
+                  SGW_EUNSUPPORTED, "time-ordering length not built");
+      SGW_HIP(hipEventRecord(ev[5], ctx->stream));
+      // 6. zeta propagation and contraction, Eq. (4), Eq. (5)
+      double *d_sig = ctx->buf("sig", sizeof(double) * 4 * S * nt1).as<double>();
+      void *zb = ctx->buf("z_b", cs * N * 2 * S).p, *zacc = ctx->buf("z_acc", cs * N * 2 * S).p;
+      void *zt = ctx->buf("z_tmp", cs * N * 2 * S).p;
+      void *dp = nullptr, *dtl = nullptr;
+      double *partial = nullptr;
+      if (xi) {
+        dp = ctx->buf("xi_dp", cs * (size_t)S * P->n_xi).p;
+        dtl = ctx->buf("xi_dt", cs * (size_t)S * P->n_xi).p;
+      } else {
+        partial = ctx->buf("c_partial", sizeof(double) * 4 * S * ((N + 4095) / 4096)).as<double>();
+      }
+      void *zc = zeta;
+      for (int j = 0; j < nt1; ++j) {
+        if (j > 0) {
+          cheb_series(ctx, zc, zb, zacc, zt, 2 * S, pb, P->emin, P->emax);
+          std::swap(zc, zacc);
+        }
+        if (xi) {
+          launch_xi_zeta(ctx, zc, d_phi.p, blocks, d_ksign.as<uint64_t>(), S, P->n_xi, nseg,
+                         amp * ctx->dV, dp, dtl);
+          launch_contract_xi(ctx, cto, dp, dtl, S, P->n_xi, nt1, j, d_sig);
+        } else {
+          launch_contract_exact(ctx, cto, zc, d_phi.p, S, nt1, j, partial, d_sig);
+        }
+      }
+      SGW_HIP(hipEventRecord(ev[6], ctx->stream));
+      std::vector<double> sig(4 * (size_t)S * nt1);
+      SGW_HIP(hipMemcpyAsync(sig.data(), d_sig, sizeof(double) * sig.size(), hipMemcpyDeviceToHost, ctx->stream));
+      SGW_HIP(hipStreamSynchronize(ctx->stream));
+      // assemble
+      for (int s = 0; s < S; ++s) {
+        double *o = sigma_t + (size_t)(b0 + s) * 2 * (2 * P->n_tau + 1);
+        const double *g = sig.data() + (size_t)s * nt1 * 4;
+        for (int j = 1; j < nt1; ++j) {
+          o[2 * (P->n_tau + j)] = g[4 * j];
+          o[2 * (P->n_tau + j) + 1] = g[4 * j + 1];
+          o[2 * (P->n_tau - j)] = g[4 * j + 2];
+          o[2 * (P->n_tau - j) + 1] = g[4 * j + 3];
+        }
+        o[2 * P->n_tau] = 0.5 * (g[0] + g[2]);
+        o[2 * P->n_tau + 1] = 0.5 * (g[1] + g[3]);
+        double xs = 0;
+        for (int k = 0; k < neta / 2; ++k) xs += xd[(size_t)s * (neta / 2) + k];
+        x_out[b0 + s] = -ctx->dV * xs / neta;
+      }
+      float t;
+      SGW_HIP(hipEventElapsedTime(&t, ev[1], ev[2])); ph[0] += t;
+      SGW_HIP(hipEventElapsedTime(&t, ev[3], ev[4])); ph[1] += t;
+      SGW_HIP(hipEventElapsedTime(&t, ev[4], ev[5])); ph[2] += t;
+      SGW_HIP(hipEventElapsedTime(&t, ev[5], ev[6])); ph[3] += t;
+      float t1, t2;
+      SGW_HIP(hipEventElapsedTime(&t1, ev[0], ev[1]));
+      SGW_HIP(hipEventElapsedTime(&t2, ev[2], ev[3]));
+      ph[4] += t1 + t2;
+      SGW_HIP(hipEventElapsedTime(&t, ev[0], ev[6])); ph[5] += t;
+    }
+    if (phase_ms)
+      for (int i = 0; i < 6; ++i) phase_ms[i] = ph[i];
+  });
+}
+
+}  // extern "C"

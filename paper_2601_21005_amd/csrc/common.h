@@ -1,0 +1,206 @@
+// Internal declarations of libsgw: device types, the context, launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/sgw.h"
+
+namespace sgw {
+
+// ---------------------------------------------------------------- types
+template <typename R> struct CT;
+template <> struct CT<float> { using C = float2; };
+template <> struct CT<double> { using C = double2; };
+template <typename R> using cplx = typename CT<R>::C;
+
+template <typename C> __host__ __device__ inline C cmake(double re, double im) {
+  C c; c.x = re; c.y = im; return c;
+}
+template <typename C> __device__ __forceinline__ C cadd(C a, C b) { C c; c.x = a.x + b.x; c.y = a.y + b.y; return c; }
+template <typename C> __device__ __forceinline__ C csub(C a, C b) { C c; c.x = a.x - b.x; c.y = a.y - b.y; return c; }
+template <typename C> __device__ __forceinline__ C cmul(C a, C b) {
+  C c; c.x = a.x * b.x - a.y * b.y; c.y = a.x * b.y + a.y * b.x; return c;
+}
+template <typename C> __device__ __forceinline__ C cconj(C a) { a.y = -a.y; return a; }
+template <typename C, typename R> __device__ __forceinline__ C cscale(C a, R s) { a.x *= s; a.y *= s; return a; }
+
+// ---------------------------------------------------------------- errors
+struct Error {
+  sgw_status code;
+  std::string msg;
+};
+
+#define SGW_HIP(call)                                                            \
+  do {                                                                           \
+    hipError_t e_ = (call);                                                      \
+    if (e_ != hipSuccess)                                                        \
+      throw ::sgw::Error{SGW_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+#define SGW_REQUIRE(cond, code, text)                                            \
+  do {                                                                           \
+    if (!(cond)) throw ::sgw::Error{code, text};                                 \
+  } while (0)
+
+// ---------------------------------------------------------------- device memory
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf &) = delete;
+  DevBuf &operator=(const DevBuf &) = delete;
+  ~DevBuf() { if (p) (void)hipFree(p); }
+  void ensure(size_t b) {
+    if (b <= bytes) return;
+    if (p) { SGW_HIP(hipFree(p)); p = nullptr; bytes = 0; }
+    hipError_t e = hipMalloc(&p, b);
+    if (e != hipSuccess) throw Error{SGW_ENOMEM, "hipMalloc of " + std::to_string(b) + " bytes failed"};
+    bytes = b;
+  }
+  template <typename T> T *as() const { return static_cast<T *>(p); }
+};
+
+// ---------------------------------------------------------------- KB tiles
+// Projector data laid out per 8x8x8 grid tile: for each touched tile the list
+// of projectors whose support meets it and their values on the tile's 512
+// points (zero outside the support).
+constexpr int KB_TILE = 8;
+constexpr int KB_TP = KB_TILE * KB_TILE * KB_TILE;  // 512 points per tile
+
+struct KBHost {
+  int nproj = 0;
+  std::vector<double> ekb;
+  std::vector<int> tile_base;       // [ntile] flat index of the tile's first point
+  std::vector<int> tile_off;        // [ntile + 1] CSR into entries
+  std::vector<int> entry_proj;      // [nentry] projector of each (tile, projector) entry
+  std::vector<double> beta;         // [nentry][512]
+  std::vector<int> proj_off;        // [nproj + 1] CSR of entries per projector
+  std::vector<int> proj_entries;    // [nentry] entry ids grouped by projector
+  std::vector<double> gram;         // [nproj][nproj] S = <beta_p|beta_q>
+};
+
+// ---------------------------------------------------------------- context
+struct Plan;  // FFT dispatch (sizes, kernels)
+
+}  // namespace sgw
+
+struct sgw_ctx {
+  int nx = 0, ny = 0, nz = 0;
+  int64_t N = 0;
+  double h = 0, dV = 0, ecut = 0;
+  sgw_precision prec = SGW_C64;
+  bool dbl = false;                  // complex double arithmetic
+  hipStream_t stream = nullptr;
+  int64_t max_nvec = 0;
+  std::vector<double> vloc;          // host copy, FP64
+  double vmin = 0, vmax = 0, tmax = 0;
+  sgw::KBHost kb;
+  bool has_kb = false;
+  std::string err;
+
+  // device data
+  sgw::DevBuf d_vloc;                // [N] real (R)
+  sgw::DevBuf d_k2;                  // kx2 [nx], ky2 [ny], kz2 [nz] (R)
+  sgw::DevBuf d_tw;                  // twiddles nx, ny, nz (C), forward sign
+  sgw::DevBuf d_kb_tile_base, d_kb_tile_off, d_kb_entry_proj, d_kb_beta,
+      d_kb_proj_off, d_kb_proj_entries, d_kb_ekb;
+  int kb_ntile = 0, kb_nentry = 0;
+
+  // launch timer of the inverse plane pass with the Chebyshev epilogue
+  bool ktimer = false;
+  std::vector<hipEvent_t> kt_events;   // pairs (start, stop)
+  int64_t kt_used = 0, kt_points = 0;
+  hipEvent_t timer_event(int which) {
+    const size_t i = 2 * (size_t)kt_used + which;
+    while (kt_events.size() <= i) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) throw sgw::Error{SGW_EHIP, "hipEventCreate failed"};
+      kt_events.push_back(e);
+    }
+    return kt_events[i];
+  }
+  ~sgw_ctx() {
+    for (auto e : kt_events) (void)hipEventDestroy(e);
+  }
+
+  // scratch (grown on demand)
+  std::map<std::string, std::unique_ptr<sgw::DevBuf>> scratch;
+  sgw::DevBuf &buf(const std::string &name, size_t bytes) {
+    auto &p = scratch[name];
+    if (!p) p.reset(new sgw::DevBuf());
+    p->ensure(bytes);
+    return *p;
+  }
+  size_t csize() const { return dbl ? 16 : 8; }
+  size_t rsize() const { return dbl ? 8 : 4; }
+};
+
+namespace sgw {
+
+// ---------------------------------------------------------------- launchers
+// FFT pass kinds
+enum PlaneMode : int {
+  PLANE_FWD = 0,          // dst = FFT_xy(src)
+  PLANE_INV_STORE = 1,    // dst = IFFT_xy(src) (no 1/N: folded into the z pass)
+  PLANE_INV_HPSI = 2,     // dst = IFFT_xy(tmp) + V x
+  PLANE_INV_CHEB = 3,     // Chebyshev update (see EpiArgs)
+  PLANE_INV_POISSON = 4,  // v = Vloc + Re - vh0, u = Im  (per sample fields)
+  PLANE_INV_SPLIT = 5,    // r0 = Re, r1 = Im  (real fields)
+};
+
+enum MulMode : int { MUL_NONE = 0, MUL_KIN = 1, MUL_PROP = 2, MUL_COUL = 3 };
+
+struct EpiArgs {
+  const void *x = nullptr;    // complex: current vector (HPSI, CHEB)
+  void *vold = nullptr;       // complex: v_{n-1} in, v_{n+1} out (CHEB)
+  void *acc = nullptr;        // complex: accumulated series (CHEB)
+  const void *vloc = nullptr; // real [N]
+  const void *vh0 = nullptr;  // real per field (POISSON)
+  void *r0 = nullptr;         // real outputs per field
+  void *r1 = nullptr;
+  double c = 0, invR = 0;     // spectral map
+  double coef_re = 0, coef_im = 0;  // coefficient of the new term
+  int first = 0;              // CHEB: v_1 = H~ v_0 (no v_{n-1} term)
+  double scale2 = 2.0;        // CHEB: factor of H~ v_n (2, or 1 when first)
+};
+
+// Full forward+multiply+inverse 3D transform of nvec vectors of `src` (ld),
+// result written through the inverse pass mode into dst / epilogue outputs.
+void fft3d_apply(sgw_ctx *ctx, const void *src, void *tmp, void *dst, int64_t nvec,
+                 int64_t ld, MulMode mul, double tau, PlaneMode inv_mode,
+                 const EpiArgs &epi);
+
+// KB (kb.hip)
+// C[p][v] = <beta_p|psi_v>  (kb_gather_e: times E_p)
+void kb_gather(sgw_ctx *ctx, const void *psi, int64_t nvec, int64_t ld, void *coef_out);
+void kb_gather_e(sgw_ctx *ctx, const void *psi, int64_t nvec, int64_t ld, void *coef_out);
+// C' = K C  (K complex [nproj][nproj] in the working precision)
+void kb_mix_dense(sgw_ctx *ctx, const void *K, const void *coef_in, void *coef_out,
+                  int64_t nvec);
+// dst[v] += s1 * B C[v];  if dst2: dst2[v] += s2 * B C[v]  (s1, s2 complex)
+void kb_scatter(sgw_ctx *ctx, const void *coef, int64_t nvec, void *dst, int64_t ld,
+                double s1re, double s1im, void *dst2, double s2re, double s2im);
+
+// host utilities (host.cpp)
+void build_kb(sgw_ctx *ctx, const sgw_projectors *p);
+// K (complex, [nproj][nproj] interleaved) with exp(-i tau V_NL) = I + dV B K B^T
+void kb_exponential_matrix(const sgw_ctx *ctx, double tau, std::vector<double> &K);
+void fermi_coefficients(double mu, double beta, double emin, double emax, int n,
+                        double *a);
+// b_n (interleaved re, im) of exp(-i H tau); returns the number of terms
+int propagator_coefficients(double emin, double emax, double tau, double tol,
+                            std::vector<double> &re_im);
+// Bessel J_0..J_nmax(x) by Miller's backward recurrence
+void bessel_j(double x, int nmax, std::vector<double> &J);
+double kb_lambda_bound(const sgw_ctx *ctx);
+int qp_solve(const double *sig, int n_tau, double dt, double gamma, double eks, double x,
+             double vxc, double *eg, double *el, double *z);
+
+}  // namespace sgw

@@ -1,0 +1,596 @@
+// Elementwise, reduction, TDH and sROI kernels.
+#include "fft_lds.h"
+#include "kernels.h"
+#include "rng.h"
+
+namespace sgw {
+
+constexpr int NT = 256;
+
+static inline dim3 grid1(int64_t n, int64_t y = 1) {
+  return dim3((unsigned)((n + NT - 1) / NT), (unsigned)y);
+}
+
+// ============================================================ vectors
+template <typename R>
+__global__ void k_scale_copy(const cplx<R> *x, int64_t ldx, cplx<R> *acc, int64_t lda,
+                             int64_t N, R cre, R cim) {
+  const int64_t r = (int64_t)blockIdx.x * NT + threadIdx.x;
+  const int64_t v = blockIdx.y;
+  if (r >= N) return;
+  const cplx<R> a = x[v * ldx + r];
+  cplx<R> o;
+  o.x = cre * a.x - cim * a.y;
+  o.y = cre * a.y + cim * a.x;
+  acc[v * lda + r] = o;
+}
+
+void launch_scale_copy(sgw_ctx *ctx, const void *x, int64_t ldx, void *acc, int64_t lda,
+                       int64_t nvec, double cre, double cim) {
+  for (int64_t v0 = 0; v0 < nvec; v0 += 65535) {
+    const int64_t nv = std::min<int64_t>(65535, nvec - v0);
+    if (ctx->dbl)
+      hipLaunchKernelGGL(k_scale_copy<double>, grid1(ctx->N, nv), dim3(NT), 0, ctx->stream,
+                         static_cast<const double2 *>(x) + v0 * ldx, ldx,
+                         static_cast<double2 *>(acc) + v0 * lda, lda, ctx->N, cre, cim);
+    else
+      hipLaunchKernelGGL(k_scale_copy<float>, grid1(ctx->N, nv), dim3(NT), 0, ctx->stream,
+                         static_cast<const float2 *>(x) + v0 * ldx, ldx,
+                         static_cast<float2 *>(acc) + v0 * lda, lda, ctx->N, (float)cre,
+                         (float)cim);
+  }
+  SGW_HIP(hipGetLastError());
+}
+
+void launch_copy(sgw_ctx *ctx, const void *src, int64_t lds, void *dst, int64_t ldd,
+                 int64_t nvec) {
+  SGW_HIP(hipMemcpy2DAsync(dst, ldd * ctx->csize(), src, lds * ctx->csize(),
+                           ctx->N * ctx->csize(), nvec, hipMemcpyDeviceToDevice,
+                           ctx->stream));
+}
+
+// ============================================================ reductions
+// Two-stage deterministic sums in FP64: stage 1 writes one partial per
+// (item, block of RCHUNK points) from a fixed-order LDS tree, stage 2 adds
+// the partials of each item in order.
+constexpr int RCHUNK = NT * 16;
+
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if (t < s) sh[t] += sh[t + s];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+enum RedOp { RED_NORM2 = 0, RED_REDOT = 1 };
+
+template <typename R, int OP>
+__global__ void k_reduce1(const cplx<R> *a, const cplx<R> *b, int64_t ld, int64_t N,
+                          double *partial, int nblk) {
+  __shared__ double sh[NT];
+  const int64_t item = blockIdx.y;
+  const int64_t r0 = (int64_t)blockIdx.x * RCHUNK;
+  const int64_t r1 = std::min<int64_t>(N, r0 + RCHUNK);
+  double acc = 0;
+  for (int64_t r = r0 + threadIdx.x; r < r1; r += NT) {
+    const cplx<R> x = a[item * ld + r];
+    if (OP == RED_NORM2) {
+      acc += (double)x.x * x.x + (double)x.y * x.y;
+    } else {
+      const cplx<R> y = b[item * ld + r];
+      acc += (double)x.x * y.x + (double)x.y * y.y;
+    }
+  }
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[item * nblk + blockIdx.x] = s;
+}
+
+__global__ void k_reduce2(const double *partial, int nblk, int64_t nitems, double *out) {
+  const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (i >= nitems) return;
+  double s = 0;
+  for (int k = 0; k < nblk; ++k) s += partial[i * nblk + k];
+  out[i] = s;
+}
+
+template <int OP>
+static void reduce(sgw_ctx *ctx, const void *a, const void *b, int64_t ld, int64_t n,
+                   double *d_out) {
+  const int nblk = (int)((ctx->N + RCHUNK - 1) / RCHUNK);
+  double *partial = ctx->buf("red_partial", sizeof(double) * nblk * std::max<int64_t>(n, 1)).as<double>();
+  for (int64_t v0 = 0; v0 < n; v0 += 65535) {
+    const int64_t nv = std::min<int64_t>(65535, n - v0);
+    if (ctx->dbl)
+      hipLaunchKernelGGL((k_reduce1<double, OP>), dim3(nblk, nv), dim3(NT), 0, ctx->stream,
+                         static_cast<const double2 *>(a) + v0 * ld,
+                         b ? static_cast<const double2 *>(b) + v0 * ld : nullptr, ld, ctx->N,
+                         partial + v0 * nblk, nblk);
+    else
+      hipLaunchKernelGGL((k_reduce1<float, OP>), dim3(nblk, nv), dim3(NT), 0, ctx->stream,
+                         static_cast<const float2 *>(a) + v0 * ld,
+                         b ? static_cast<const float2 *>(b) + v0 * ld : nullptr, ld, ctx->N,
+                         partial + v0 * nblk, nblk);
+  }
+  hipLaunchKernelGGL(k_reduce2, grid1(n), dim3(NT), 0, ctx->stream, partial, nblk, n, d_out);
+  SGW_HIP(hipGetLastError());
+}
+
+void launch_norm2(sgw_ctx *ctx, const void *x, int64_t ld, int64_t nvec, double *d_out) {
+  reduce<RED_NORM2>(ctx, x, nullptr, ld, nvec, d_out);
+}
+void launch_redot(sgw_ctx *ctx, const void *a, const void *b, int64_t ld, int64_t nf,
+                  double *d_out) {
+  reduce<RED_REDOT>(ctx, a, b, ld, nf, d_out);
+}
+
+// ============================================================ white noise
+template <typename R>
+__global__ void k_fill_noise(const uint64_t *keys, int64_t nr, int64_t N, R amp,
+                             cplx<R> *out) {
+  const int64_t r = (int64_t)blockIdx.x * NT + threadIdx.x;
+  const int64_t k = blockIdx.y;
+  if (r >= N) return;
+  cplx<R> o;
+  o.x = noise_bit(keys[2 * k], r) ? -amp : amp;
+  o.y = (2 * k + 1 < nr) ? (noise_bit(keys[2 * k + 1], r) ? -amp : amp) : (R)0;
+  out[k * N + r] = o;
+}
+
+void launch_fill_noise(sgw_ctx *ctx, const uint64_t *d_keys, int64_t nr, void *out) {
+  const int64_t nc = (nr + 1) / 2;
+  const double amp = 1.0 / std::sqrt(ctx->dV);
+  for (int64_t k0 = 0; k0 < nc; k0 += 65535) {
+    const int64_t nk = std::min<int64_t>(65535, nc - k0);
+    if (ctx->dbl)
+      hipLaunchKernelGGL(k_fill_noise<double>, grid1(ctx->N, nk), dim3(NT), 0, ctx->stream,
+                         d_keys + 2 * k0, nr - 2 * k0, ctx->N, amp,
+                         static_cast<double2 *>(out) + k0 * ctx->N);
+    else
+      hipLaunchKernelGGL(k_fill_noise<float>, grid1(ctx->N, nk), dim3(NT), 0, ctx->stream,
+                         d_keys + 2 * k0, nr - 2 * k0, ctx->N, (float)amp,
+                         static_cast<float2 *>(out) + k0 * ctx->N);
+  }
+  SGW_HIP(hipGetLastError());
+}
+
+template <typename R>
+__device__ __forceinline__ R real_component(const cplx<R> *filt, int64_t q, int64_t N,
+                                            int64_t r) {
+  const cplx<R> c = filt[(q >> 1) * N + r];
+  return (q & 1) ? c.y : c.x;
+}
+
+template <typename R>
+__global__ void k_unpack(UnpackArgs a, int64_t N, R amp) {
+  using C = cplx<R>;
+  const int64_t r = (int64_t)blockIdx.x * NT + threadIdx.x;
+  const int64_t s = blockIdx.y;
+  if (r >= N) return;
+  const C *filt = static_cast<const C *>(a.filt);
+  const int64_t q0 = s * (1 + a.neta);
+  const R zocc = real_component<R>(filt, q0, N, r);
+  const R zb = noise_bit(a.keys[q0], r) ? -amp : amp;
+  const R ph = static_cast<const R *>(a.phi)[r];
+  C *zeta = static_cast<C *>(a.zeta) + s * 2 * N;
+  zeta[r] = cmake<C>(zb - zocc, 0);
+  zeta[N + r] = cmake<C>(zocc, 0);
+  static_cast<C *>(a.kick)[s * N + r] = cmake<C>(ph * zb, 0);
+  C *psi = static_cast<C *>(a.psi) + s * 2 * a.neta * N;
+  C *xs = static_cast<C *>(a.xsrc) + s * (a.neta / 2) * N;
+  for (int l = 0; l < a.neta; l += 2) {
+    const R e0 = real_component<R>(filt, q0 + 1 + l, N, r);
+    const R e1 = real_component<R>(filt, q0 + 2 + l, N, r);
+    psi[(int64_t)l * N + r] = cmake<C>(e0, 0);
+    psi[(int64_t)(l + 1) * N + r] = cmake<C>(e1, 0);
+    xs[(int64_t)(l / 2) * N + r] = cmake<C>(ph * e0, ph * e1);
+  }
+}
+
+void launch_unpack(sgw_ctx *ctx, const UnpackArgs &a) {
+  const double amp = 1.0 / std::sqrt(ctx->dV);
+  if (ctx->dbl)
+    hipLaunchKernelGGL(k_unpack<double>, grid1(ctx->N, a.S), dim3(NT), 0, ctx->stream, a,
+                       ctx->N, amp);
+  else
+    hipLaunchKernelGGL(k_unpack<float>, grid1(ctx->N, a.S), dim3(NT), 0, ctx->stream, a,
+                       ctx->N, (float)amp);
+  SGW_HIP(hipGetLastError());
+}
+
+// ============================================================ TDH
+// psi[s][1][l] = -i dv_s psi[s][0][l]
+template <typename R>
+__global__ void k_tdh_tangent(cplx<R> *psi, const R *dv, int neta, int64_t N) {
+  const int64_t r = (int64_t)blockIdx.x * NT + threadIdx.x;
+  const int64_t s = blockIdx.y;
+  if (r >= N) return;
+  const R d = dv[s * N + r];
+  cplx<R> *p0 = psi + s * 2 * neta * N;
+  cplx<R> *p1 = p0 + (int64_t)neta * N;
+  for (int l = 0; l < neta; ++l) {
+    const cplx<R> e = p0[(int64_t)l * N + r];
+    p1[(int64_t)l * N + r] = cmake<cplx<R>>(d * e.y, -d * e.x);
+  }
+}
+
+// Local step of length a:  eta <- e^{-i V a} eta,
+// delta-eta <- e^{-i V a} (delta-eta - i a u eta)
+template <typename R>
+__global__ void k_tdh_local(cplx<R> *psi, const R *v, const R *u, int neta, int64_t N, R a) {
+  const int64_t r = (int64_t)blockIdx.x * NT + threadIdx.x;
+  const int64_t s = blockIdx.y;
+  if (r >= N) return;
+  R sn, cs;
+  const R ph = v[s * N + r] * a;
+  if constexpr (sizeof(R) == 4) sincosf(ph, &sn, &cs);
+  else sincos(ph, &sn, &cs);
+  const R au = a * u[s * N + r];
+  cplx<R> *p0 = psi + s * 2 * neta * N;
+  cplx<R> *p1 = p0 + (int64_t)neta * N;
+  for (int l = 0; l < neta; ++l) {
+    const cplx<R> e = p0[(int64_t)l * N + r];
+    cplx<R> d = p1[(int64_t)l * N + r];
+    d.x += au * e.y;      // - i a u eta
+    d.y -= au * e.x;
+    // multiply by (cs - i sn)
+    p0[(int64_t)l * N + r] = cmake<cplx<R>>(cs * e.x + sn * e.y, cs * e.y - sn * e.x);
+    p1[(int64_t)l * N + r] = cmake<cplx<R>>(cs * d.x + sn * d.y, cs * d.y - sn * d.x);
+  }
+}
+
+// rho[s] = w sum_l |eta_l|^2 + i w sum_l 2 Re(conj(eta_l) delta-eta_l)
+template <typename R>
+__global__ void k_tdh_density(const cplx<R> *psi, cplx<R> *rho, int neta, int64_t N, R w) {
+  const int64_t r = (int64_t)blockIdx.x * NT + threadIdx.x;
+  const int64_t s = blockIdx.y;
+  if (r >= N) return;
+  const cplx<R> *p0 = psi + s * 2 * neta * N;
+  const cplx<R> *p1 = p0 + (int64_t)neta * N;
+  R n = 0, dn = 0;
+  for (int l = 0; l < neta; ++l) {
+    const cplx<R> e = p0[(int64_t)l * N + r];
+    const cplx<R> d = p1[(int64_t)l * N + r];
+    n += e.x * e.x + e.y * e.y;
+    dn += e.x * d.x + e.y * d.y;
+  }
+  rho[s * N + r] = cmake<cplx<R>>(w * n, (R)2 * w * dn);
+}
+
+template <typename R>
+__global__ void k_bcast_real(const R *src, R *dst, int64_t N) {
+  const int64_t r = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (r < N) dst[(int64_t)blockIdx.y * N + r] = src[r];
+}
+
+void launch_tdh_tangent(sgw_ctx *ctx, void *psi, const void *dv, int S, int neta) {
+  if (ctx->dbl)
+    hipLaunchKernelGGL(k_tdh_tangent<double>, grid1(ctx->N, S), dim3(NT), 0, ctx->stream,
+                       static_cast<double2 *>(psi), static_cast<const double *>(dv), neta, ctx->N);
+  else
+    hipLaunchKernelGGL(k_tdh_tangent<float>, grid1(ctx->N, S), dim3(NT), 0, ctx->stream,
+                       static_cast<float2 *>(psi), static_cast<const float *>(dv), neta, ctx->N);
+  SGW_HIP(hipGetLastError());
+}
+
+void launch_tdh_local(sgw_ctx *ctx, void *psi, const void *v, const void *u, int S, int neta,
+                      double a) {
+  if (ctx->dbl)
+    hipLaunchKernelGGL(k_tdh_local<double>, grid1(ctx->N, S), dim3(NT), 0, ctx->stream,
+                       static_cast<double2 *>(psi), static_cast<const double *>(v),
+                       static_cast<const double *>(u), neta, ctx->N, a);
+  else
+    hipLaunchKernelGGL(k_tdh_local<float>, grid1(ctx->N, S), dim3(NT), 0, ctx->stream,
+                       static_cast<float2 *>(psi), static_cast<const float *>(v),
+                       static_cast<const float *>(u), neta, ctx->N, (float)a);
+  SGW_HIP(hipGetLastError());
+}
+
+void launch_tdh_density(sgw_ctx *ctx, const void *psi, void *rho, int S, int neta, double w) {
+  if (ctx->dbl)
+    hipLaunchKernelGGL(k_tdh_density<double>, grid1(ctx->N, S), dim3(NT), 0, ctx->stream,
+                       static_cast<const double2 *>(psi), static_cast<double2 *>(rho), neta,
+                       ctx->N, w);
+  else
+    hipLaunchKernelGGL(k_tdh_density<float>, grid1(ctx->N, S), dim3(NT), 0, ctx->stream,
+                       static_cast<const float2 *>(psi), static_cast<float2 *>(rho), neta,
+                       ctx->N, (float)w);
+  SGW_HIP(hipGetLastError());
+}
+
+void launch_bcast_real(sgw_ctx *ctx, const void *src, void *dst, int S) {
+  if (ctx->dbl)
+    hipLaunchKernelGGL(k_bcast_real<double>, grid1(ctx->N, S), dim3(NT), 0, ctx->stream,
+                       static_cast<const double *>(src), static_cast<double *>(dst), ctx->N);
+  else
+    hipLaunchKernelGGL(k_bcast_real<float>, grid1(ctx->N, S), dim3(NT), 0, ctx->stream,
+                       static_cast<const float *>(src), static_cast<float *>(dst), ctx->N);
+  SGW_HIP(hipGetLastError());
+}
+
+// ============================================================ sROI
+// Segment blocks of xi_m: draw word mod nblocks, replace a used block by the
+// next free one (linear probing); one thread per (sample, m).
+__global__ void k_xi_supports(const uint64_t *keys, int S, int n_xi, int nseg,
+                              uint64_t nblocks, int *blocks) {
+  const int64_t t = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (t >= (int64_t)S * n_xi) return;
+  const int s = (int)(t / n_xi);
+  const int64_t m = t % n_xi;
+  int *row = blocks + t * nseg;
+  const uint64_t key = keys[s];
+  for (int g = 0; g < nseg; ++g) {
+    uint64_t b = sm64(key + (uint64_t)(m * nseg + g)) % nblocks;
+    for (;;) {
+      bool used = false;
+      for (int q = 0; q < g; ++q) used |= ((uint64_t)row[q] == b);
+      if (!used) break;
+      b = (b + 1) % nblocks;
+    }
+    row[g] = (int)b;
+  }
+}
+
+void launch_xi_supports(sgw_ctx *ctx, const uint64_t *d_keys, int S, int n_xi, int nseg,
+                        int *blocks) {
+  hipLaunchKernelGGL(k_xi_supports, grid1((int64_t)S * n_xi), dim3(NT), 0, ctx->stream,
+                     d_keys, S, n_xi, nseg, (uint64_t)(ctx->N / 32), blocks);
+  SGW_HIP(hipGetLastError());
+}
+
+template <typename T> __device__ __forceinline__ T wave_sum(T v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+
+// one wavefront per xi_m: half-waves take alternate segments of 32 points
+template <typename R>
+__global__ __launch_bounds__(NT) void k_xi_real(const R *u, const int *blocks,
+                                                const uint64_t *skeys, int n_xi, int nseg,
+                                                int64_t N, R amp_dv, R *out,
+                                                int64_t out_stride_s, int64_t out_off) {
+  const int lane = threadIdx.x & 63;
+  const int64_t m = (int64_t)blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
+  const int s = blockIdx.y;
+  if (m >= n_xi) return;
+  const int *row = blocks + ((int64_t)s * n_xi + m) * nseg;
+  const uint64_t key = skeys[s];
+  const R *us = u + (int64_t)s * N;
+  const int p = lane & 31;
+  R acc = 0;
+  for (int g = lane >> 5; g < nseg; g += 2) {
+    const uint64_t w = sm64(key + (uint64_t)(m * nseg + g));
+    const R val = us[(int64_t)row[g] * 32 + p];
+    acc += ((w >> p) & 1ull) ? -val : val;
+  }
+  acc = wave_sum(acc);
+  if (lane == 0) out[s * out_stride_s + out_off + m] = amp_dv * acc;
+}
+
+template <typename R>
+__global__ __launch_bounds__(NT) void k_xi_zeta(const cplx<R> *zeta, const R *phi,
+                                                const int *blocks, const uint64_t *skeys,
+                                                int n_xi, int nseg, int64_t N, R amp_dv,
+                                                cplx<R> *dp, cplx<R> *dt) {
+  const int lane = threadIdx.x & 63;
+  const int64_t m = (int64_t)blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
+  const int s = blockIdx.y;
+  if (m >= n_xi) return;
+  const int *row = blocks + ((int64_t)s * n_xi + m) * nseg;
+  const uint64_t key = skeys[s];
+  const cplx<R> *zp = zeta + (int64_t)s * 2 * N;
+  const cplx<R> *zt = zp + N;
+  const int p = lane & 31;
+  R a0 = 0, a1 = 0, b0 = 0, b1 = 0;
+  for (int g = lane >> 5; g < nseg; g += 2) {
+    const uint64_t w = sm64(key + (uint64_t)(m * nseg + g));
+    const int64_t r = (int64_t)row[g] * 32 + p;
+    R f = phi[r];
+    if ((w >> p) & 1ull) f = -f;
+    const cplx<R> x = zp[r], y = zt[r];
+    a0 += f * x.x; a1 += f * x.y;
+    b0 += f * y.x; b1 += f * y.y;
+  }
+  a0 = wave_sum(a0); a1 = wave_sum(a1); b0 = wave_sum(b0); b1 = wave_sum(b1);
+  if (lane == 0) {
+    dp[(int64_t)s * n_xi + m] = cmake<cplx<R>>(amp_dv * a0, amp_dv * a1);
+    dt[(int64_t)s * n_xi + m] = cmake<cplx<R>>(amp_dv * b0, amp_dv * b1);
+  }
+}
+
+void launch_xi_real(sgw_ctx *ctx, const void *u, const int *blocks, const uint64_t *d_sign_keys,
+                    int S, int n_xi, int nseg, double amp_dv, void *out, int64_t out_stride_s,
+                    int64_t out_off) {
+  const dim3 g((n_xi + 3) / 4, S);
+  if (ctx->dbl)
+    hipLaunchKernelGGL(k_xi_real<double>, g, dim3(NT), 0, ctx->stream,
+                       static_cast<const double *>(u), blocks, d_sign_keys, n_xi, nseg, ctx->N,
+                       amp_dv, static_cast<double *>(out), out_stride_s, out_off);
+  else
+    hipLaunchKernelGGL(k_xi_real<float>, g, dim3(NT), 0, ctx->stream,
+                       static_cast<const float *>(u), blocks, d_sign_keys, n_xi, nseg, ctx->N,
+                       (float)amp_dv, static_cast<float *>(out), out_stride_s, out_off);
+  SGW_HIP(hipGetLastError());
+}
+
+void launch_xi_zeta(sgw_ctx *ctx, const void *zeta, const void *phi, const int *blocks,
+                    const uint64_t *d_sign_keys, int S, int n_xi, int nseg, double amp_dv,
+                    void *dp, void *dt) {
+  const dim3 g((n_xi + 3) / 4, S);
+  if (ctx->dbl)
+    hipLaunchKernelGGL(k_xi_zeta<double>, g, dim3(NT), 0, ctx->stream,
+                       static_cast<const double2 *>(zeta), static_cast<const double *>(phi),
+                       blocks, d_sign_keys, n_xi, nseg, ctx->N, amp_dv,
+                       static_cast<double2 *>(dp), static_cast<double2 *>(dt));
+  else
+    hipLaunchKernelGGL(k_xi_zeta<float>, g, dim3(NT), 0, ctx->stream,
+                       static_cast<const float2 *>(zeta), static_cast<const float *>(phi),
+                       blocks, d_sign_keys, n_xi, nseg, ctx->N, (float)amp_dv,
+                       static_cast<float2 *>(dp), static_cast<float2 *>(dt));
+  SGW_HIP(hipGetLastError());
+}
+
+// ============================================================ time ordering
+// Row f_j (j < nt1, zero beyond), A = FFT(f).  For real f, conj(A_k) is the
+// e^{+i omega t} transform at omega_k = 2 pi k / (NFT dt); it is kept for
+// k <= NFT/2 (omega >= 0) and conjugated -- giving back A_k -- for k > NFT/2
+// (omega < 0).  g = FFT(G) / NFT, g_j kept for j < nt1.
+template <typename R, int NFT>
+__global__ __launch_bounds__(NT) void k_time_order(const R *in, cplx<R> *out, int64_t n_inner,
+                                                   int nt1, const cplx<R> *tw) {
+  using C = cplx<R>;
+  __shared__ C s[NFT];
+  const int64_t row = blockIdx.x;
+  const int64_t base = (row / n_inner) * nt1 * n_inner + row % n_inner;
+  for (int j = threadIdx.x; j < NFT; j += NT)
+    s[j] = cmake<C>(j < nt1 ? in[base + (int64_t)j * n_inner] : (R)0, 0);
+  __syncthreads();
+  lds_fft<C, NFT, 1, 0, 1, false, NT>(s, tw, threadIdx.x);
+  for (int k = threadIdx.x; k <= NFT / 2; k += NT) s[k] = cconj(s[k]);
+  __syncthreads();
+  lds_fft<C, NFT, 1, 0, 1, false, NT>(s, tw, threadIdx.x);
+  const R inv = (R)1 / (R)NFT;
+  for (int j = threadIdx.x; j < nt1; j += NT) out[base + (int64_t)j * n_inner] = cscale(s[j], inv);
+}
+
+template <typename R>
+static bool to_dispatch(sgw_ctx *ctx, const void *in, void *out, int64_t nrows, int64_t n_inner,
+                        int nt1, int nft, const void *tw) {
+  using C = cplx<R>;
+  const R *i = static_cast<const R *>(in);
+  C *o = static_cast<C *>(out);
+  const C *t = static_cast<const C *>(tw);
+  const dim3 g((unsigned)nrows);
+  switch (nft) {
+#define SGW_TO(N) case N: hipLaunchKernelGGL((k_time_order<R, N>), g, dim3(NT), 0, ctx->stream, i, o, n_inner, nt1, t); break;
+    SGW_TO(16) SGW_TO(32) SGW_TO(64) SGW_TO(128) SGW_TO(256) SGW_TO(512) SGW_TO(1024)
+    SGW_TO(2048)
+#undef SGW_TO
+    case 4096:
+      if constexpr (sizeof(R) == 4) {
+        hipLaunchKernelGGL((k_time_order<R, 4096>), g, dim3(NT), 0, ctx->stream, i, o, n_inner,
+                           nt1, t);
+        break;
+      }
+      return false;
+    default: return false;
+  }
+  return true;
+}
+
+bool launch_time_order(sgw_ctx *ctx, const void *in, void *out, int64_t nrows, int64_t n_inner,
+                       int nt1, int nft, const void *d_tw) {
+  const bool ok = ctx->dbl ? to_dispatch<double>(ctx, in, out, nrows, n_inner, nt1, nft, d_tw)
+                           : to_dispatch<float>(ctx, in, out, nrows, n_inner, nt1, nft, d_tw);
+  SGW_HIP(hipGetLastError());
+  return ok;
+}
+
+// ============================================================ contraction
+// sig[(s nt1 + j) 4 + {0,1,2,3}] = (Sigma^+, Sigma^-) of step j, FP64 sums
+template <typename R>
+__global__ __launch_bounds__(NT) void k_contract_xi(const cplx<R> *cto, const cplx<R> *dp,
+                                                    const cplx<R> *dt, int n_xi, int nt1, int j,
+                                                    double *sig) {
+  __shared__ double sh[NT];
+  const int s = blockIdx.x;
+  const cplx<R> *c = cto + ((int64_t)s * nt1 + j) * n_xi;
+  const cplx<R> *a = dp + (int64_t)s * n_xi;
+  const cplx<R> *b = dt + (int64_t)s * n_xi;
+  double pr = 0, pi = 0, mr = 0, mi = 0;
+  for (int m = threadIdx.x; m < n_xi; m += NT) {
+    const double cr = c[m].x, ci = c[m].y;
+    const double ar = a[m].x, ai = a[m].y;
+    const double br = -b[m].x, bi = b[m].y;   // -conj(d~)
+    pr += cr * ar - ci * ai;
+    pi += cr * ai + ci * ar;
+    mr += cr * br - ci * bi;
+    mi += cr * bi + ci * br;
+  }
+  pr = block_sum(pr, sh);
+  pi = block_sum(pi, sh);
+  mr = block_sum(mr, sh);
+  mi = block_sum(mi, sh);
+  if (threadIdx.x == 0) {
+    double *o = sig + ((int64_t)s * nt1 + j) * 4;
+    o[0] = pr; o[1] = pi; o[2] = mr; o[3] = mi;
+  }
+}
+
+void launch_contract_xi(sgw_ctx *ctx, const void *cto, const void *dp, const void *dt, int S,
+                        int n_xi, int nt1, int j, double *d_sig) {
+  if (ctx->dbl)
+    hipLaunchKernelGGL(k_contract_xi<double>, dim3(S), dim3(NT), 0, ctx->stream,
+                       static_cast<const double2 *>(cto), static_cast<const double2 *>(dp),
+                       static_cast<const double2 *>(dt), n_xi, nt1, j, d_sig);
+  else
+    hipLaunchKernelGGL(k_contract_xi<float>, dim3(S), dim3(NT), 0, ctx->stream,
+                       static_cast<const float2 *>(cto), static_cast<const float2 *>(dp),
+                       static_cast<const float2 *>(dt), n_xi, nt1, j, d_sig);
+  SGW_HIP(hipGetLastError());
+}
+
+template <typename R>
+__global__ __launch_bounds__(NT) void k_contract_exact1(const cplx<R> *uto, const cplx<R> *zeta,
+                                                        const R *phi, int nt1, int j, int64_t N,
+                                                        double *partial, int nblk) {
+  __shared__ double sh[NT];
+  const int s = blockIdx.y;
+  const int64_t r0 = (int64_t)blockIdx.x * RCHUNK;
+  const int64_t r1 = std::min<int64_t>(N, r0 + RCHUNK);
+  const cplx<R> *u = uto + ((int64_t)s * nt1 + j) * N;
+  const cplx<R> *zp = zeta + (int64_t)s * 2 * N;
+  const cplx<R> *zt = zp + N;
+  double pr = 0, pi = 0, mr = 0, mi = 0;
+  for (int64_t r = r0 + threadIdx.x; r < r1; r += NT) {
+    const double f = phi[r];
+    const double ur = u[r].x, ui = u[r].y;
+    const double ar = f * zp[r].x, ai = f * zp[r].y;
+    const double br = -f * zt[r].x, bi = f * zt[r].y;   // -phi conj(z~)
+    pr += ar * ur - ai * ui;
+    pi += ar * ui + ai * ur;
+    mr += br * ur - bi * ui;
+    mi += br * ui + bi * ur;
+  }
+  pr = block_sum(pr, sh);
+  pi = block_sum(pi, sh);
+  mr = block_sum(mr, sh);
+  mi = block_sum(mi, sh);
+  if (threadIdx.x == 0) {
+    double *o = partial + ((int64_t)s * nblk + blockIdx.x) * 4;
+    o[0] = pr; o[1] = pi; o[2] = mr; o[3] = mi;
+  }
+}
+
+__global__ void k_contract_exact2(const double *partial, int nblk, int S, int nt1, int j,
+                                  double dV, double *sig) {
+  const int t = blockIdx.x * NT + threadIdx.x;
+  if (t >= S * 4) return;
+  const int s = t / 4, c = t % 4;
+  double acc = 0;
+  for (int b = 0; b < nblk; ++b) acc += partial[((int64_t)s * nblk + b) * 4 + c];
+  sig[((int64_t)s * nt1 + j) * 4 + c] = dV * acc;
+}
+
+void launch_contract_exact(sgw_ctx *ctx, const void *uto, const void *zeta, const void *phi,
+                           int S, int nt1, int j, double *d_partial, double *d_sig) {
+  const int nblk = (int)((ctx->N + RCHUNK - 1) / RCHUNK);
+  if (ctx->dbl)
+    hipLaunchKernelGGL(k_contract_exact1<double>, dim3(nblk, S), dim3(NT), 0, ctx->stream,
+                       static_cast<const double2 *>(uto), static_cast<const double2 *>(zeta),
+                       static_cast<const double *>(phi), nt1, j, ctx->N, d_partial, nblk);
+  else
+    hipLaunchKernelGGL(k_contract_exact1<float>, dim3(nblk, S), dim3(NT), 0, ctx->stream,
+                       static_cast<const float2 *>(uto), static_cast<const float2 *>(zeta),
+                       static_cast<const float *>(phi), nt1, j, ctx->N, d_partial, nblk);
+  hipLaunchKernelGGL(k_contract_exact2, dim3((S * 4 + NT - 1) / NT), dim3(NT), 0, ctx->stream,
+                     d_partial, nblk, S, nt1, j, ctx->dV, d_sig);
+  SGW_HIP(hipGetLastError());
+}
+
+}  // namespace sgw

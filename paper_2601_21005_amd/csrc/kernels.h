@@ -1,0 +1,69 @@
+// Launchers of the elementwise, reduction, TDH and sROI kernels.
+#pragma once
+
+#include "common.h"
+
+namespace sgw {
+
+bool fft_size_supported(int n, bool dbl);
+
+// ---- vectors
+// acc[v] = (cre + i cim) x[v]
+void launch_scale_copy(sgw_ctx *ctx, const void *x, int64_t ldx, void *acc, int64_t lda,
+                       int64_t nvec, double cre, double cim);
+// dst[v] = src[v]
+void launch_copy(sgw_ctx *ctx, const void *src, int64_t lds, void *dst, int64_t ldd,
+                 int64_t nvec);
+// out[v] = sum_r |x_v(r)|^2 (FP64, deterministic two-stage)
+void launch_norm2(sgw_ctx *ctx, const void *x, int64_t ld, int64_t nvec, double *d_out);
+// out[f] = sum_r Re(conj(a_f(r)) b_f(r))  (FP64)
+void launch_redot(sgw_ctx *ctx, const void *a, const void *b, int64_t ld, int64_t nf,
+                  double *d_out);
+
+// ---- white noise and unpacking (sgw_sigma_estimate)
+// Filter input: complex vector k carries real noise vectors 2k and 2k+1 of the
+// flat list keys[0..nr-1] (+-1/sqrt(dV)).
+void launch_fill_noise(sgw_ctx *ctx, const uint64_t *d_keys, int64_t nr, void *out);
+struct UnpackArgs {
+  const void *filt;        // [nc][N] complex, filtered
+  const uint64_t *keys;    // [nr] noise keys (zeta-bar of sample s at s (1+neta))
+  const void *phi;         // [N] real
+  void *psi;               // [S][2][neta][N] complex: copy 0 <- eta
+  void *zeta;              // [S][2][N] complex: zeta^+ = zb - F zb, zeta~ = F zb
+  void *kick;              // [S][N] complex: phi zb
+  void *xsrc;              // [S][neta/2][N] complex: phi eta_2k + i phi eta_2k+1
+  int S = 0, neta = 0;
+};
+void launch_unpack(sgw_ctx *ctx, const UnpackArgs &a);
+
+// ---- TDH
+void launch_tdh_tangent(sgw_ctx *ctx, void *psi, const void *dv, int S, int neta);
+void launch_tdh_local(sgw_ctx *ctx, void *psi, const void *v, const void *u, int S,
+                      int neta, double a);
+void launch_tdh_density(sgw_ctx *ctx, const void *psi, void *rho, int S, int neta,
+                        double w);
+void launch_bcast_real(sgw_ctx *ctx, const void *src, void *dst, int S);
+
+// ---- sROI
+void launch_xi_supports(sgw_ctx *ctx, const uint64_t *d_keys, int S, int n_xi, int nseg,
+                        int *blocks);
+// cR[(s (n_t) + j) n_xi + m] = amp dV <xi_m|u_s>
+void launch_xi_real(sgw_ctx *ctx, const void *u, const int *blocks, const uint64_t *d_sign_keys,
+                    int S, int n_xi, int nseg, double amp_dv, void *out, int64_t out_stride_s,
+                    int64_t out_off);
+// dp[s][m] = amp dV <xi_m|phi zeta_s0>, dt[s][m] = amp dV <xi_m|phi zeta_s1>
+void launch_xi_zeta(sgw_ctx *ctx, const void *zeta, const void *phi, const int *blocks,
+                    const uint64_t *d_sign_keys, int S, int n_xi, int nseg, double amp_dv,
+                    void *dp, void *dt);
+// time ordering of rows: in real, out complex, element (row, j) at
+// base(row) + j * stride with base(row) = (row / n_inner) * nt1 * n_inner + row % n_inner
+bool launch_time_order(sgw_ctx *ctx, const void *in, void *out, int64_t nrows,
+                       int64_t n_inner, int nt1, int nft, const void *d_tw);
+// sig_p[s][j] += sum_m c[s][j][m] dp[s][m];  sig_m[s][j] += sum_m c (-conj dt)
+void launch_contract_xi(sgw_ctx *ctx, const void *cto, const void *dp, const void *dt,
+                        int S, int n_xi, int nt1, int j, double *d_sig);
+// exact mode: sig[s][j] (+: dV sum phi z+ u ; -: -dV sum phi conj(z~) u)
+void launch_contract_exact(sgw_ctx *ctx, const void *uto, const void *zeta, const void *phi,
+                           int S, int nt1, int j, double *d_partial, double *d_sig);
+
+}  // namespace sgw

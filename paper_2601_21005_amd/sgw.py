@@ -1,0 +1,279 @@
+"""Thin Python binding of libsgw (include/sgw.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  Device arrays are torch tensors on the ROCm device (torch supplies
+memory and the stream); host arrays are numpy.  If the library is missing
+the import fails -- there is no CPU fallback.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsgw.so")
+
+SGW_OK, SGW_EINVAL, SGW_ENOMEM, SGW_EHIP, SGW_EDIVERGED, SGW_ENOROOT, SGW_EUNSUPPORTED = \
+    0, -1, -2, -3, -4, -5, -6
+SGW_C128, SGW_C64, SGW_C64_BF16KB = 0, 1, 2
+
+STATUS_NAMES = {0: "SGW_OK", -1: "SGW_EINVAL", -2: "SGW_ENOMEM", -3: "SGW_EHIP",
+                -4: "SGW_EDIVERGED", -5: "SGW_ENOROOT", -6: "SGW_EUNSUPPORTED"}
+
+# every entry point declared in include/sgw.h
+EXPORTS = ["sgw_create", "sgw_destroy", "sgw_last_error", "sgw_bounds", "sgw_apply_H",
+           "sgw_fermi_coefficients", "sgw_fermi_filter", "sgw_propagator_coefficients",
+           "sgw_cheb_propagate", "sgw_tdh_init", "sgw_tdh_step", "sgw_sigma_estimate",
+           "sgw_qp_solve", "sgw_sigma_omega", "sgw_kernel_timer", "sgw_kernel_timer_read"]
+
+
+class SgwGrid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("h", C.c_double), ("ecut", C.c_double)]
+
+
+class SgwProjectors(C.Structure):
+    _fields_ = [("natom", C.c_int32),
+                ("pos", C.POINTER(C.c_double)),
+                ("proj_begin", C.POINTER(C.c_int32)),
+                ("l", C.POINTER(C.c_int32)),
+                ("m", C.POINTER(C.c_int32)),
+                ("rc", C.POINTER(C.c_double)),
+                ("ekb", C.POINTER(C.c_double)),
+                ("rcut_over_rc", C.c_double)]
+
+
+class SgwTdhState(C.Structure):
+    _fields_ = [("nsample", C.c_int32), ("neta", C.c_int32), ("weight", C.c_double),
+                ("psi", C.c_void_p), ("v", C.c_void_p), ("u", C.c_void_p),
+                ("vh0", C.c_void_p)]
+
+
+class SgwSigmaParams(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("first_sample", C.c_int32), ("n_zeta", C.c_int32),
+                ("n_eta", C.c_int32), ("n_tau", C.c_int32), ("dt", C.c_double),
+                ("m_sub", C.c_int32), ("mu", C.c_double), ("beta", C.c_double),
+                ("ncoef", C.c_int32), ("emin", C.c_double), ("emax", C.c_double),
+                ("n_xi", C.c_int32), ("f_g", C.c_double), ("mode", C.c_int32),
+                ("prop_tol", C.c_double), ("n_ft", C.c_int32), ("batch", C.c_int32)]
+
+
+class SgwError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load():
+    """Load libsgw.so (build it first with paper_2601_21005_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_2601_21005_amd.build` (no CPU fallback exists)")
+    lib = C.CDLL(LIB_PATH)
+    vp, i32, i64, d, dp = C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.POINTER(C.c_double)
+    lib.sgw_create.argtypes = [C.POINTER(SgwGrid), dp, C.POINTER(SgwProjectors), C.c_int,
+                               vp, i64, C.POINTER(vp)]
+    lib.sgw_destroy.argtypes = [vp]
+    lib.sgw_destroy.restype = None
+    lib.sgw_last_error.argtypes = [vp]
+    lib.sgw_last_error.restype = C.c_char_p
+    lib.sgw_bounds.argtypes = [vp, d, dp, dp]
+    lib.sgw_apply_H.argtypes = [vp, vp, vp, i64, i64]
+    lib.sgw_fermi_coefficients.argtypes = [d, d, d, d, i32, dp]
+    lib.sgw_fermi_filter.argtypes = [vp, vp, i64, i64, dp, i32, d, d]
+    lib.sgw_propagator_coefficients.argtypes = [d, d, d, d, i32, dp, C.POINTER(i32)]
+    lib.sgw_cheb_propagate.argtypes = [vp, vp, i64, i64, d, i32, d, d, d]
+    lib.sgw_tdh_init.argtypes = [vp, C.POINTER(SgwTdhState), vp]
+    lib.sgw_tdh_step.argtypes = [vp, C.POINTER(SgwTdhState), i32, d]
+    lib.sgw_sigma_estimate.argtypes = [vp, C.POINTER(SgwSigmaParams), dp, dp, dp, dp]
+    lib.sgw_qp_solve.argtypes = [dp, i32, d, d, d, d, d, dp, dp, dp]
+    lib.sgw_sigma_omega.argtypes = [dp, i32, d, d, dp, i32, dp]
+    lib.sgw_kernel_timer.argtypes = [vp, i32]
+    lib.sgw_kernel_timer_read.argtypes = [vp, dp, C.POINTER(i64), C.POINTER(i64)]
+    for name in EXPORTS:
+        if name not in ("sgw_destroy", "sgw_last_error"):
+            getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _dptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _iptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def _check(code, ctx=None):
+    if code != SGW_OK:
+        msg = load().sgw_last_error(ctx)
+        raise SgwError(code, msg.decode() if msg else "")
+
+
+def _dev(t, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a torch tensor on the GPU")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+# ------------------------------------------------------------------ host calls
+def sgw_fermi_coefficients(mu, beta, emin, emax, ncoef):
+    out = np.zeros(int(ncoef))
+    _check(load().sgw_fermi_coefficients(mu, beta, emin, emax, int(ncoef), _dptr(out)))
+    return out
+
+
+def sgw_propagator_coefficients(emin, emax, tau, tol=1e-14, max_terms=4096):
+    out = np.zeros(2 * max_terms)
+    nt = C.c_int32(0)
+    _check(load().sgw_propagator_coefficients(emin, emax, tau, tol, max_terms, _dptr(out),
+                                             C.byref(nt)))
+    b = out[:2 * nt.value]
+    return b[0::2] + 1j * b[1::2]
+
+
+def sgw_qp_solve(sigma_t, dt, gamma, eps_ks, x, vxc=0.0):
+    s = np.ascontiguousarray(np.asarray(sigma_t, dtype=np.complex128))
+    n_tau = (s.size - 1) // 2
+    buf = np.ascontiguousarray(np.stack([s.real, s.imag], axis=-1).ravel())
+    eg, el, z = C.c_double(), C.c_double(), C.c_double()
+    _check(load().sgw_qp_solve(_dptr(buf), n_tau, dt, gamma, eps_ks, x, vxc, C.byref(eg),
+                               C.byref(el), C.byref(z)))
+    return eg.value, el.value, z.value
+
+
+def sgw_sigma_omega(sigma_t, dt, gamma, omega):
+    s = np.asarray(sigma_t, dtype=np.complex128)
+    n_tau = (s.size - 1) // 2
+    buf = np.ascontiguousarray(np.stack([s.real, s.imag], axis=-1).ravel())
+    om = np.ascontiguousarray(np.atleast_1d(np.asarray(omega, dtype=np.float64)))
+    out = np.zeros(2 * om.size)
+    _check(load().sgw_sigma_omega(_dptr(buf), n_tau, dt, gamma, _dptr(om), om.size, _dptr(out)))
+    return out[0::2] + 1j * out[1::2]
+
+
+# ------------------------------------------------------------------ context
+class Context:
+    """A libsgw context: H on a grid, in one precision, on one stream."""
+
+    def __init__(self, n, h, v_loc, projectors=None, precision=SGW_C64, ecut=0.0,
+                 max_nvec=256, stream=None):
+        import torch
+        lib = load()
+        nx, ny, nz = (n, n, n) if np.isscalar(n) else tuple(n)
+        self.n = (int(nx), int(ny), int(nz))
+        self.N = self.n[0] * self.n[1] * self.n[2]
+        self.precision = precision
+        self.cdtype = torch.complex128 if precision == SGW_C128 else torch.complex64
+        self.rdtype = torch.float64 if precision == SGW_C128 else torch.float32
+        g = SgwGrid(self.n[0], self.n[1], self.n[2], float(h), float(ecut))
+        v = np.ascontiguousarray(np.asarray(v_loc, dtype=np.float64).ravel())
+        if v.size != self.N:
+            raise ValueError("v_loc has the wrong size")
+        self._keep = [v]
+        pp = None
+        if projectors is not None:
+            p = projectors
+            arrs = dict(pos=np.ascontiguousarray(np.asarray(p.pos, dtype=np.float64)),
+                        pb=np.ascontiguousarray(np.asarray(p.proj_begin, dtype=np.int32)),
+                        l=np.ascontiguousarray(np.asarray(p.l, dtype=np.int32)),
+                        m=np.ascontiguousarray(np.asarray(p.m, dtype=np.int32)),
+                        rc=np.ascontiguousarray(np.asarray(p.rc, dtype=np.float64)),
+                        ekb=np.ascontiguousarray(np.asarray(p.ekb, dtype=np.float64)))
+            self._keep.append(arrs)
+            pp = SgwProjectors(len(arrs["pb"]) - 1, _dptr(arrs["pos"]), _iptr(arrs["pb"]),
+                               _iptr(arrs["l"]), _iptr(arrs["m"]), _dptr(arrs["rc"]),
+                               _dptr(arrs["ekb"]), float(p.rcut_over_rc))
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self.stream = stream
+        ctx = C.c_void_p()
+        code = lib.sgw_create(C.byref(g), _dptr(v), C.byref(pp) if pp is not None else None,
+                              int(precision), C.c_void_p(stream), int(max_nvec), C.byref(ctx))
+        _check(code, None)
+        self.ctx = ctx
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            load().sgw_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # device arrays of this context's precision
+    def vectors(self, nvec):
+        import torch
+        return torch.zeros((nvec, self.N), dtype=self.cdtype, device="cuda")
+
+    def fields(self, n):
+        import torch
+        return torch.zeros((n, self.N), dtype=self.rdtype, device="cuda")
+
+    def bounds(self, pad=0.01):
+        a, b = C.c_double(), C.c_double()
+        _check(load().sgw_bounds(self.ctx, pad, C.byref(a), C.byref(b)), self.ctx)
+        return a.value, b.value
+
+    def apply_H(self, psi, hpsi):
+        _check(load().sgw_apply_H(self.ctx, _dev(psi, "psi"), _dev(hpsi, "hpsi"),
+                                  psi.shape[0], psi.shape[-1]), self.ctx)
+
+    def fermi_filter(self, v, coef, emin, emax):
+        c = np.ascontiguousarray(np.asarray(coef, dtype=np.float64))
+        _check(load().sgw_fermi_filter(self.ctx, _dev(v, "v"), v.shape[0], v.shape[-1],
+                                       _dptr(c), c.size, emin, emax), self.ctx)
+
+    def cheb_propagate(self, psi, dt, nsteps, emin, emax, tol=1e-14):
+        _check(load().sgw_cheb_propagate(self.ctx, _dev(psi, "psi"), psi.shape[0],
+                                         psi.shape[-1], dt, int(nsteps), emin, emax, tol),
+               self.ctx)
+
+    def tdh_state(self, psi, v, u, vh0, nsample, neta, weight):
+        st = SgwTdhState(int(nsample), int(neta), float(weight), _dev(psi, "psi"),
+                         _dev(v, "v"), _dev(u, "u"), _dev(vh0, "vh0"))
+        st._keep = (psi, v, u, vh0)
+        return st
+
+    def tdh_init(self, st, dv):
+        _check(load().sgw_tdh_init(self.ctx, C.byref(st), _dev(dv, "dv")), self.ctx)
+
+    def tdh_step(self, st, nsub, dt_sub):
+        _check(load().sgw_tdh_step(self.ctx, C.byref(st), int(nsub), float(dt_sub)), self.ctx)
+
+    def kernel_timer(self, enable):
+        _check(load().sgw_kernel_timer(self.ctx, 1 if enable else 0), self.ctx)
+
+    def kernel_timer_read(self):
+        ms, n, pts = C.c_double(), C.c_int64(), C.c_int64()
+        _check(load().sgw_kernel_timer_read(self.ctx, C.byref(ms), C.byref(n), C.byref(pts)),
+               self.ctx)
+        return ms.value, n.value, pts.value
+
+    def sigma_estimate(self, phi, seed, n_zeta, n_eta, n_tau, dt, m_sub, mu, beta, ncoef,
+                       emin, emax, n_xi=10000, f_g=0.003, mode=0, prop_tol=1e-14, n_ft=0,
+                       first_sample=0, batch=0):
+        p = SgwSigmaParams(int(seed), int(first_sample), int(n_zeta), int(n_eta), int(n_tau),
+                           float(dt), int(m_sub), float(mu), float(beta), int(ncoef),
+                           float(emin), float(emax), int(n_xi), float(f_g), int(mode),
+                           float(prop_tol), int(n_ft), int(batch))
+        ph = np.ascontiguousarray(np.asarray(phi, dtype=np.float64).ravel())
+        sig = np.zeros((n_zeta, 2 * n_tau + 1, 2))
+        x = np.zeros(n_zeta)
+        ms = np.zeros(6)
+        _check(load().sgw_sigma_estimate(self.ctx, C.byref(p), _dptr(ph), _dptr(sig), _dptr(x),
+                                         _dptr(ms)), self.ctx)
+        return sig[..., 0] + 1j * sig[..., 1], x, ms

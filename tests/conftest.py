@@ -52,3 +52,53 @@ def tiny12_eig(tiny12):
     from oracle import eigen
     s, H = tiny12
     return eigen.dense_eigh(H)
+
+
+def make_ctx(system, precision, max_nvec=64):
+    """libsgw context for a ``systems.System`` (GPU tests only)."""
+    from paper_2601_21005_amd import sgw
+    return sgw.Context(system.grid.n, system.grid.h, system.v_loc, system.projectors,
+                       precision=precision, ecut=system.ecut, max_nvec=max_nvec)
+
+
+def rel_err(a, b):
+    """max |a - b| / max |b|."""
+    import numpy as np
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def norm_err(a, b):
+    """||a - b|| / ||b|| per row (max over rows)."""
+    import numpy as np
+    a, b = np.atleast_2d(a), np.atleast_2d(b)
+    return float(np.max(np.linalg.norm(a - b, axis=-1) / np.linalg.norm(b, axis=-1)))
+
+
+@pytest.fixture(scope="session")
+def cfg1():
+    from paper_2601_21005_amd import systems
+    s = systems.gaussian_wells()
+    return s, build_oracle_h(s)
+
+
+@pytest.fixture(scope="session")
+def si35():
+    from paper_2601_21005_amd import systems
+    s = systems.si35h36()
+    return s, build_oracle_h(s, workers=8)
+
+
+@pytest.fixture(scope="session")
+def tiny12l():
+    """12^3 local-only system (radix-3 FFT path; KB tiles need n % 8 == 0)."""
+    from paper_2601_21005_amd import systems
+    s = systems.tiny_system(12, 0.5, with_kb=False)
+    return s, build_oracle_h(s)
+
+
+@pytest.fixture(scope="session")
+def tiny12l_eig(tiny12l):
+    from oracle import eigen
+    s, H = tiny12l
+    return eigen.dense_eigh(H)

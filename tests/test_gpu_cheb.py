@@ -1,0 +1,118 @@
+"""GPU parity: Chebyshev filter (Eq. 3) and propagator through the C ABI."""
+import numpy as np
+import pytest
+import torch
+
+from conftest import make_ctx, norm_err
+from oracle import chebyshev as cheb
+from oracle import qp as oqp
+from paper_2601_21005_amd import sgw
+
+pytestmark = pytest.mark.gpu
+
+
+def to_dev(ctx, x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(ctx.cdtype).cuda()
+
+
+def test_host_coefficients_match_oracle():
+    for mu, beta, lo, hi, n in ((-0.3, 50.0, -5.0, 60.0, 4000), (0.1, 6.0, -5.7, 61.0, 300)):
+        a = sgw.sgw_fermi_coefficients(mu, beta, lo, hi, n)
+        assert np.max(np.abs(a - cheb.fermi_coefficients(mu, beta, lo, hi, n))) < 1e-13
+    for tau in (0.05, 0.2, -0.2, 1.5):
+        b = sgw.sgw_propagator_coefficients(-14.8, 28.4, tau)
+        ob = cheb.propagator_coefficients(-14.8, 28.4, tau)
+        assert b.size == ob.size and np.max(np.abs(b - ob)) < 1e-14
+
+
+def test_host_qp_solve_matches_oracle():
+    nt, dt = 80, 0.1
+    t = dt * np.arange(-nt, nt + 1)
+    sig = (np.where(t > 0, -0.08j * np.exp(0.4j * t), 0)
+           + np.where(t < 0, 0.05j * np.exp(1.3j * t), 0))
+    sig[nt] = 0.5 * (-0.08j + 0.05j)
+    for eks, x in ((-0.6, -0.2), (0.1, -0.05)):
+        got = sgw.sgw_qp_solve(sig, dt, 0.2, eks, x)
+        ref = oqp.qp_solve(sig, dt, 0.2, eks, x)
+        assert np.allclose(got, ref, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("prec,tol", [(sgw.SGW_C128, 1e-11), (sgw.SGW_C64, 5e-5)])
+def test_filter_tiny12(tiny12l, tiny12l_eig, prec, tol):
+    s, H = tiny12l
+    e, _ = tiny12l_eig
+    ctx = make_ctx(s, prec, max_nvec=2)
+    lo, hi = ctx.bounds()
+    mu, beta = 0.5 * (e[1] + e[2]), 6.0
+    n = cheb.suggested_ncoef(mu, beta, lo, hi, tol=1e-12, nmax=8192)
+    rs = np.random.default_rng(1)
+    x = rs.standard_normal((3, s.grid.N)) + 1j * rs.standard_normal((3, s.grid.N))
+    xd = to_dev(ctx, x)
+    ctx.fermi_filter(xd, sgw.sgw_fermi_coefficients(mu, beta, lo, hi, n), lo, hi)
+    xin = to_dev(ctx, x).cpu().numpy().astype(np.complex128)
+    ref = cheb.apply_series(H, cheb.fermi_coefficients(mu, beta, lo, hi, n), lo, hi, xin)
+    assert norm_err(xd.cpu().numpy(), ref) < tol
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec,tol", [(sgw.SGW_C128, 1e-10), (sgw.SGW_C64, 2e-4)])
+def test_filter_gaussian_wells_long(cfg1, prec, tol):
+    """Config-1 filter (beta = 50 /Ha, mu mid-gap): ~4.5k terms."""
+    s, H = cfg1
+    ctx = make_ctx(s, prec, max_nvec=2)
+    lo, hi = ctx.bounds()
+    mu, beta = -0.15, 50.0
+    n = cheb.suggested_ncoef(mu, beta, lo, hi, tol=1e-10, nmax=16384)
+    assert n > 3000
+    x = np.stack([np.random.default_rng(2).choice([-1.0, 1.0], s.grid.N) / np.sqrt(0.125)
+                  * (1 + 1j)])
+    xd = to_dev(ctx, x)
+    ctx.fermi_filter(xd, sgw.sgw_fermi_coefficients(mu, beta, lo, hi, n), lo, hi)
+    ref = cheb.apply_series(H, cheb.fermi_coefficients(mu, beta, lo, hi, n), lo, hi, x)
+    assert norm_err(xd.cpu().numpy(), ref) < tol
+    ctx.close()
+
+
+def test_filter_detects_narrow_interval(tiny8):
+    s, H = tiny8
+    ctx = make_ctx(s, sgw.SGW_C128)
+    lo, hi = ctx.bounds()
+    hi_bad = lo + 0.3 * (hi - lo)                  # far below the spectrum's top
+    x = to_dev(ctx, np.random.default_rng(3).standard_normal((1, s.grid.N)) + 0j)
+    with pytest.raises(sgw.SgwError) as e:
+        ctx.fermi_filter(x, sgw.sgw_fermi_coefficients(-1.0, 5.0, lo, hi_bad, 400), lo, hi_bad)
+    assert e.value.code == sgw.SGW_EDIVERGED
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec,tol", [(sgw.SGW_C128, 1e-12), (sgw.SGW_C64, 2e-5)])
+def test_propagator_tiny12_many_steps(tiny12l, prec, tol):
+    s, H = tiny12l
+    ctx = make_ctx(s, prec)
+    lo, hi = ctx.bounds()
+    rs = np.random.default_rng(4)
+    x = rs.standard_normal((2, s.grid.N)) + 1j * rs.standard_normal((2, s.grid.N))
+    xd = to_dev(ctx, x)
+    xin = xd.cpu().numpy().astype(np.complex128)
+    ctx.cheb_propagate(xd, 0.2, 10, lo, hi)
+    ref = xin
+    for _ in range(10):
+        ref = cheb.propagate(H, lo, hi, 0.2, ref)
+    assert norm_err(xd.cpu().numpy(), ref) < tol
+    ctx.close()
+
+
+def test_propagator_si35h36_one_step_fp32(si35):
+    """One output step (dt = 0.05) of the zeta propagator in complex FP32 on
+    the 64^3 cluster: relative error per step below 1e-6."""
+    s, H = si35
+    ctx = make_ctx(s, sgw.SGW_C64)
+    lo, hi = ctx.bounds()
+    rs = np.random.default_rng(5)
+    x = rs.standard_normal((3, s.grid.N)) + 1j * rs.standard_normal((3, s.grid.N))
+    xd = to_dev(ctx, x)
+    xin = xd.cpu().numpy().astype(np.complex128)
+    ctx.cheb_propagate(xd, 0.05, 1, lo, hi)
+    ref = cheb.propagate(H, lo, hi, 0.05, xin)
+    assert norm_err(xd.cpu().numpy(), ref) < 1e-6
+    ctx.close()

@@ -1,0 +1,103 @@
+"""GPU parity: H|psi> through the C ABI against the FP64 oracle (Eq. 1)."""
+import numpy as np
+import pytest
+import torch
+
+from conftest import make_ctx, norm_err, rel_err
+from paper_2601_21005_amd import sgw
+
+pytestmark = pytest.mark.gpu
+
+# FP32 paths: inputs are exact FP32 values on both sides, so the error is the
+# kernels' own rounding: ~log2(N_g) FFT stages of unit roundoff 6e-8 in each
+# direction plus the potential and projector terms -> 3e-6 normwise (the
+# largest entries of H psi come from T(k) up to 60 Ha).
+TOL = {sgw.SGW_C128: 1e-12, sgw.SGW_C64: 3e-6}
+
+
+def run_hpsi(system, H, prec, nvec=5, pad=0, seed=0):
+    ctx = make_ctx(system, prec, max_nvec=4)        # forces chunking (5 > 4)
+    N = system.grid.N
+    rs = np.random.default_rng(seed)
+    x = rs.standard_normal((nvec, N)) + 1j * rs.standard_normal((nvec, N))
+    dt = ctx.cdtype
+    xin = torch.zeros((nvec, N + pad), dtype=dt, device="cuda")
+    xin[:, :N] = torch.from_numpy(x).to(dt)
+    out = torch.zeros_like(xin)
+    ctx.apply_H(xin, out)
+    torch.cuda.synchronize()
+    xin_h = xin[:, :N].cpu().numpy().astype(np.complex128)
+    ref = H.apply(xin_h)
+    got = out[:, :N].cpu().numpy().astype(np.complex128)
+    if pad:
+        assert torch.all(out[:, N:] == 0)
+    ctx.close()
+    return got, ref
+
+
+@pytest.mark.parametrize("prec", [sgw.SGW_C128, sgw.SGW_C64])
+def test_hpsi_tiny_with_kb(tiny8, prec):
+    s, H = tiny8
+    got, ref = run_hpsi(s, H, prec)
+    assert norm_err(got, ref) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", [sgw.SGW_C128, sgw.SGW_C64])
+def test_hpsi_tiny12_padded_ld(tiny12l, prec):
+    s, H = tiny12l
+    got, ref = run_hpsi(s, H, prec, nvec=3, pad=40)
+    assert norm_err(got, ref) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", [sgw.SGW_C128, sgw.SGW_C64])
+def test_hpsi_gaussian_wells_32(cfg1, prec):
+    s, H = cfg1
+    got, ref = run_hpsi(s, H, prec, nvec=7)
+    assert norm_err(got, ref) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", [sgw.SGW_C128, sgw.SGW_C64])
+def test_hpsi_si35h36_64(si35, prec):
+    # C128 at 64^3 runs the x-line / y-pencil fallback (plane too big for LDS)
+    s, H = si35
+    got, ref = run_hpsi(s, H, prec, nvec=9)
+    assert norm_err(got, ref) < TOL[prec]
+    assert rel_err(got, ref) < 10 * TOL[prec]
+
+
+def test_hpsi_errors_and_empty(tiny8):
+    s, H = tiny8
+    ctx = make_ctx(s, sgw.SGW_C128)
+    x = torch.zeros((2, s.grid.N), dtype=torch.complex128, device="cuda")
+    y = torch.zeros_like(x)
+    ctx.apply_H(x[:0], y[:0])                         # nvec = 0: no-op
+    with pytest.raises(sgw.SgwError) as e:          # ld < N
+        sgw._check(sgw.load().sgw_apply_H(ctx.ctx, x.data_ptr(), y.data_ptr(), 2,
+                                          s.grid.N - 1), ctx.ctx)
+    assert e.value.code == sgw.SGW_EINVAL
+    with pytest.raises(sgw.SgwError) as e:          # in place is refused
+        sgw._check(sgw.load().sgw_apply_H(ctx.ctx, x.data_ptr(), x.data_ptr(), 2, s.grid.N),
+                   ctx.ctx)
+    assert e.value.code == sgw.SGW_EINVAL
+    ctx.close()
+
+
+def test_create_rejects_bad_input(tiny8):
+    s, _ = tiny8
+    v = s.v_loc.copy()
+    v[3] = np.nan
+    with pytest.raises(sgw.SgwError) as e:
+        sgw.Context(8, 0.7, v, None, precision=sgw.SGW_C128)
+    assert e.value.code == sgw.SGW_EINVAL
+    with pytest.raises(sgw.SgwError) as e:
+        sgw.Context(10, 0.7, np.zeros(1000), None, precision=sgw.SGW_C128)
+    assert e.value.code == sgw.SGW_EUNSUPPORTED
+
+
+def test_bounds_match_oracle(si35, tiny8):
+    for s, H in (si35, tiny8):
+        ctx = make_ctx(s, sgw.SGW_C64)
+        a, b = ctx.bounds(0.01)
+        ea, eb = H.bounds(0.01)
+        assert abs(a - ea) < 1e-10 * abs(ea) and abs(b - eb) < 1e-10 * abs(eb)
+        ctx.close()

@@ -1,0 +1,88 @@
+"""GPU parity of the whole hot path: Sigma_c,i(t) and X_i per sample
+(Sec. 2.1, Eq. 3-5) and the QP energy (Eq. 6, 7), identical seeds."""
+import numpy as np
+import pytest
+
+from conftest import make_ctx, rel_err
+from oracle import chebyshev as cheb
+from oracle import eigen
+from oracle import qp as oqp
+from oracle.sigma import SGWParams, estimate
+from paper_2601_21005_amd import sgw
+
+pytestmark = pytest.mark.gpu
+HA_EV = 27.211386245988
+
+
+def compare(system, H, phi, prec, **kw):
+    ctx = make_ctx(system, prec, max_nvec=8)
+    lo, hi = ctx.bounds()
+    kw.update(emin=lo, emax=hi)
+    mode = kw.pop("mode", "xi")
+    sig, x, ms = ctx.sigma_estimate(phi, mode=0 if mode == "xi" else 1, **kw)
+    ctx.close()
+    kw.pop("batch", None)
+    p = SGWParams(mode=mode, **kw)
+    sig_o, x_o = estimate(H, phi, p)
+    return sig, x, sig_o, x_o, p
+
+
+def qp_pair(sig, x, sig_o, x_o, p, eks):
+    gam = oqp.default_gamma(p.n_tau, p.dt)
+    e1 = oqp.qp_solve(sig.mean(0), p.dt, gam, eks, x.mean())[0]
+    e0 = oqp.qp_solve(sig_o.mean(0), p.dt, gam, eks, x_o.mean())[0]
+    return e1, e0
+
+
+@pytest.fixture(scope="module")
+def tiny_states(tiny8_eig):
+    return tiny8_eig
+
+
+@pytest.mark.parametrize("mode", ["xi", "exact"])
+@pytest.mark.parametrize("prec,tol", [(sgw.SGW_C128, 1e-9), (sgw.SGW_C64, 2e-4)])
+def test_sigma_tiny8(tiny8, tiny_states, mode, prec, tol):
+    s, H = tiny8
+    e, V = tiny_states
+    phi = V[s.n_occ - 1]
+    lo, hi = H.bounds()
+    mu = 0.5 * (e[1] + e[2])
+    n = cheb.suggested_ncoef(mu, 10.0, lo, hi, tol=1e-12, nmax=8192)
+    sig, x, sig_o, x_o, p = compare(s, H, phi, prec, seed=11, n_zeta=3, n_eta=4, n_tau=6,
+                                    dt=0.2, m_sub=2, mu=mu, beta=10.0, ncoef=n, n_xi=64,
+                                    f_g=0.125, mode=mode, batch=2)
+    assert rel_err(sig, sig_o) < tol
+    assert rel_err(x, x_o) < tol
+    e1, e0 = qp_pair(sig, x, sig_o, x_o, p, e[s.n_occ - 1])
+    assert abs(e1 - e0) * HA_EV < (1e-9 if prec == sgw.SGW_C128 else 1e-4)
+
+
+@pytest.mark.parametrize("prec", [sgw.SGW_C128, sgw.SGW_C64])
+def test_sigma_gaussian_wells(cfg1, prec):
+    """Config 1 shape: 32^3, 8 wells, N_eta = 8; shortened time axis."""
+    s, H = cfg1
+    ev, V = eigen.lowest_states(H, 10)
+    phi = V[7]
+    mu = 0.5 * (ev[7] + ev[8])
+    lo, hi = H.bounds()
+    n = cheb.suggested_ncoef(mu, 10.0, lo, hi, tol=1e-10, nmax=8192)
+    sig, x, sig_o, x_o, p = compare(s, H, phi, prec, seed=1001, n_zeta=2, n_eta=8, n_tau=8,
+                                    dt=0.2, m_sub=4, mu=mu, beta=10.0, ncoef=n,
+                                    n_xi=2000, f_g=0.003, mode="xi")
+    tol = 1e-9 if prec == sgw.SGW_C128 else 2e-4
+    assert rel_err(sig, sig_o) < tol
+    e1, e0 = qp_pair(sig, x, sig_o, x_o, p, ev[7])
+    assert abs(e1 - e0) * HA_EV < (1e-9 if prec == sgw.SGW_C128 else 1e-4)
+
+
+def test_sigma_si35h36_fp32(si35):
+    """64^3 cluster with KB projectors, complex FP32: a short run."""
+    s, H = si35
+    rs = np.random.default_rng(8)
+    phi = rs.standard_normal(s.grid.N)
+    phi /= np.sqrt(H.grid.dV * np.sum(phi * phi))
+    sig, x, sig_o, x_o, p = compare(s, H, phi, sgw.SGW_C64, seed=1002, n_zeta=1, n_eta=4,
+                                    n_tau=3, dt=0.05, m_sub=1, mu=-4.65, beta=2.0, ncoef=120,
+                                    n_xi=500, f_g=0.003, mode="xi")
+    assert rel_err(sig, sig_o) < 2e-4
+    assert rel_err(x, x_o) < 1e-5
