@@ -58,19 +58,21 @@ def lowest_states(ctx, nstates, emin, emax, dV, block=None, degree=16, tol=None,
             Yn = (_apply_real(ctx, Yc, win, wout) - c * Yc) * (2.0 * sig2 / e) - (sig * sig2) * Yp
             Yp, Yc, sig = Yc, Yn, sig2
         Y = Yc
-        # orthonormalise (Cholesky QR, twice for stability)
+        # orthonormalise (Cholesky QR, twice for stability); the k x k algebra
+        # runs on the host in FP64, the block products are GEMMs on the GPU
         for _ in range(2):
-            G = Y @ Y.T
-            L = torch.linalg.cholesky(G)
-            Y = torch.linalg.solve_triangular(L, Y, upper=False)
+            G = (Y @ Y.T).cpu()
+            Linv = torch.linalg.inv(torch.linalg.cholesky(G))
+            Y = Linv.to(Y.device) @ Y
         HY = _apply_real(ctx, Y, win, wout)
-        Hs = Y @ HY.T
+        Hs = (Y @ HY.T).cpu()
         Hs = 0.5 * (Hs + Hs.T)
         w, Q = torch.linalg.eigh(Hs)
-        Y = Q.T @ Y
-        HY = Q.T @ HY
+        Qd = Q.to(Y.device)
+        Y = Qd.T @ Y
+        HY = Qd.T @ HY
         lam = w
-        res = torch.linalg.norm(HY - w[:, None] * Y, dim=1)
+        res = torch.linalg.norm(HY - w.to(Y.device)[:, None] * Y, dim=1)
         if float(res[:nstates].max()) < tol:
             break
         a = float(w[-1])
