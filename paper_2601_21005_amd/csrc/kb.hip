@@ -38,8 +38,8 @@ __global__ __launch_bounds__(NTK) void k_kb_gather(const cplx<R> *psi, int64_t l
   constexpr int NV = KBV<R>::NV;
   using C = cplx<R>;
   __shared__ C s[KB_TP * NV];
-  const int t = blockIdx.x;
-  const int64_t v0 = (int64_t)blockIdx.y * NV;
+  const int t = blockIdx.y;
+  const int64_t v0 = (int64_t)blockIdx.x * NV;
   const int base = tile_base[t];
   for (int idx = threadIdx.x; idx < KB_TP * NV; idx += NTK) {
     const int vl = idx / KB_TP, p = idx % KB_TP;
@@ -121,8 +121,8 @@ __global__ __launch_bounds__(NTK) void k_kb_scatter(const cplx<R> *coef, int64_t
   constexpr int NV = KBV<R>::NV;
   using C = cplx<R>;
   __shared__ C c[KB_MAXE * NV];
-  const int t = blockIdx.x;
-  const int64_t v0 = (int64_t)blockIdx.y * NV;
+  const int t = blockIdx.y;
+  const int64_t v0 = (int64_t)blockIdx.x * NV;
   const int off = tile_off[t], ne = tile_off[t + 1] - off;
   const int base = tile_base[t];
   for (int idx = threadIdx.x; idx < ne * NV; idx += NTK) {
@@ -173,8 +173,8 @@ static void gather_t(sgw_ctx *ctx, const void *psi, int64_t nvec, int64_t ld, vo
   using C = cplx<R>;
   C *partial = ctx->buf("kb_partial", sizeof(C) * (size_t)ctx->kb_nentry * nvec).as<C>();
   const int64_t nvb = (nvec + NV - 1) / NV;
-  SGW_REQUIRE(nvb <= 65535, SGW_EUNSUPPORTED, "KB gather: too many vectors in one call");
-  hipLaunchKernelGGL(k_kb_gather<R>, dim3(ctx->kb_ntile, nvb), dim3(NTK), 0, ctx->stream,
+  SGW_REQUIRE(ctx->kb_ntile <= 65535, SGW_EUNSUPPORTED, "KB gather: too many tiles");
+  hipLaunchKernelGGL(k_kb_gather<R>, dim3(nvb, ctx->kb_ntile), dim3(NTK), 0, ctx->stream,
                      static_cast<const C *>(psi), ld, nvec, ctx->d_kb_tile_base.as<int>(),
                      ctx->d_kb_tile_off.as<int>(), ctx->d_kb_beta.as<R>(), partial, ctx->nx,
                      ctx->ny, (R)ctx->dV);
@@ -216,8 +216,8 @@ static void scatter_t(sgw_ctx *ctx, const void *coef, int64_t nvec, void *dst, i
   constexpr int NV = KBV<R>::NV;
   using C = cplx<R>;
   const int64_t nvb = (nvec + NV - 1) / NV;
-  SGW_REQUIRE(nvb <= 65535, SGW_EUNSUPPORTED, "KB scatter: too many vectors in one call");
-  hipLaunchKernelGGL(k_kb_scatter<R>, dim3(ctx->kb_ntile, nvb), dim3(NTK), 0, ctx->stream,
+  SGW_REQUIRE(ctx->kb_ntile <= 65535, SGW_EUNSUPPORTED, "KB scatter: too many tiles");
+  hipLaunchKernelGGL(k_kb_scatter<R>, dim3(nvb, ctx->kb_ntile), dim3(NTK), 0, ctx->stream,
                      static_cast<const C *>(coef), nvec, ctx->d_kb_tile_base.as<int>(),
                      ctx->d_kb_tile_off.as<int>(), ctx->d_kb_entry_proj.as<int>(),
                      ctx->d_kb_beta.as<R>(), static_cast<C *>(dst), ld, (R)s1re, (R)s1im,
