@@ -2,6 +2,7 @@
 // filter and propagator, the TDH response and the full Sigma_c(t) estimate.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 
 #include "common.h"
@@ -78,14 +79,17 @@ void *cheb_series(sgw_ctx *ctx, void *v0, void *w1, void *acc, void *tmp, int64_
   const int nc = (int)coef.size() / 2;
   const int64_t N = ctx->N;
   const double c = 0.5 * (emax + emin), R = 0.5 * (emax - emin), invR = 1.0 / R;
-  launch_scale_copy(ctx, v0, N, acc, N, nvec, coef[0], coef[1]);
+  if (nc == 1) {
+    launch_scale_copy(ctx, v0, N, acc, N, nvec, coef[0], coef[1]);
+    return v0;
+  }
   void *cur = v0, *old = w1;
   void *kbC = nullptr;
   if (ctx->has_kb) kbC = ctx->buf("kbC", ctx->csize() * ctx->kb.nproj * nvec).p;
   for (int k = 0; k + 1 < nc; ++k) {
     const bool first = (k == 0);
     const double s2 = first ? 1.0 : 2.0;
-    const double br = coef[2 * (k + 1)], bi = coef[2 * (k + 1) + 1];
+    const double br = coef[2 * k], bi = coef[2 * k + 1];   // term of x = v_k
     if (ctx->has_kb) kb_gather_e(ctx, cur, nvec, N, kbC);
     EpiArgs e;
     e.x = cur;
@@ -99,10 +103,11 @@ void *cheb_series(sgw_ctx *ctx, void *v0, void *w1, void *acc, void *tmp, int64_
     e.first = first ? 1 : 0;
     e.scale2 = s2;
     fft3d_apply(ctx, cur, tmp, nullptr, nvec, N, MUL_KIN, 0.0, PLANE_INV_CHEB, e);
-    if (ctx->has_kb)
-      kb_scatter(ctx, kbC, nvec, old, N, s2 * invR, 0.0, acc, br * s2 * invR, bi * s2 * invR);
+    if (ctx->has_kb) kb_scatter(ctx, kbC, nvec, old, N, s2 * invR, 0.0, nullptr, 0.0, 0.0);
     std::swap(cur, old);
   }
+  // the last term
+  launch_axpy(ctx, cur, N, acc, N, nvec, coef[2 * (nc - 1)], coef[2 * (nc - 1) + 1]);
   return cur;
 }
 
@@ -252,6 +257,19 @@ sgw_status sgw_create(const sgw_grid *grid, const double *v_loc, const sgw_proje
     c->ecut = grid->ecut > 0 ? grid->ecut : 0.0;
     c->prec = prec;
     c->dbl = dbl;
+    if (const char *fv = std::getenv("SGW_FORCE_VARIANT")) {
+      // "name=i,name=i": pin autotuned kernel variants (testing)
+      std::string spec(fv);
+      size_t pos = 0;
+      while (pos < spec.size()) {
+        const size_t comma = spec.find(',', pos);
+        const std::string item = spec.substr(pos, comma == std::string::npos ? std::string::npos : comma - pos);
+        const size_t eq = item.find('=');
+        if (eq != std::string::npos) c->forced[item.substr(0, eq)] = std::atoi(item.c_str() + eq + 1);
+        if (comma == std::string::npos) break;
+        pos = comma + 1;
+      }
+    }
     c->stream = static_cast<hipStream_t>(hip_stream);
     c->max_nvec = max_nvec;
     c->vloc.assign(v_loc, v_loc + c->N);

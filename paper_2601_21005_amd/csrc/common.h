@@ -130,6 +130,38 @@ struct sgw_ctx {
     for (auto e : kt_events) (void)hipEventDestroy(e);
   }
 
+  // autotuned kernel variants: key "name/nvec" -> variant index.  Every
+  // variant of one name gives bit-identical results (only speed differs).
+  std::map<std::string, int> tuned;
+  std::map<std::string, int> forced;   // from SGW_FORCE_VARIANT="name=i,name=i"
+  template <typename F> int tune(const char *name, int64_t nvec, int nvar, F &&trial) {
+    const auto fit = forced.find(name);
+    if (fit != forced.end() && fit->second >= 0 && fit->second < nvar) return fit->second;
+    const std::string key = std::string(name) + "/" + std::to_string(nvec);
+    const auto it = tuned.find(key);
+    if (it != tuned.end()) return it->second;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+      throw sgw::Error{SGW_EHIP, "hipEventCreate failed"};
+    int best = 0;
+    float best_ms = 1e30f;
+    for (int i = 0; i < nvar; ++i) {
+      trial(i);                               // warm-up
+      (void)hipEventRecord(e0, stream);
+      trial(i);
+      (void)hipEventRecord(e1, stream);
+      (void)hipEventSynchronize(e1);
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (hipGetLastError() != hipSuccess) continue;
+      if (ms < best_ms) { best_ms = ms; best = i; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    tuned[key] = best;
+    return best;
+  }
+
   // scratch (grown on demand)
   std::map<std::string, std::unique_ptr<sgw::DevBuf>> scratch;
   sgw::DevBuf &buf(const std::string &name, size_t bytes) {

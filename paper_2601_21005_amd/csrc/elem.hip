@@ -42,6 +42,36 @@ void launch_scale_copy(sgw_ctx *ctx, const void *x, int64_t ldx, void *acc, int6
   SGW_HIP(hipGetLastError());
 }
 
+template <typename R>
+__global__ void k_axpy(const cplx<R> *x, int64_t ldx, cplx<R> *acc, int64_t lda, int64_t N,
+                       R cre, R cim) {
+  const int64_t r = (int64_t)blockIdx.x * NT + threadIdx.x;
+  const int64_t v = blockIdx.y;
+  if (r >= N) return;
+  const cplx<R> a = x[v * ldx + r];
+  cplx<R> o = acc[v * lda + r];
+  o.x += cre * a.x - cim * a.y;
+  o.y += cre * a.y + cim * a.x;
+  acc[v * lda + r] = o;
+}
+
+void launch_axpy(sgw_ctx *ctx, const void *x, int64_t ldx, void *acc, int64_t lda,
+                 int64_t nvec, double cre, double cim) {
+  for (int64_t v0 = 0; v0 < nvec; v0 += 65535) {
+    const int64_t nv = std::min<int64_t>(65535, nvec - v0);
+    if (ctx->dbl)
+      hipLaunchKernelGGL(k_axpy<double>, grid1(ctx->N, nv), dim3(NT), 0, ctx->stream,
+                         static_cast<const double2 *>(x) + v0 * ldx, ldx,
+                         static_cast<double2 *>(acc) + v0 * lda, lda, ctx->N, cre, cim);
+    else
+      hipLaunchKernelGGL(k_axpy<float>, grid1(ctx->N, nv), dim3(NT), 0, ctx->stream,
+                         static_cast<const float2 *>(x) + v0 * ldx, ldx,
+                         static_cast<float2 *>(acc) + v0 * lda, lda, ctx->N, (float)cre,
+                         (float)cim);
+  }
+  SGW_HIP(hipGetLastError());
+}
+
 void launch_copy(sgw_ctx *ctx, const void *src, int64_t lds, void *dst, int64_t ldd,
                  int64_t nvec) {
   SGW_HIP(hipMemcpy2DAsync(dst, ldd * ctx->csize(), src, lds * ctx->csize(),

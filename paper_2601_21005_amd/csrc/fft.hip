@@ -50,8 +50,10 @@ __device__ __forceinline__ void epilogue(const PassArgs &a, int64_t v, int64_t r
       static_cast<C *>(a.dst)[v * a.ld_dst + r] = val;
     } break;
     case PLANE_INV_CHEB: {
-      // w = (H x - c x)/R ; v_new = s2 w - v_old (v_old absent on the first
-      // step) ; acc += coef v_new
+      // x = v_n:  w = (H x - c x)/R ; v_{n+1} = s2 w - v_{n-1} (no v_{n-1}
+      // on the first step) ; acc += coef_n x  (acc = coef_0 x on the first
+      // step).  The projector part of H x is added to v_{n+1} afterwards, so
+      // the term of v_{n+1} enters acc on the next step, when it is x.
       const int64_t o = v * a.ld_x + r;
       const C x = static_cast<const C *>(a.e.x)[o];
       const R V = static_cast<const R *>(a.e.vloc)[r];
@@ -63,17 +65,21 @@ __device__ __forceinline__ void epilogue(const PassArgs &a, int64_t v, int64_t r
       nv.x = s2 * w.x;
       nv.y = s2 * w.y;
       C *vold = static_cast<C *>(a.e.vold);
+      C *acc = static_cast<C *>(a.e.acc);
+      const R br = (R)a.e.coef_re, bi = (R)a.e.coef_im;
+      C s;
       if (!a.e.first) {
         const C p = vold[o];
         nv.x -= p.x;
         nv.y -= p.y;
+        s = acc[o];
+      } else {
+        s.x = 0;
+        s.y = 0;
       }
       vold[o] = nv;
-      C *acc = static_cast<C *>(a.e.acc);
-      C s = acc[o];
-      const R br = (R)a.e.coef_re, bi = (R)a.e.coef_im;
-      s.x += br * nv.x - bi * nv.y;
-      s.y += br * nv.y + bi * nv.x;
+      s.x += br * x.x - bi * x.y;
+      s.y += br * x.y + bi * x.x;
       acc[o] = s;
     } break;
     case PLANE_INV_POISSON: {

@@ -11,6 +11,9 @@ bool fft_size_supported(int n, bool dbl);
 // acc[v] = (cre + i cim) x[v]
 void launch_scale_copy(sgw_ctx *ctx, const void *x, int64_t ldx, void *acc, int64_t lda,
                        int64_t nvec, double cre, double cim);
+// acc[v] += (cre + i cim) x[v]
+void launch_axpy(sgw_ctx *ctx, const void *x, int64_t ldx, void *acc, int64_t lda,
+                 int64_t nvec, double cre, double cim);
 // dst[v] = src[v]
 void launch_copy(sgw_ctx *ctx, const void *src, int64_t lds, void *dst, int64_t ldd,
                  int64_t nvec);

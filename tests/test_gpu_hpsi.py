@@ -101,3 +101,25 @@ def test_bounds_match_oracle(si35, tiny8):
         ea, eb = H.bounds(0.01)
         assert abs(a - ea) < 1e-10 * abs(ea) and abs(b - eb) < 1e-10 * abs(eb)
         ctx.close()
+
+
+def test_kb_variants_bit_identical(si35, monkeypatch):
+    """Every autotuned KB kernel variant adds the same products in the same
+    order: H psi is bitwise the same whichever variant runs."""
+    s, H = si35
+    rs = np.random.default_rng(9)
+    x = rs.standard_normal((20, s.grid.N)) + 1j * rs.standard_normal((20, s.grid.N))
+    ref = None
+    for g in range(6):
+        for sc in range(2):
+            monkeypatch.setenv("SGW_FORCE_VARIANT", f"kb_gather={g},kb_scatter={sc}")
+            ctx = make_ctx(s, sgw.SGW_C64, max_nvec=32)
+            xd = torch.from_numpy(x).to(torch.complex64).cuda()
+            yd = torch.empty_like(xd)
+            ctx.apply_H(xd, yd)
+            out = yd.cpu().numpy()
+            ctx.close()
+            if ref is None:
+                ref = out
+            else:
+                assert np.array_equal(out, ref), (g, sc)
