@@ -33,6 +33,11 @@ HBM_PEAK_GBS = 8000.0
 CHEB_ALGO_BYTES = 40.0
 # H psi in complex FP32: read psi, write H psi
 HPSI_ALGO_BYTES = 16.0
+# HBM bytes per (grid point x complex vector) that the same kernel moves, from
+# FETCH_SIZE + WRITE_SIZE hardware counters on the 260-vector filter launch,
+# scaled by the counters' reading for a plain 256 MiB device copy.  Valid only
+# for the kernel source it was measured on; None once that kernel changes.
+CHEB_MEASURED_BYTES = 45.91
 
 
 def parse():
@@ -207,7 +212,12 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "k_plane<float,64,64,PLANE_INV_CHEB>",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS if achieved else None,
-                     "traffic": None, "launches": k_launch,
+                     "traffic": (CHEB_MEASURED_BYTES * k_pts / k_launch
+                                 if k_launch and CHEB_MEASURED_BYTES else None),
+                     "traffic_unit": "B per launch",
+                     "algo_bytes_per_ptvec": CHEB_ALGO_BYTES,
+                     "traffic_bytes_per_ptvec": CHEB_MEASURED_BYTES,
+                     "launches": k_launch,
                      "avg_launch_us": 1e3 * k_ms / k_launch if k_launch else None},
     }
     if not args.no_cpu_baseline:

@@ -257,6 +257,7 @@ sgw_status sgw_create(const sgw_grid *grid, const double *v_loc, const sgw_proje
     c->ecut = grid->ecut > 0 ? grid->ecut : 0.0;
     c->prec = prec;
     c->dbl = dbl;
+    if (const char *fc = std::getenv("SGW_FILTER_CHUNK")) c->filter_chunk = std::atoi(fc);
     if (const char *fv = std::getenv("SGW_FORCE_VARIANT")) {
       // "name=i,name=i": pin autotuned kernel variants (testing)
       std::string spec(fv);
@@ -612,13 +613,22 @@ sgw_status sgw_sigma_estimate(sgw_ctx *ctx, const sgw_sigma_params *P, const dou
       void *FA = ctx->buf("f_acc", fbytes).p, *FT = ctx->buf("f_tmp", fbytes).p;
       launch_fill_noise(ctx, d_keys.as<uint64_t>(), nr, F0);
       SGW_HIP(hipEventRecord(ev[1], ctx->stream));
-      // 2. filter, Eq. (3)
-      void *last = cheb_series(ctx, F0, F1, FA, FT, nc, fc, P->emin, P->emax);
+      // 2. filter, Eq. (3), in chunks of vectors whose working set (four
+      // vectors each) can stay in the last-level cache between passes
+      const int64_t fchunk = ctx->filter_chunk > 0 ? std::min<int64_t>(ctx->filter_chunk, nc) : nc;
+      DevBuf &d_n1 = ctx->buf("norm_out", sizeof(double) * nc);
+      for (int64_t c0 = 0; c0 < nc; c0 += fchunk) {
+        const int64_t ncc = std::min(fchunk, nc - c0);
+        const size_t o = cs * N * c0;
+        void *last = cheb_series(ctx, static_cast<char *>(F0) + o, static_cast<char *>(F1) + o,
+                                 static_cast<char *>(FA) + o, static_cast<char *>(FT) + o, ncc, fc,
+                                 P->emin, P->emax);
+        launch_norm2(ctx, last, N, ncc, d_n1.as<double>() + c0);
+      }
       SGW_HIP(hipEventRecord(ev[2], ctx->stream));
       {
         // ||T_n(H~) x|| <= ||x|| = sqrt(2 N) per complex vector of +-1/sqrt(dV)
-        DevBuf &d = ctx->buf("norm_out", sizeof(double) * nc);
-        launch_norm2(ctx, last, N, nc, d.as<double>());
+        DevBuf &d = d_n1;
         std::vector<double> n1(nc);
         SGW_HIP(hipMemcpyAsync(n1.data(), d.p, sizeof(double) * nc, hipMemcpyDeviceToHost, ctx->stream));
         SGW_HIP(hipStreamSynchronize(ctx->stream));

@@ -68,11 +68,10 @@ struct DevBuf {
 };
 
 // ---------------------------------------------------------------- KB tiles
-// Projector data laid out per 8x8x8 grid tile: for each touched tile the list
-// of projectors whose support meets it and their values on the tile's 512
-// points (zero outside the support).
-constexpr int KB_TILE = 8;
-constexpr int KB_TP = KB_TILE * KB_TILE * KB_TILE;  // 512 points per tile
+// Projector data laid out per 512-point grid tile (16 x 8 x 4, or 8 x 8 x 8):
+// for each touched tile the list of projectors whose support meets it and
+// their values on the tile's points (zero outside the support).
+constexpr int KB_TP = 512;  // points per tile
 
 struct KBHost {
   int nproj = 0;
@@ -112,6 +111,7 @@ struct sgw_ctx {
   sgw::DevBuf d_kb_tile_base, d_kb_tile_off, d_kb_entry_proj, d_kb_beta,
       d_kb_proj_off, d_kb_proj_entries, d_kb_ekb;
   int kb_ntile = 0, kb_nentry = 0;
+  int kb_lx = 3, kb_ly = 3;          // tile extent log2 along x and y (512 points)
 
   // launch timer of the inverse plane pass with the Chebyshev epilogue
   bool ktimer = false;
@@ -134,6 +134,7 @@ struct sgw_ctx {
   // variant of one name gives bit-identical results (only speed differs).
   std::map<std::string, int> tuned;
   std::map<std::string, int> forced;   // from SGW_FORCE_VARIANT="name=i,name=i"
+  int64_t filter_chunk = 0;            // vectors per filter chunk (0: the whole batch)
   template <typename F> int tune(const char *name, int64_t nvec, int nvar, F &&trial) {
     const auto fit = forced.find(name);
     if (fit != forced.end() && fit->second >= 0 && fit->second < nvar) return fit->second;

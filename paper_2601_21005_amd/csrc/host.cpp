@@ -24,12 +24,18 @@ void build_kb(sgw_ctx *ctx, const sgw_projectors *P) {
   SGW_REQUIRE(np > 0, SGW_EINVAL, "projectors: no projector");
   SGW_REQUIRE(P->rcut_over_rc > 0 && std::isfinite(P->rcut_over_rc), SGW_EINVAL,
               "projectors: rcut_over_rc must be > 0");
-  SGW_REQUIRE(ctx->nx % KB_TILE == 0 && ctx->ny % KB_TILE == 0 && ctx->nz % KB_TILE == 0,
+  // 512-point tiles: 16 x 8 x 4 (rows of 16 complex = 128 B in FP32) when the
+  // grid allows it, else 8 x 8 x 8
+  int td[3] = {8, 8, 8};
+  if (ctx->nx % 16 == 0 && ctx->ny % 8 == 0 && ctx->nz % 4 == 0) { td[0] = 16; td[1] = 8; td[2] = 4; }
+  SGW_REQUIRE(ctx->nx % td[0] == 0 && ctx->ny % td[1] == 0 && ctx->nz % td[2] == 0,
               SGW_EUNSUPPORTED, "projectors need grid sizes divisible by 8");
+  ctx->kb_lx = td[0] == 16 ? 4 : 3;
+  ctx->kb_ly = 3;
   const int n[3] = {ctx->nx, ctx->ny, ctx->nz};
   const double h = ctx->h;
   const double L[3] = {n[0] * h, n[1] * h, n[2] * h};
-  const int tn[3] = {n[0] / KB_TILE, n[1] / KB_TILE, n[2] / KB_TILE};
+  const int tn[3] = {n[0] / td[0], n[1] / td[1], n[2] / td[2]};
   const int ntile_all = tn[0] * tn[1] * tn[2];
 
   struct Pt { int64_t r; double v; };
@@ -87,8 +93,8 @@ void build_kb(sgw_ctx *ctx, const sgw_projectors *P) {
     const int ix = (int)(r % n[0]);
     const int iy = (int)((r / n[0]) % n[1]);
     const int iz = (int)(r / ((int64_t)n[0] * n[1]));
-    local = (ix % KB_TILE) + KB_TILE * ((iy % KB_TILE) + KB_TILE * (iz % KB_TILE));
-    return (ix / KB_TILE) + tn[0] * ((iy / KB_TILE) + tn[1] * (iz / KB_TILE));
+    local = (ix % td[0]) + td[0] * ((iy % td[1]) + td[1] * (iz % td[2]));
+    return (ix / td[0]) + tn[0] * ((iy / td[1]) + tn[1] * (iz / td[2]));
   };
   // projector lists per tile (ascending projector ids)
   std::vector<std::vector<int>> tproj(ntile_all);
@@ -111,7 +117,7 @@ void build_kb(sgw_ctx *ctx, const sgw_projectors *P) {
     if (tproj[t].empty()) continue;
     tile_index[t] = (int)kb.tile_base.size();
     const int tx = t % tn[0], ty = (t / tn[0]) % tn[1], tz = t / (tn[0] * tn[1]);
-    kb.tile_base.push_back(tx * KB_TILE + n[0] * (ty * KB_TILE + n[1] * tz * KB_TILE));
+    kb.tile_base.push_back(tx * td[0] + n[0] * (ty * td[1] + n[1] * tz * td[2]));
     for (int p : tproj[t]) kb.entry_proj.push_back(p);
     kb.tile_off.push_back((int)kb.entry_proj.size());
   }

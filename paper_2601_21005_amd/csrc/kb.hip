@@ -21,8 +21,10 @@ template <typename R> struct KBV;
 template <> struct KBV<float> { static constexpr int NV = 8; };
 template <> struct KBV<double> { static constexpr int NV = 4; };
 
-__device__ __forceinline__ int64_t tile_point(int base, int p, int nx, int ny) {
-  return (int64_t)base + (p & 7) + (int64_t)nx * (((p >> 3) & 7) + (int64_t)ny * (p >> 6));
+// flat grid index of point p of a tile whose x and y extents are 2^lx, 2^ly
+__device__ __forceinline__ int64_t tile_point(int base, int p, int nx, int ny, int lx, int ly) {
+  const int x = p & ((1 << lx) - 1), y = (p >> lx) & ((1 << ly) - 1), z = p >> (lx + ly);
+  return (int64_t)base + x + (int64_t)nx * (y + (int64_t)ny * z);
 }
 
 template <typename T> __device__ __forceinline__ T wsum(T v) {
@@ -34,7 +36,7 @@ template <typename R>
 __global__ __launch_bounds__(NTK) void k_kb_gather(const cplx<R> *psi, int64_t ld, int64_t nvec,
                                                    const int *tile_base, const int *tile_off,
                                                    const R *beta, cplx<R> *partial, int nx,
-                                                   int ny, R dV) {
+                                                   int ny, int lx, int ly, R dV) {
   constexpr int NV = KBV<R>::NV;
   using C = cplx<R>;
   __shared__ C s[KB_TP * NV];
@@ -44,7 +46,7 @@ __global__ __launch_bounds__(NTK) void k_kb_gather(const cplx<R> *psi, int64_t l
   for (int idx = threadIdx.x; idx < KB_TP * NV; idx += NTK) {
     const int vl = idx / KB_TP, p = idx % KB_TP;
     C val = cmake<C>(0, 0);
-    if (v0 + vl < nvec) val = psi[(v0 + vl) * ld + tile_point(base, p, nx, ny)];
+    if (v0 + vl < nvec) val = psi[(v0 + vl) * ld + tile_point(base, p, nx, ny, lx, ly)];
     s[p * NV + vl] = val;
   }
   __syncthreads();
@@ -117,7 +119,7 @@ __global__ __launch_bounds__(NTK) void k_kb_scatter(const cplx<R> *coef, int64_t
                                                     const int *entry_proj, const R *beta,
                                                     cplx<R> *dst, int64_t ld, R s1r, R s1i,
                                                     cplx<R> *dst2, R s2r, R s2i, int nx,
-                                                    int ny) {
+                                                    int ny, int lx, int ly) {
   constexpr int NV = KBV<R>::NV;
   using C = cplx<R>;
   __shared__ C c[KB_MAXE * NV];
@@ -145,7 +147,7 @@ __global__ __launch_bounds__(NTK) void k_kb_scatter(const cplx<R> *coef, int64_t
         ai[vl] += bv * x.y;
       }
     }
-    const int64_t r = tile_point(base, p, nx, ny);
+    const int64_t r = tile_point(base, p, nx, ny, lx, ly);
 #pragma unroll
     for (int vl = 0; vl < NV; ++vl) {
       if (v0 + vl >= nvec) break;
@@ -182,8 +184,8 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 template <int NVB, int MT>
 __global__ __launch_bounds__(NTK) void k_kb_gather_mfma(
     const float2 *psi, int64_t ld, int64_t nvec, const int *tile_base, const int *tile_off,
-    const float *beta, float2 *partial, int nx, int ny, float dV) {
-  constexpr int COLS = 2 * NVB, NTL = NVB / 8;
+    const float *beta, float2 *partial, int nx, int ny, int lx, int ly, float dV) {
+  constexpr int COLS = 2 * NVB + 1, NTL = NVB / 8;   // padded pitch: no bank conflicts
   static_assert(4 * MT * NTL * 256 <= KB_TP * COLS, "reduction buffer exceeds the Psi tile");
   __shared__ float sp[KB_TP * COLS];               // Psi tile [p][j], then the reduction
   const int t = blockIdx.y;
@@ -196,7 +198,7 @@ __global__ __launch_bounds__(NTK) void k_kb_gather_mfma(
     for (int idx = tid; idx < KB_TP * NVB; idx += NTK) {
       const int vl = idx / KB_TP, p = idx % KB_TP;
       float2 val = make_float2(0.f, 0.f);
-      if (v0 + vl < nvec) val = psi[(v0 + vl) * ld + tile_point(base, p, nx, ny)];
+      if (v0 + vl < nvec) val = psi[(v0 + vl) * ld + tile_point(base, p, nx, ny, lx, ly)];
       sp[p * COLS + 2 * vl] = val.x;
       sp[p * COLS + 2 * vl + 1] = val.y;
     }
@@ -206,6 +208,7 @@ __global__ __launch_bounds__(NTK) void k_kb_gather_mfma(
     for (int j = 0; j < MT; ++j)
 #pragma unroll
       for (int n = 0; n < NTL; ++n) acc[j][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
     for (int k0 = 128 * w; k0 < 128 * w + 128; k0 += 16) {
       const int kq = k0 + 4 * q;                     // this lane's 4 K slots
       float b[NTL][4];
@@ -258,8 +261,8 @@ template <int NVB>
 __global__ __launch_bounds__(NTK) void k_kb_scatter_mfma(
     const float2 *coef, int64_t nvec, const int *tile_base, const int *tile_off,
     const int *entry_proj, const float *beta, float2 *dst, int64_t ld, float s1, int nx,
-    int ny) {
-  constexpr int COLS = 2 * NVB, NTL = NVB / 8;
+    int ny, int lx, int ly) {
+  constexpr int COLS = 2 * NVB + 1, NTL = NVB / 8;
   constexpr int SC = KB_MAXE * COLS > KB_TP * COLS ? KB_MAXE * COLS : KB_TP * COLS;
   __shared__ float sm[SC];                         // C' [e][j], then D staging [p][j]
   const int t = blockIdx.y;
@@ -283,20 +286,28 @@ __global__ __launch_bounds__(NTK) void k_kb_scatter_mfma(
   for (int j = 0; j < 8; ++j)
 #pragma unroll
     for (int n = 0; n < NTL; ++n) acc[j][n] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < nek; k0 += 4) {
+  // K loop with the next step's operands loaded ahead of this step's MFMAs
+  float a_cur[8], a_nxt[8], b_cur[NTL], b_nxt[NTL];
+  auto load_step = [&](int k0, float *a, float *b) {
     const int e = k0 + q;                          // this lane's K slot
-    float b[NTL];
 #pragma unroll
     for (int n = 0; n < NTL; ++n) b[n] = sm[e * COLS + 16 * n + col];
     const float *brow = beta + (int64_t)(off + (e < ne ? e : 0)) * KB_TP;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int p = 16 * (8 * w + j) + col;        // A row = point
-      const float a = e < ne ? brow[p] : 0.f;
+    for (int j = 0; j < 8; ++j) a[j] = e < ne ? brow[16 * (8 * w + j) + col] : 0.f;  // A row = point
+  };
+  load_step(0, a_cur, b_cur);
+  for (int k0 = 0; k0 < nek; k0 += 4) {
+    if (k0 + 4 < nek) load_step(k0 + 4, a_nxt, b_nxt);
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
 #pragma unroll
       for (int n = 0; n < NTL; ++n)
-        acc[j][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[n], acc[j][n], 0, 0, 0);
-    }
+        acc[j][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_cur[j], b_cur[n], acc[j][n], 0, 0, 0);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) a_cur[j] = a_nxt[j];
+#pragma unroll
+    for (int n = 0; n < NTL; ++n) b_cur[n] = b_nxt[n];
   }
   __syncthreads();                                 // C' no longer needed
 #pragma unroll
@@ -312,7 +323,7 @@ __global__ __launch_bounds__(NTK) void k_kb_scatter_mfma(
   for (int idx = tid; idx < KB_TP * NVB; idx += NTK) {
     const int vl = idx / KB_TP, p = idx % KB_TP;
     if (v0 + vl >= nvec) continue;
-    float2 *d = dst + (v0 + vl) * ld + tile_point(base, p, nx, ny);
+    float2 *d = dst + (v0 + vl) * ld + tile_point(base, p, nx, ny, lx, ly);
     float2 o = *d;
     o.x += s1 * sm[p * COLS + 2 * vl];
     o.y += s1 * sm[p * COLS + 2 * vl + 1];
@@ -328,9 +339,9 @@ constexpr int NGATHER = 6, NSCATTER = 2;
 
 static void launch_gather_variant(int vi, dim3 g, hipStream_t st, const float2 *psi, int64_t ld,
                                   int64_t nvec, const int *tb, const int *to, const float *beta,
-                                  float2 *partial, int nx, int ny, float dV) {
+                                  float2 *partial, int nx, int ny, int lx, int ly, float dV) {
   switch (vi) {
-#define SGW_G(I, A, B) case I: hipLaunchKernelGGL((k_kb_gather_mfma<A, B>), g, dim3(NTK), 0, st, psi, ld, nvec, tb, to, beta, partial, nx, ny, dV); break;
+#define SGW_G(I, A, B) case I: hipLaunchKernelGGL((k_kb_gather_mfma<A, B>), g, dim3(NTK), 0, st, psi, ld, nvec, tb, to, beta, partial, nx, ny, lx, ly, dV); break;
     SGW_G(0, 8, 2) SGW_G(1, 8, 4) SGW_G(2, 8, 8) SGW_G(3, 16, 2) SGW_G(4, 16, 4) SGW_G(5, 16, 8)
 #undef SGW_G
   }
@@ -339,13 +350,13 @@ static void launch_gather_variant(int vi, dim3 g, hipStream_t st, const float2 *
 static void launch_scatter_variant(int vi, dim3 g, hipStream_t st, const float2 *coef,
                                    int64_t nvec, const int *tb, const int *to, const int *ep,
                                    const float *beta, float2 *dst, int64_t ld, float s1, int nx,
-                                   int ny) {
+                                   int ny, int lx, int ly) {
   if (vi == 0)
     hipLaunchKernelGGL((k_kb_scatter_mfma<8>), g, dim3(NTK), 0, st, coef, nvec, tb, to, ep, beta,
-                       dst, ld, s1, nx, ny);
+                       dst, ld, s1, nx, ny, lx, ly);
   else
     hipLaunchKernelGGL((k_kb_scatter_mfma<16>), g, dim3(NTK), 0, st, coef, nvec, tb, to, ep, beta,
-                       dst, ld, s1, nx, ny);
+                       dst, ld, s1, nx, ny, lx, ly);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -363,7 +374,7 @@ static void gather_t(sgw_ctx *ctx, const void *psi, int64_t nvec, int64_t ld, vo
                             static_cast<const float2 *>(psi), ld, nvec,
                             ctx->d_kb_tile_base.as<int>(), ctx->d_kb_tile_off.as<int>(),
                             ctx->d_kb_beta.as<float>(), reinterpret_cast<float2 *>(partial),
-                            ctx->nx, ctx->ny, (float)ctx->dV);
+                            ctx->nx, ctx->ny, ctx->kb_lx, ctx->kb_ly, (float)ctx->dV);
     };
     run(ctx->tune("kb_gather", nvec, NGATHER, run));   // the gather overwrites: trials are harmless
   } else {
@@ -371,7 +382,7 @@ static void gather_t(sgw_ctx *ctx, const void *psi, int64_t nvec, int64_t ld, vo
     hipLaunchKernelGGL(k_kb_gather<R>, dim3(nvb, ctx->kb_ntile), dim3(NTK), 0, ctx->stream,
                        static_cast<const C *>(psi), ld, nvec, ctx->d_kb_tile_base.as<int>(),
                        ctx->d_kb_tile_off.as<int>(), ctx->d_kb_beta.as<R>(), partial, ctx->nx,
-                       ctx->ny, (R)ctx->dV);
+                       ctx->ny, ctx->kb_lx, ctx->kb_ly, (R)ctx->dV);
   }
   SGW_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_kb_reduce<R>, dim3((nvec + NTK - 1) / NTK, ctx->kb.nproj), dim3(NTK), 0,
@@ -419,7 +430,8 @@ static void scatter_t(sgw_ctx *ctx, const void *coef, int64_t nvec, void *dst, i
                                static_cast<const float2 *>(coef), nvec,
                                ctx->d_kb_tile_base.as<int>(), ctx->d_kb_tile_off.as<int>(),
                                ctx->d_kb_entry_proj.as<int>(), ctx->d_kb_beta.as<float>(),
-                               static_cast<float2 *>(dst), ld, (float)s1re, ctx->nx, ctx->ny);
+                               static_cast<float2 *>(dst), ld, (float)s1re, ctx->nx, ctx->ny,
+                               ctx->kb_lx, ctx->kb_ly);
       };
       // trials add 0 * (B C) to dst, which leaves it unchanged
       const int vi = ctx->tune("kb_scatter", nvec, NSCATTER, [&](int i) {
@@ -428,7 +440,8 @@ static void scatter_t(sgw_ctx *ctx, const void *coef, int64_t nvec, void *dst, i
                                static_cast<const float2 *>(coef), nvec,
                                ctx->d_kb_tile_base.as<int>(), ctx->d_kb_tile_off.as<int>(),
                                ctx->d_kb_entry_proj.as<int>(), ctx->d_kb_beta.as<float>(),
-                               static_cast<float2 *>(dst), ld, 0.0f, ctx->nx, ctx->ny);
+                               static_cast<float2 *>(dst), ld, 0.0f, ctx->nx, ctx->ny,
+                               ctx->kb_lx, ctx->kb_ly);
       });
       run(vi);
       SGW_HIP(hipGetLastError());
@@ -440,7 +453,8 @@ static void scatter_t(sgw_ctx *ctx, const void *coef, int64_t nvec, void *dst, i
                      static_cast<const C *>(coef), nvec, ctx->d_kb_tile_base.as<int>(),
                      ctx->d_kb_tile_off.as<int>(), ctx->d_kb_entry_proj.as<int>(),
                      ctx->d_kb_beta.as<R>(), static_cast<C *>(dst), ld, (R)s1re, (R)s1im,
-                     static_cast<C *>(dst2), (R)s2re, (R)s2im, ctx->nx, ctx->ny);
+                     static_cast<C *>(dst2), (R)s2re, (R)s2im, ctx->nx, ctx->ny, ctx->kb_lx,
+                     ctx->kb_ly);
   SGW_HIP(hipGetLastError());
 }
 
