@@ -205,3 +205,26 @@ def tiny_system(n=8, h=0.7, with_kb=True, n_occ=2):
                              rc=np.array([0.75, 0.8]), ekb=np.array([-1.5, 0.8]),
                              rcut_over_rc=3.0)
     return System("tiny", g, v, proj, n_occ=n_occ, pos=centres)
+
+
+# ------------------------------------------------------------------ MLP inputs
+MLP_SIZES = (64, 256, 256)          # features -> hidden -> hidden (-> 1)
+
+
+def mlp_param_count(din=64, h1=256, h2=256):
+    return h1 * din + h1 + h2 * h1 + h2 + h2 + 1
+
+
+def mlp_init(seed=7, din=64, h1=256, h2=256):
+    """Seeded initial parameters of the control-variate network, packed as
+    W1 [h1][din], b1 [h1], W2 [h2][h1], b2 [h2], w3 [h2], b3 (FP64): uniform
+    +-sqrt(6 / (fan_in + fan_out)) weights (Glorot), zero biases."""
+    rs = np.random.default_rng(seed)
+
+    def glorot(fo, fi):
+        a = np.sqrt(6.0 / (fi + fo))
+        return rs.uniform(-a, a, size=(fo, fi))
+
+    parts = [glorot(h1, din).ravel(), np.zeros(h1), glorot(h2, h1).ravel(), np.zeros(h2),
+             glorot(1, h2).ravel(), np.zeros(1)]
+    return np.concatenate(parts)
