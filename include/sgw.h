@@ -51,7 +51,9 @@ typedef enum {
 typedef enum {
   SGW_C128 = 0,           /* complex double throughout */
   SGW_C64 = 1,            /* complex float; FP64 coefficients and sums */
-  SGW_C64_BF16KB = 2      /* as SGW_C64 (BF16 projector GEMMs: not built yet) */
+  SGW_C64_BF16KB = 2      /* as SGW_C64, but the projector GEMMs take their operands
+                           * (beta, psi, the mixed coefficients) rounded to BF16
+                           * (nearest even) with FP32 accumulation on MFMA */
 } sgw_precision;
 
 /* Grid (Eq. 1 on a Fourier grid, Sec. 2.2).  ecut > 0 clips the kinetic
@@ -250,6 +252,87 @@ sgw_status sgw_sigma_omega(const double *sigma_t, int32_t n_tau, double dt, doub
 sgw_status sgw_kernel_timer(sgw_ctx *ctx, int32_t enable);
 sgw_status sgw_kernel_timer_read(sgw_ctx *ctx, double *total_ms, int64_t *launches,
                                  int64_t *points);
+
+
+/* ---------------------------------------------------------------------------
+ * Learned control variate (an addition to the paper's Monte Carlo average,
+ * Sec. 3: samples are averaged until the QP error bar is below 0.03 eV).
+ * Per sample i, y_i = X_i + Re Sigma_c,i(omega) enters the QP equation
+ * (Eq. 6) linearly.  A network g(x_i) of cheap features x_i of the same white
+ * noise zeta_i, fitted to y on a set A, gives the estimate
+ *   mean_B(y - c g) + c mean_M(g),  c = Cov_A(y, g) / Var_A(g),
+ * over an evaluation set B and M cheap samples (features only).  All
+ * products run on MFMA with BF16 operands and FP32 accumulation.
+ * ------------------------------------------------------------------------- */
+
+/* Features x[i][k] = |<phi_k|zeta_i>|^2 for samples i = first_sample ..
+ * first_sample + nsamp - 1, zeta_i the white noise of Monte Carlo sample i
+ * (the zeta-bar stream that sgw_sigma_estimate draws for that sample).
+ * phi: device float [K][ld_phi] real orbitals (1 <= K <= 64, ld_phi >= N),
+ * rounded to BF16 on the device; x: device float [nsamp][K].  The sample
+ * indices must lie in [0, 2^20); N must be divisible by 64 (else
+ * SGW_EUNSUPPORTED).  Asynchronous on the context's stream. */
+sgw_status sgw_cv_features(sgw_ctx *ctx, const float *phi, int32_t K, int64_t ld_phi,
+                           uint64_t seed, int64_t first_sample, int64_t nsamp, float *x);
+
+/* The network g(x) = w3 . tanh(W2 tanh(W1 xh + b1) + b2) + b3 with
+ * xh = (x - mean) / std.  Parameters are packed W1 [h1][din], b1 [h1],
+ * W2 [h2][h1], b2 [h2], w3 [h2], b3 [1]; the library keeps FP32 master
+ * copies, Adam moments and a gradient on the device.  theta0: host FP64
+ * initial parameters (copied).  Work is enqueued on hip_stream (NULL: the
+ * default stream).  The standardization starts as mean 0, std 1. */
+typedef struct sgw_mlp sgw_mlp;
+sgw_status sgw_mlp_create(int32_t din, int32_t h1, int32_t h2, const double *theta0,
+                          void *hip_stream, sgw_mlp **out);
+void sgw_mlp_destroy(sgw_mlp *mlp);
+const char *sgw_mlp_last_error(const sgw_mlp *mlp);   /* NULL: last create failure */
+/* mean, std: host FP64 [din], std > 0 (synchronous) */
+sgw_status sgw_mlp_set_standardization(sgw_mlp *mlp, const double *mean, const double *std);
+/* theta: host FP64 [nparam] <- the FP32 master parameters (synchronous) */
+sgw_status sgw_mlp_get_params(sgw_mlp *mlp, double *theta);
+/* g: device float [n] <- network(x), x: device float [n][din] (asynchronous) */
+sgw_status sgw_mlp_forward(sgw_mlp *mlp, const float *x, int64_t n, float *g);
+/* Mean squared error L = (1/n) sum (g(x_i) - y_i)^2 (host *loss) and its
+ * gradient (host FP64 [nparam], also kept on the device for sgw_mlp_adam);
+ * x: device [n][din], y: device [n] (synchronous). */
+sgw_status sgw_mlp_gradient(sgw_mlp *mlp, const float *x, const float *y, int64_t n,
+                            double *loss, double *grad);
+/* One Adam step (bias-corrected moments) with the device gradient of the
+ * last sgw_mlp_gradient / training step, or with the host FP64 gradient
+ * `grad` when it is not NULL. */
+sgw_status sgw_mlp_adam(sgw_mlp *mlp, const double *grad, double lr, double b1, double b2,
+                        double eps);
+/* `steps` full-batch steps (forward, gradient, Adam with b1 = 0.9,
+ * b2 = 0.999, eps = 1e-8) on device data x [n][din], y [n], all on the
+ * device; loss_hist (host [steps] or NULL) receives the loss before each
+ * step (synchronous when loss_hist is given). */
+sgw_status sgw_mlp_train(sgw_mlp *mlp, const float *x, const float *y, int64_t n,
+                         int32_t steps, double lr, double *loss_hist);
+/* Mean and sample variance (FP64) of g over the cheap samples first_sample
+ * .. first_sample + count - 1: features and network in chunks of `chunk`
+ * samples on the context's stream, which must be the network's stream.
+ * K must equal the network's din. Synchronous. */
+sgw_status sgw_cv_cheap_moments(sgw_ctx *ctx, sgw_mlp *mlp, const float *phi, int32_t K,
+                                int64_t ld_phi, uint64_t seed, int64_t first_sample,
+                                int64_t count, int64_t chunk, double *mean, double *var);
+
+typedef struct {
+  double estimate;        /* the control-variate estimate, or the plain one on fallback */
+  double sigma;           /* its standard error */
+  double c;               /* Cov_A(y, g) / Var_A(g) */
+  double rho2;            /* squared correlation of y and g on A */
+  double plain;           /* mean of y over A and B */
+  double sigma_plain;     /* its standard error */
+  double sigma_cv;        /* standard error of the control-variate form */
+  int32_t fallback;       /* 1: |cv - plain| > 3 sqrt(sigma_cv^2 + sigma_plain^2) */
+} sgw_cv_result;
+
+/* Host FP64: the estimator above from per-sample y, g on A (nA >= 2) and B
+ * (nB >= 2) and the mean and variance of g over M >= 2 cheap samples.
+ * Sample variances use n - 1. */
+sgw_status sgw_cv_estimate(const double *yA, const double *gA, int64_t nA, const double *yB,
+                           const double *gB, int64_t nB, double gM_mean, double gM_var,
+                           int64_t M, sgw_cv_result *out);
 
 #ifdef __cplusplus
 }

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libsgw.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["fft.hip", "elem.hip", "kb.hip", "api.hip", "host.cpp"]
+SOURCES = ["fft.hip", "elem.hip", "kb.hip", "cv.hip", "api.hip", "host.cpp"]
 
 
 def hipcc():

@@ -305,6 +305,7 @@ sgw_status sgw_create(const sgw_grid *grid, const double *v_loc, const sgw_proje
       upload(c->d_kb_proj_entries, c->kb.proj_entries.data(), c->kb.proj_entries.size());
       upload(c->d_kb_ekb, c->kb.ekb.data(), c->kb.ekb.size());
       upload_real(c.get(), c->d_kb_beta, c->kb.beta.data(), c->kb.beta.size());
+      if (!c->dbl) kb_upload_operands(c.get());
     }
     ctx = c.release();
   });

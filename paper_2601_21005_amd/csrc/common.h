@@ -110,6 +110,9 @@ struct sgw_ctx {
   sgw::DevBuf d_tw;                  // twiddles nx, ny, nz (C), forward sign
   sgw::DevBuf d_kb_tile_base, d_kb_tile_off, d_kb_entry_proj, d_kb_beta,
       d_kb_proj_off, d_kb_proj_entries, d_kb_ekb;
+  sgw::DevBuf d_kb_tile_offT;        // [ntile + 1] per-tile offsets of betaT in entry rows
+  sgw::DevBuf d_kb_betaT;            // per tile [512][entries padded to 32], FP32 or BF16
+  sgw::DevBuf d_kb_beta16;           // [entry][512] BF16 (SGW_C64_BF16KB)
   int kb_ntile = 0, kb_nentry = 0;
   int kb_lx = 3, kb_ly = 3;          // tile extent log2 along x and y (512 points)
 
@@ -218,8 +221,12 @@ void kb_gather_e(sgw_ctx *ctx, const void *psi, int64_t nvec, int64_t ld, void *
 void kb_mix_dense(sgw_ctx *ctx, const void *K, const void *coef_in, void *coef_out,
                   int64_t nvec);
 // dst[v] += s1 * B C[v];  if dst2: dst2[v] += s2 * B C[v]  (s1, s2 complex)
+// (the MFMA kernels of the complex FP32 precisions take s1 real and no dst2)
 void kb_scatter(sgw_ctx *ctx, const void *coef, int64_t nvec, void *dst, int64_t ld,
                 double s1re, double s1im, void *dst2, double s2re, double s2im);
+
+// operand arrays of the MFMA kernels (after build_kb and the upload of beta)
+void kb_upload_operands(sgw_ctx *ctx);
 
 // host utilities (host.cpp)
 void build_kb(sgw_ctx *ctx, const sgw_projectors *p);

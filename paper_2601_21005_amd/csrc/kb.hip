@@ -1,6 +1,7 @@
 // Kleinman-Bylander projector contraction (the separable pseudopotential
 // part, applied in the paper with atomic adds where neighbouring projector
-// spheres overlap, Sec. 3).  Here the work is owned by 8x8x8 grid tiles:
+// spheres overlap, Sec. 3).  Here the work is owned by 512-point grid tiles
+// (16 x 8 x 4 where the grid allows it, else 8 x 8 x 8):
 //   gather   partial[e][v] = dV sum_{r in tile} beta_e(r) psi_v(r)   per
 //            (tile, projector) entry e -- the tile of NV vectors sits in LDS;
 //   reduce   C[p][v] = sum of the partials of projector p, in a fixed order
@@ -167,196 +168,340 @@ __global__ __launch_bounds__(NTK) void k_kb_scatter(const cplx<R> *coef, int64_t
   }
 }
 
-// ---------------------------------------------------------------- MFMA (FP32)
-// Per tile the gather is the GEMM  C[e][j] = sum_p beta[e][p] Psi[p][j]
+// ---------------------------------------------------------------- MFMA
+// Per tile the gather is the GEMM  D[e][c] = sum_p beta[e][p] Psi[p][c]
 // (M = projector entries, K = 512 points, N = 2 NVB real columns = NVB
-// complex vectors) and the scatter  D[p][j] = sum_e beta[e][p] C'[e][j]
-// (M = 512 points, K = entries).  Both run on v_mfma_f32_16x16x4f32: lane l
-// supplies A[l % 16][k] and B[k][l % 16] for the lane's K slot k, and holds
-// D[4 (l / 16) + r][l % 16] in accumulator register r.  Within a group of 4
-// MFMA steps lane l takes the K slots 4 (l / 16) + s, s = 0..3, so that its
-// four A values are 16 contiguous bytes.  The four waves of a workgroup split
-// K (the gather: 128 points each, summed in wave order) or M (the scatter), so
-// every variant below adds the same products in the same order: the choice of
-// NVB and MT changes the speed, not a single bit of the result.
+// complex vectors) and the scatter  D[p][c] = sum_e beta[e][p] C'[e][c]
+// (M = 512 points, K = entries padded to 32).  The operands are stored in
+// FP32 (SGW_C64) or in BF16 rounded to nearest even (SGW_C64_BF16KB); the
+// accumulation is FP32 either way.  A lane feeds 16 contiguous bytes of A and
+// of B per group of K values:
+//   FP32: four v_mfma_f32_16x16x4f32, K group 16, lane l holds the K slots
+//         4 (l / 16) + s, s = 0..3, one per instruction;
+//   BF16: one v_mfma_f32_16x16x32_bf16, K group 32, lane l holds the K slots
+//         8 (l / 16) + s, s = 0..7;
+// lane l supplies row l % 16 of A and column l % 16 of B and receives
+// D[4 (l / 16) + r][l % 16] in accumulator register r.  Every variant below
+// (vectors per workgroup NVB, entry tiles per pass MT) computes each output
+// with the same instructions in the same order, so the choice changes the
+// speed, not a bit of the result.
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-template <int NVB, int MT>
-__global__ __launch_bounds__(NTK) void k_kb_gather_mfma(
+// float -> bfloat16 bits, round to nearest even (finite inputs)
+__host__ __device__ __forceinline__ uint32_t bf16_bits(float f) {
+  uint32_t u;
+  __builtin_memcpy(&u, &f, 4);
+  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+
+struct OpF32 {
+  using T = float;
+  static constexpr int GK = 16;
+  __device__ static void mma(f32x4 &acc, const u32x4 &a, const u32x4 &b) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a[0]), __uint_as_float(b[0]), acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a[1]), __uint_as_float(b[1]), acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a[2]), __uint_as_float(b[2]), acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a[3]), __uint_as_float(b[3]), acc, 0, 0, 0);
+  }
+  __device__ static void put2(T *d, float x, float y) {
+    *reinterpret_cast<float2 *>(d) = make_float2(x, y);
+  }
+  __device__ static void put1(T *d, float x) { *d = x; }
+};
+
+struct OpBF16 {
+  using T = uint16_t;
+  static constexpr int GK = 32;
+  __device__ static void mma(f32x4 &acc, const u32x4 &a, const u32x4 &b) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                  __builtin_bit_cast(bf16x8, b), acc, 0, 0, 0);
+  }
+  __device__ static void put2(T *d, float x, float y) {
+    *reinterpret_cast<uint32_t *>(d) = bf16_bits(x) | (bf16_bits(y) << 16);
+  }
+  __device__ static void put1(T *d, float x) { *d = (uint16_t)bf16_bits(x); }
+};
+
+template <class T> __device__ __forceinline__ u32x4 ld16(const T *p) {
+  return *reinterpret_cast<const u32x4 *>(p);
+}
+
+// partial[off + e][v] = dV sum_p beta_e(p) psi_v(p) for the entries e of tile t
+template <class Op, int NVB, int MT>
+__global__ __launch_bounds__(NTK) void k_kb_gather_mma(
     const float2 *psi, int64_t ld, int64_t nvec, const int *tile_base, const int *tile_off,
-    const float *beta, float2 *partial, int nx, int ny, int lx, int ly, float dV) {
-  constexpr int COLS = 2 * NVB + 1, NTL = NVB / 8;   // padded pitch: no bank conflicts
-  static_assert(4 * MT * NTL * 256 <= KB_TP * COLS, "reduction buffer exceeds the Psi tile");
-  __shared__ float sp[KB_TP * COLS];               // Psi tile [p][j], then the reduction
+    const typename Op::T *beta, float2 *partial, int nx, int ny, int lx, int ly, float dV) {
+  using T = typename Op::T;
+  constexpr int NC = 2 * NVB, NTL = NC / 16;
+  constexpr int EL = 16 / (int)sizeof(T);           // operand elements per lane per group
+  constexpr int PITCH = KB_TP + EL;                 // 16 B of padding: conflict-free 16 B reads
+  constexpr int NG = 128 / Op::GK;                  // K groups of one wave (128 points)
+  static_assert(4 * MT * NTL * 256 * 4 <= NC * PITCH * (int)sizeof(T),
+                "cross-wave sums exceed the tile buffer");
+  __shared__ __align__(16) T sp[NC * PITCH];       // Psi tile [column][point], then the sums
   const int t = blockIdx.y;
   const int64_t v0 = (int64_t)blockIdx.x * NVB;
   const int base = tile_base[t];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, q = lane >> 4, col = lane & 15;
   const int off = tile_off[t], ne = tile_off[t + 1] - off;
-  const int q = lane >> 4, col = lane & 15;
-  for (int mg = 0; mg < ne; mg += 16 * MT) {
-    for (int idx = tid; idx < KB_TP * NVB; idx += NTK) {
-      const int vl = idx / KB_TP, p = idx % KB_TP;
-      float2 val = make_float2(0.f, 0.f);
-      if (v0 + vl < nvec) val = psi[(v0 + vl) * ld + tile_point(base, p, nx, ny, lx, ly)];
-      sp[p * COLS + 2 * vl] = val.x;
-      sp[p * COLS + 2 * vl + 1] = val.y;
+  {
+    // thread tid owns the tile points 2 tid and 2 tid + 1 (neighbours along x):
+    // every load of the NVB vectors is issued before the first store
+    const int64_t r0 = tile_point(base, 2 * tid, nx, ny, lx, ly);
+    float2 v[NVB][2];
+#pragma unroll
+    for (int vl = 0; vl < NVB; ++vl) {
+      if (v0 + vl < nvec) {
+        const float2 *s = psi + (v0 + vl) * ld + r0;
+        v[vl][0] = s[0];
+        v[vl][1] = s[1];
+      } else {
+        v[vl][0] = v[vl][1] = make_float2(0.f, 0.f);
+      }
     }
-    __syncthreads();
+#pragma unroll
+    for (int vl = 0; vl < NVB; ++vl) {
+      Op::put2(sp + (2 * vl) * PITCH + 2 * tid, v[vl][0].x, v[vl][1].x);
+      Op::put2(sp + (2 * vl + 1) * PITCH + 2 * tid, v[vl][0].y, v[vl][1].y);
+    }
+  }
+  __syncthreads();
+  // B operands of this wave's quarter of K, kept in registers for all entries
+  u32x4 b[NG][NTL];
+#pragma unroll
+  for (int g = 0; g < NG; ++g)
+#pragma unroll
+    for (int n = 0; n < NTL; ++n)
+      b[g][n] = ld16(sp + (16 * n + col) * PITCH + 128 * w + g * Op::GK + EL * q);
+  float *red = reinterpret_cast<float *>(sp);       // [w][j][n][lane][4]
+  for (int mg = 0; mg < ne; mg += 16 * MT) {
     f32x4 acc[MT][NTL];
 #pragma unroll
     for (int j = 0; j < MT; ++j)
 #pragma unroll
       for (int n = 0; n < NTL; ++n) acc[j][n] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 2
-    for (int k0 = 128 * w; k0 < 128 * w + 128; k0 += 16) {
-      const int kq = k0 + 4 * q;                     // this lane's 4 K slots
-      float b[NTL][4];
 #pragma unroll
-      for (int n = 0; n < NTL; ++n)
-#pragma unroll
-        for (int s4 = 0; s4 < 4; ++s4) b[n][s4] = sp[(kq + s4) * COLS + 16 * n + col];
+    for (int g = 0; g < NG; ++g) {
+      u32x4 a[MT];
 #pragma unroll
       for (int j = 0; j < MT; ++j) {
-        if (mg + 16 * j < ne) {
-          const int e = mg + 16 * j + col;           // A row = lane % 16
-          f32x4 a = f32x4{0.f, 0.f, 0.f, 0.f};
-          if (e < ne) a = *reinterpret_cast<const f32x4 *>(beta + (int64_t)(off + e) * KB_TP + kq);
-#pragma unroll
-          for (int n = 0; n < NTL; ++n)
-#pragma unroll
-            for (int s4 = 0; s4 < 4; ++s4)
-              acc[j][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s4], b[n][s4], acc[j][n], 0, 0, 0);
-        }
+        const int e = mg + 16 * j + col;            // A row = lane % 16
+        a[j] = u32x4{0u, 0u, 0u, 0u};
+        if (e < ne) a[j] = ld16(beta + (int64_t)(off + e) * KB_TP + 128 * w + g * Op::GK + EL * q);
       }
+#pragma unroll
+      for (int j = 0; j < MT; ++j)
+        if (mg + 16 * j < ne)
+#pragma unroll
+          for (int n = 0; n < NTL; ++n) Op::mma(acc[j][n], a[j], b[g][n]);
     }
-    __syncthreads();                                 // every wave is done with Psi
-    float *red = sp;                                 // [w][j][n][lane][4]
+    __syncthreads();                                // B operands loaded / last sums read
 #pragma unroll
     for (int j = 0; j < MT; ++j)
 #pragma unroll
       for (int n = 0; n < NTL; ++n)
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          red[(((w * MT + j) * NTL + n) * 64 + lane) * 4 + r] = acc[j][n][r];
+        *reinterpret_cast<f32x4 *>(red + (((w * MT + j) * NTL + n) * 64 + lane) * 4) = acc[j][n];
     __syncthreads();
-    for (int o = tid; o < MT * NTL * 256; o += NTK) {
-      const int jn = o / 256, l = (o / 4) % 64, r = o % 4;
-      const int j = jn / NTL, n = jn % NTL;
-      const int e = mg + 16 * j + 4 * (l >> 4) + r;  // D row
-      const int c = 16 * n + (l & 15);               // D column
-      float sum = 0.f;
+    // the four K quarters summed in wave order; one complex (entry, vector) per item
+    for (int o = tid; o < MT * 16 * NVB; o += NTK) {
+      const int j = o / (16 * NVB), er = (o / NVB) % 16, vl = o % NVB;
+      const int e = mg + 16 * j + er;
+      const int n = vl >> 3, lre = 16 * (er >> 2) + 2 * (vl & 7), r = er & 3;
+      float re = 0.f, im = 0.f;
 #pragma unroll
-      for (int ww = 0; ww < 4; ++ww) sum += red[(((ww * MT + j) * NTL + n) * 64 + l) * 4 + r];
-      const int vl = c >> 1;
+      for (int ww = 0; ww < 4; ++ww) {
+        const float *s = red + (((ww * MT + j) * NTL + n) * 64) * 4;
+        re += s[lre * 4 + r];
+        im += s[(lre + 1) * 4 + r];
+      }
       if (e < ne && v0 + vl < nvec)
-        reinterpret_cast<float *>(partial + (int64_t)(off + e) * nvec + v0 + vl)[c & 1] = dV * sum;
+        partial[(int64_t)(off + e) * nvec + v0 + vl] = make_float2(dV * re, dV * im);
     }
     __syncthreads();
   }
 }
 
-// dst_v(r) += s1 * sum_e beta_e(r) C[p(e)][v]  (s1 real)
-template <int NVB>
-__global__ __launch_bounds__(NTK) void k_kb_scatter_mfma(
+// dst_v(r) += s1 sum_e beta_e(r) C'[p(e)][v] on the points r of tile t (s1 real).
+// betaT holds each tile's block transposed, [512 points][nek entries], with the
+// entry count nek padded to 32 (zeros).
+template <class Op, int NVB>
+__global__ __launch_bounds__(NTK) void k_kb_scatter_mma(
     const float2 *coef, int64_t nvec, const int *tile_base, const int *tile_off,
-    const int *entry_proj, const float *beta, float2 *dst, int64_t ld, float s1, int nx,
-    int ny, int lx, int ly) {
-  constexpr int COLS = 2 * NVB + 1, NTL = NVB / 8;
-  constexpr int SC = KB_MAXE * COLS > KB_TP * COLS ? KB_MAXE * COLS : KB_TP * COLS;
-  __shared__ float sm[SC];                         // C' [e][j], then D staging [p][j]
+    const int *tile_offT, const int *entry_proj, const typename Op::T *betaT, float2 *dst,
+    int64_t ld, float s1, int nx, int ny, int lx, int ly) {
+  using T = typename Op::T;
+  constexpr int NC = 2 * NVB, NTL = NC / 16;
+  constexpr int EL = 16 / (int)sizeof(T);
+  constexpr int PE = KB_MAXE + EL;                  // LDS pitch of a coefficient column
+  __shared__ __align__(16) T sc[NC * PE];          // C' [column][entry]
   const int t = blockIdx.y;
   const int64_t v0 = (int64_t)blockIdx.x * NVB;
   const int off = tile_off[t], ne = tile_off[t + 1] - off;
-  const int nek = (ne + 3) & ~3;                   // K padded to the MFMA step
+  const int offT = tile_offT[t], nek = tile_offT[t + 1] - offT;
   const int base = tile_base[t];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  for (int idx = tid; idx < nek * NVB; idx += NTK) {
-    const int el = idx / NVB, vl = idx % NVB;
-    float2 val = make_float2(0.f, 0.f);
-    if (el < ne && v0 + vl < nvec) val = coef[(int64_t)entry_proj[off + el] * nvec + v0 + vl];
-    sm[el * COLS + 2 * vl] = val.x;
-    sm[el * COLS + 2 * vl + 1] = val.y;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, q = lane >> 4, col = lane & 15;
+  // C' rows of this tile's entries (zero from ne up to nek), four loads in flight
+  for (int i0 = 0; i0 < nek * NVB; i0 += 4 * NTK) {
+    float2 val[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int idx = i0 + u * NTK + tid, el = idx / NVB, vl = idx % NVB;
+      val[u] = make_float2(0.f, 0.f);
+      if (el < ne && v0 + vl < nvec) val[u] = coef[(int64_t)entry_proj[off + el] * nvec + v0 + vl];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int idx = i0 + u * NTK + tid, el = idx / NVB, vl = idx % NVB;
+      if (el < nek) {
+        Op::put1(sc + (2 * vl) * PE + el, val[u].x);
+        Op::put1(sc + (2 * vl + 1) * PE + el, val[u].y);
+      }
+    }
   }
   __syncthreads();
-  const int q = lane >> 4, col = lane & 15;
-  // wave w: M tiles (16 points each) 8 w .. 8 w + 7
+  // wave w owns the M tiles (16 points each) 8 w .. 8 w + 7
   f32x4 acc[8][NTL];
 #pragma unroll
   for (int j = 0; j < 8; ++j)
 #pragma unroll
     for (int n = 0; n < NTL; ++n) acc[j][n] = f32x4{0.f, 0.f, 0.f, 0.f};
-  // K loop with the next step's operands loaded ahead of this step's MFMAs
-  float a_cur[8], a_nxt[8], b_cur[NTL], b_nxt[NTL];
-  auto load_step = [&](int k0, float *a, float *b) {
-    const int e = k0 + q;                          // this lane's K slot
+  const T *bt = betaT + (int64_t)offT * KB_TP + (int64_t)(128 * w + col) * nek + EL * q;
+  u32x4 a_cur[8], a_nxt[8], b_cur[NTL], b_nxt[NTL];
+  auto load_group = [&](int k0, u32x4 *a, u32x4 *b) {
 #pragma unroll
-    for (int n = 0; n < NTL; ++n) b[n] = sm[e * COLS + 16 * n + col];
-    const float *brow = beta + (int64_t)(off + (e < ne ? e : 0)) * KB_TP;
+    for (int j = 0; j < 8; ++j) a[j] = ld16(bt + (int64_t)(16 * j) * nek + k0);
 #pragma unroll
-    for (int j = 0; j < 8; ++j) a[j] = e < ne ? brow[16 * (8 * w + j) + col] : 0.f;  // A row = point
+    for (int n = 0; n < NTL; ++n) b[n] = ld16(sc + (16 * n + col) * PE + k0 + EL * q);
   };
-  load_step(0, a_cur, b_cur);
-  for (int k0 = 0; k0 < nek; k0 += 4) {
-    if (k0 + 4 < nek) load_step(k0 + 4, a_nxt, b_nxt);
+  if (nek > 0) load_group(0, a_cur, b_cur);
+  for (int k0 = 0; k0 < nek; k0 += Op::GK) {
+    if (k0 + Op::GK < nek) load_group(k0 + Op::GK, a_nxt, b_nxt);
 #pragma unroll
     for (int j = 0; j < 8; ++j)
 #pragma unroll
-      for (int n = 0; n < NTL; ++n)
-        acc[j][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_cur[j], b_cur[n], acc[j][n], 0, 0, 0);
+      for (int n = 0; n < NTL; ++n) Op::mma(acc[j][n], a_cur[j], b_cur[n]);
 #pragma unroll
     for (int j = 0; j < 8; ++j) a_cur[j] = a_nxt[j];
 #pragma unroll
     for (int n = 0; n < NTL; ++n) b_cur[n] = b_nxt[n];
   }
-  __syncthreads();                                 // C' no longer needed
+  // Epilogue from the accumulators.  Lanes col and col ^ 1 hold the real and
+  // imaginary columns of vector 8 n + col / 2 at the points 4 q + r; they swap
+  // halves so that each lane owns two complete values at two neighbouring
+  // points (even lane: r = 0, 1; odd lane: r = 2, 3).
+  const int odd = col & 1;
+  const int vcol = col >> 1;
+  float2 c[8][NTL][2];
+  float2 *ptr[8][NTL];
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+#pragma unroll
+    for (int n = 0; n < NTL; ++n) {
+      const f32x4 d = acc[j][n];
+      const float x0 = __shfl_xor(odd ? d[0] : d[2], 1, 64);
+      const float x1 = __shfl_xor(odd ? d[1] : d[3], 1, 64);
+      c[j][n][0] = odd ? make_float2(x0, d[2]) : make_float2(d[0], x0);
+      c[j][n][1] = odd ? make_float2(x1, d[3]) : make_float2(d[1], x1);
+      const int vl = 8 * n + vcol;
+      const int pb = 16 * (8 * w + j) + 4 * q + 2 * odd;
+      ptr[j][n] = v0 + vl < nvec ? dst + (v0 + vl) * ld + tile_point(base, pb, nx, ny, lx, ly)
+                                 : nullptr;
+    }
+  float2 o[8][NTL][2];
 #pragma unroll
   for (int j = 0; j < 8; ++j)
 #pragma unroll
     for (int n = 0; n < NTL; ++n)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int p = 16 * (8 * w + j) + 4 * q + r;
-        sm[p * COLS + 16 * n + col] = acc[j][n][r];
+      if (ptr[j][n]) {
+        o[j][n][0] = ptr[j][n][0];
+        o[j][n][1] = ptr[j][n][1];
       }
-  __syncthreads();
-  for (int idx = tid; idx < KB_TP * NVB; idx += NTK) {
-    const int vl = idx / KB_TP, p = idx % KB_TP;
-    if (v0 + vl >= nvec) continue;
-    float2 *d = dst + (v0 + vl) * ld + tile_point(base, p, nx, ny, lx, ly);
-    float2 o = *d;
-    o.x += s1 * sm[p * COLS + 2 * vl];
-    o.y += s1 * sm[p * COLS + 2 * vl + 1];
-    *d = o;
-  }
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+#pragma unroll
+    for (int n = 0; n < NTL; ++n)
+      if (ptr[j][n]) {
+        ptr[j][n][0] = make_float2(o[j][n][0].x + s1 * c[j][n][0].x, o[j][n][0].y + s1 * c[j][n][0].y);
+        ptr[j][n][1] = make_float2(o[j][n][1].x + s1 * c[j][n][1].x, o[j][n][1].y + s1 * c[j][n][1].y);
+      }
 }
 
-// variants (autotuned per context and batch size)
+// variants (autotuned per context, operand type and batch width)
 struct GatherVariant { int nvb, mt; };
-static const GatherVariant kGather[] = {{8, 2}, {8, 4}, {8, 8}, {16, 2}, {16, 4}, {16, 8}};
+static const GatherVariant kGather[] = {{8, 2}, {8, 4}, {16, 2}, {16, 4}};
 static const int kScatterNvb[] = {8, 16};
-constexpr int NGATHER = 6, NSCATTER = 2;
+constexpr int NGATHER = 4, NSCATTER = 2;
 
+template <class Op>
 static void launch_gather_variant(int vi, dim3 g, hipStream_t st, const float2 *psi, int64_t ld,
-                                  int64_t nvec, const int *tb, const int *to, const float *beta,
-                                  float2 *partial, int nx, int ny, int lx, int ly, float dV) {
+                                  int64_t nvec, const int *tb, const int *to,
+                                  const typename Op::T *beta, float2 *partial, int nx, int ny,
+                                  int lx, int ly, float dV) {
   switch (vi) {
-#define SGW_G(I, A, B) case I: hipLaunchKernelGGL((k_kb_gather_mfma<A, B>), g, dim3(NTK), 0, st, psi, ld, nvec, tb, to, beta, partial, nx, ny, lx, ly, dV); break;
-    SGW_G(0, 8, 2) SGW_G(1, 8, 4) SGW_G(2, 8, 8) SGW_G(3, 16, 2) SGW_G(4, 16, 4) SGW_G(5, 16, 8)
+#define SGW_G(I, A, B)                                                                           \
+  case I:                                                                                        \
+    hipLaunchKernelGGL((k_kb_gather_mma<Op, A, B>), g, dim3(NTK), 0, st, psi, ld, nvec, tb, to, \
+                       beta, partial, nx, ny, lx, ly, dV);                                       \
+    break;
+    SGW_G(0, 8, 2) SGW_G(1, 8, 4) SGW_G(2, 16, 2) SGW_G(3, 16, 4)
 #undef SGW_G
   }
 }
 
+template <class Op>
 static void launch_scatter_variant(int vi, dim3 g, hipStream_t st, const float2 *coef,
-                                   int64_t nvec, const int *tb, const int *to, const int *ep,
-                                   const float *beta, float2 *dst, int64_t ld, float s1, int nx,
-                                   int ny, int lx, int ly) {
+                                   int64_t nvec, const int *tb, const int *to, const int *toT,
+                                   const int *ep, const typename Op::T *betaT, float2 *dst,
+                                   int64_t ld, float s1, int nx, int ny, int lx, int ly) {
   if (vi == 0)
-    hipLaunchKernelGGL((k_kb_scatter_mfma<8>), g, dim3(NTK), 0, st, coef, nvec, tb, to, ep, beta,
-                       dst, ld, s1, nx, ny, lx, ly);
+    hipLaunchKernelGGL((k_kb_scatter_mma<Op, 8>), g, dim3(NTK), 0, st, coef, nvec, tb, to, toT,
+                       ep, betaT, dst, ld, s1, nx, ny, lx, ly);
   else
-    hipLaunchKernelGGL((k_kb_scatter_mfma<16>), g, dim3(NTK), 0, st, coef, nvec, tb, to, ep, beta,
-                       dst, ld, s1, nx, ny, lx, ly);
+    hipLaunchKernelGGL((k_kb_scatter_mma<Op, 16>), g, dim3(NTK), 0, st, coef, nvec, tb, to,
+                       toT, ep, betaT, dst, ld, s1, nx, ny, lx, ly);
+}
+
+// Operand arrays of the MFMA kernels: beta per entry [entry][512] in the
+// operand type (BF16 only; FP32 uses the working-precision copy) and the
+// transposed per-tile blocks [512][nek], nek = entries rounded up to 32.
+void kb_upload_operands(sgw_ctx *ctx) {
+  const KBHost &kb = ctx->kb;
+  auto upload = [](DevBuf &b, const auto *src, size_t n) {
+    b.ensure(n * sizeof(*src));
+    SGW_HIP(hipMemcpy(b.p, src, n * sizeof(*src), hipMemcpyHostToDevice));
+  };
+  const int nt = (int)kb.tile_base.size();
+  std::vector<int> offT(nt + 1, 0);
+  for (int t = 0; t < nt; ++t) {
+    const int ne = kb.tile_off[t + 1] - kb.tile_off[t];
+    offT[t + 1] = offT[t] + ((ne + 31) & ~31);
+  }
+  upload(ctx->d_kb_tile_offT, offT.data(), offT.size());
+  const size_t nT = (size_t)offT[nt] * KB_TP;
+  const bool bf = ctx->prec == SGW_C64_BF16KB;
+  auto fill_T = [&](auto *out, auto conv) {
+    for (int t = 0; t < nt; ++t) {
+      const int e0 = kb.tile_off[t], ne = kb.tile_off[t + 1] - e0, nek = offT[t + 1] - offT[t];
+      auto *blk = out + (size_t)offT[t] * KB_TP;
+      for (int p = 0; p < KB_TP; ++p)
+        for (int e = 0; e < ne; ++e) blk[(size_t)p * nek + e] = conv(kb.beta[(size_t)(e0 + e) * KB_TP + p]);
+    }
+  };
+  if (bf) {
+    auto conv = [](double v) { return (uint16_t)bf16_bits((float)v); };
+    std::vector<uint16_t> t16(nT, 0);
+    fill_T(t16.data(), conv);
+    upload(ctx->d_kb_betaT, t16.data(), t16.size());
+    std::vector<uint16_t> b16(kb.beta.size());
+    for (size_t i = 0; i < b16.size(); ++i) b16[i] = conv(kb.beta[i]);
+    upload(ctx->d_kb_beta16, b16.data(), b16.size());
+  } else {
+    std::vector<float> tf(nT, 0.f);
+    fill_T(tf.data(), [](double v) { return (float)v; });
+    upload(ctx->d_kb_betaT, tf.data(), tf.size());
+  }
 }
 
 // ---------------------------------------------------------------- launchers
@@ -368,15 +513,22 @@ static void gather_t(sgw_ctx *ctx, const void *psi, int64_t nvec, int64_t ld, vo
   C *partial = ctx->buf("kb_partial", sizeof(C) * (size_t)ctx->kb_nentry * nvec).as<C>();
   SGW_REQUIRE(ctx->kb_ntile <= 65535, SGW_EUNSUPPORTED, "KB gather: too many tiles");
   if constexpr (sizeof(R) == 4) {
-    auto run = [&](int vi) {
-      const int64_t nvb = (nvec + kGather[vi].nvb - 1) / kGather[vi].nvb;
-      launch_gather_variant(vi, dim3(nvb, ctx->kb_ntile), ctx->stream,
-                            static_cast<const float2 *>(psi), ld, nvec,
-                            ctx->d_kb_tile_base.as<int>(), ctx->d_kb_tile_off.as<int>(),
-                            ctx->d_kb_beta.as<float>(), reinterpret_cast<float2 *>(partial),
-                            ctx->nx, ctx->ny, ctx->kb_lx, ctx->kb_ly, (float)ctx->dV);
+    auto go = [&](auto op, const char *name, const auto *beta) {
+      using Op = decltype(op);
+      auto run = [&](int vi) {
+        const int64_t nvb = (nvec + kGather[vi].nvb - 1) / kGather[vi].nvb;
+        launch_gather_variant<Op>(vi, dim3(nvb, ctx->kb_ntile), ctx->stream,
+                                  static_cast<const float2 *>(psi), ld, nvec,
+                                  ctx->d_kb_tile_base.as<int>(), ctx->d_kb_tile_off.as<int>(),
+                                  beta, reinterpret_cast<float2 *>(partial), ctx->nx, ctx->ny,
+                                  ctx->kb_lx, ctx->kb_ly, (float)ctx->dV);
+      };
+      run(ctx->tune(name, nvec, NGATHER, run));   // the gather overwrites: trials are harmless
     };
-    run(ctx->tune("kb_gather", nvec, NGATHER, run));   // the gather overwrites: trials are harmless
+    if (ctx->prec == SGW_C64_BF16KB)
+      go(OpBF16{}, "kb_gather_bf16", ctx->d_kb_beta16.as<uint16_t>());
+    else
+      go(OpF32{}, "kb_gather", ctx->d_kb_beta.as<float>());
   } else {
     const int64_t nvb = (nvec + NV - 1) / NV;
     hipLaunchKernelGGL(k_kb_gather<R>, dim3(nvb, ctx->kb_ntile), dim3(NTK), 0, ctx->stream,
@@ -423,30 +575,29 @@ static void scatter_t(sgw_ctx *ctx, const void *coef, int64_t nvec, void *dst, i
   using C = cplx<R>;
   SGW_REQUIRE(ctx->kb_ntile <= 65535, SGW_EUNSUPPORTED, "KB scatter: too many tiles");
   if constexpr (sizeof(R) == 4) {
-    if (dst2 == nullptr && s1im == 0.0) {
-      auto run = [&](int vi) {
+    SGW_REQUIRE(dst2 == nullptr && s1im == 0.0, SGW_EUNSUPPORTED,
+                "KB scatter (FP32): complex scale or second output not built");
+    auto go = [&](auto op, const char *name, const auto *betaT) {
+      using Op = decltype(op);
+      auto launch = [&](int vi, float s) {
         const int64_t nvb = (nvec + kScatterNvb[vi] - 1) / kScatterNvb[vi];
-        launch_scatter_variant(vi, dim3(nvb, ctx->kb_ntile), ctx->stream,
-                               static_cast<const float2 *>(coef), nvec,
-                               ctx->d_kb_tile_base.as<int>(), ctx->d_kb_tile_off.as<int>(),
-                               ctx->d_kb_entry_proj.as<int>(), ctx->d_kb_beta.as<float>(),
-                               static_cast<float2 *>(dst), ld, (float)s1re, ctx->nx, ctx->ny,
-                               ctx->kb_lx, ctx->kb_ly);
+        launch_scatter_variant<Op>(vi, dim3(nvb, ctx->kb_ntile), ctx->stream,
+                                   static_cast<const float2 *>(coef), nvec,
+                                   ctx->d_kb_tile_base.as<int>(), ctx->d_kb_tile_off.as<int>(),
+                                   ctx->d_kb_tile_offT.as<int>(), ctx->d_kb_entry_proj.as<int>(),
+                                   betaT, static_cast<float2 *>(dst), ld, s, ctx->nx, ctx->ny,
+                                   ctx->kb_lx, ctx->kb_ly);
       };
       // trials add 0 * (B C) to dst, which leaves it unchanged
-      const int vi = ctx->tune("kb_scatter", nvec, NSCATTER, [&](int i) {
-        const int64_t nvb = (nvec + kScatterNvb[i] - 1) / kScatterNvb[i];
-        launch_scatter_variant(i, dim3(nvb, ctx->kb_ntile), ctx->stream,
-                               static_cast<const float2 *>(coef), nvec,
-                               ctx->d_kb_tile_base.as<int>(), ctx->d_kb_tile_off.as<int>(),
-                               ctx->d_kb_entry_proj.as<int>(), ctx->d_kb_beta.as<float>(),
-                               static_cast<float2 *>(dst), ld, 0.0f, ctx->nx, ctx->ny,
-                               ctx->kb_lx, ctx->kb_ly);
-      });
-      run(vi);
-      SGW_HIP(hipGetLastError());
-      return;
-    }
+      const int vi = ctx->tune(name, nvec, NSCATTER, [&](int i) { launch(i, 0.0f); });
+      launch(vi, (float)s1re);
+    };
+    if (ctx->prec == SGW_C64_BF16KB)
+      go(OpBF16{}, "kb_scatter_bf16", ctx->d_kb_betaT.as<uint16_t>());
+    else
+      go(OpF32{}, "kb_scatter", ctx->d_kb_betaT.as<float>());
+    SGW_HIP(hipGetLastError());
+    return;
   }
   const int64_t nvb = (nvec + NV - 1) / NV;
   hipLaunchKernelGGL(k_kb_scatter<R>, dim3(nvb, ctx->kb_ntile), dim3(NTK), 0, ctx->stream,

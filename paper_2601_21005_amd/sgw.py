@@ -24,7 +24,11 @@ STATUS_NAMES = {0: "SGW_OK", -1: "SGW_EINVAL", -2: "SGW_ENOMEM", -3: "SGW_EHIP",
 EXPORTS = ["sgw_create", "sgw_destroy", "sgw_last_error", "sgw_bounds", "sgw_apply_H",
            "sgw_fermi_coefficients", "sgw_fermi_filter", "sgw_propagator_coefficients",
            "sgw_cheb_propagate", "sgw_tdh_init", "sgw_tdh_step", "sgw_sigma_estimate",
-           "sgw_qp_solve", "sgw_sigma_omega", "sgw_kernel_timer", "sgw_kernel_timer_read"]
+           "sgw_qp_solve", "sgw_sigma_omega", "sgw_kernel_timer", "sgw_kernel_timer_read",
+           "sgw_cv_features", "sgw_mlp_create", "sgw_mlp_destroy", "sgw_mlp_last_error",
+           "sgw_mlp_set_standardization", "sgw_mlp_get_params", "sgw_mlp_forward",
+           "sgw_mlp_gradient", "sgw_mlp_adam", "sgw_mlp_train", "sgw_cv_cheap_moments",
+           "sgw_cv_estimate"]
 
 
 class SgwGrid(C.Structure):
@@ -56,6 +60,12 @@ class SgwSigmaParams(C.Structure):
                 ("ncoef", C.c_int32), ("emin", C.c_double), ("emax", C.c_double),
                 ("n_xi", C.c_int32), ("f_g", C.c_double), ("mode", C.c_int32),
                 ("prop_tol", C.c_double), ("n_ft", C.c_int32), ("batch", C.c_int32)]
+
+
+class SgwCvResult(C.Structure):
+    _fields_ = [("estimate", C.c_double), ("sigma", C.c_double), ("c", C.c_double),
+                ("rho2", C.c_double), ("plain", C.c_double), ("sigma_plain", C.c_double),
+                ("sigma_cv", C.c_double), ("fallback", C.c_int32)]
 
 
 class SgwError(RuntimeError):
@@ -96,8 +106,25 @@ def load():
     lib.sgw_sigma_omega.argtypes = [dp, i32, d, d, dp, i32, dp]
     lib.sgw_kernel_timer.argtypes = [vp, i32]
     lib.sgw_kernel_timer_read.argtypes = [vp, dp, C.POINTER(i64), C.POINTER(i64)]
+    u64, fp = C.c_uint64, C.c_void_p
+    lib.sgw_cv_features.argtypes = [vp, fp, i32, i64, u64, i64, i64, fp]
+    lib.sgw_mlp_create.argtypes = [i32, i32, i32, dp, vp, C.POINTER(vp)]
+    lib.sgw_mlp_destroy.argtypes = [vp]
+    lib.sgw_mlp_destroy.restype = None
+    lib.sgw_mlp_last_error.argtypes = [vp]
+    lib.sgw_mlp_last_error.restype = C.c_char_p
+    lib.sgw_mlp_set_standardization.argtypes = [vp, dp, dp]
+    lib.sgw_mlp_get_params.argtypes = [vp, dp]
+    lib.sgw_mlp_forward.argtypes = [vp, fp, i64, fp]
+    lib.sgw_mlp_gradient.argtypes = [vp, fp, fp, i64, dp, dp]
+    lib.sgw_mlp_adam.argtypes = [vp, dp, d, d, d, d]
+    lib.sgw_mlp_train.argtypes = [vp, fp, fp, i64, i32, d, dp]
+    lib.sgw_cv_cheap_moments.argtypes = [vp, vp, fp, i32, i64, u64, i64, i64, i64, dp, dp]
+    lib.sgw_cv_estimate.argtypes = [dp, dp, i64, dp, dp, i64, d, d, i64,
+                                    C.POINTER(SgwCvResult)]
     for name in EXPORTS:
-        if name not in ("sgw_destroy", "sgw_last_error"):
+        if name not in ("sgw_destroy", "sgw_last_error", "sgw_mlp_destroy",
+                        "sgw_mlp_last_error"):
             getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -114,6 +141,12 @@ def _iptr(a):
 def _check(code, ctx=None):
     if code != SGW_OK:
         msg = load().sgw_last_error(ctx)
+        raise SgwError(code, msg.decode() if msg else "")
+
+
+def _check_mlp(code, mlp=None):
+    if code != SGW_OK:
+        msg = load().sgw_mlp_last_error(mlp)
         raise SgwError(code, msg.decode() if msg else "")
 
 
@@ -277,3 +310,119 @@ class Context:
         _check(load().sgw_sigma_estimate(self.ctx, C.byref(p), _dptr(ph), _dptr(sig), _dptr(x),
                                          _dptr(ms)), self.ctx)
         return sig[..., 0] + 1j * sig[..., 1], x, ms
+
+
+# ------------------------------------------------------------------ control variate
+def sgw_cv_estimate(yA, gA, yB, gB, gM_mean, gM_var, M):
+    """Control-variate estimate (host FP64); returns a dict of sgw_cv_result."""
+    arr = [np.ascontiguousarray(np.asarray(a, dtype=np.float64)) for a in (yA, gA, yB, gB)]
+    if arr[0].size != arr[1].size or arr[2].size != arr[3].size:
+        raise ValueError("y and g must have the same length on each set")
+    r = SgwCvResult()
+    _check(load().sgw_cv_estimate(_dptr(arr[0]), _dptr(arr[1]), arr[0].size, _dptr(arr[2]),
+                                  _dptr(arr[3]), arr[2].size, float(gM_mean), float(gM_var),
+                                  int(M), C.byref(r)))
+    return {f: getattr(r, f) for f, _ in SgwCvResult._fields_} | {"fallback": bool(r.fallback)}
+
+
+def _fdev(t, name, n=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32:
+        raise TypeError(f"{name} must be a float32 torch tensor on the GPU")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if n is not None and t.numel() < n:
+        raise ValueError(f"{name} is too small")
+    return C.c_void_p(t.data_ptr())
+
+
+def cv_features(ctx, phi, seed, first_sample, nsamp, out=None):
+    """x[i][k] = |<phi_k|zeta_i>|^2 for samples first_sample .. + nsamp - 1
+    (phi: float32 [K][N] on the GPU); returns a float32 [nsamp][K] tensor."""
+    import torch
+    K = phi.shape[0]
+    if out is None:
+        out = torch.empty((nsamp, K), dtype=torch.float32, device="cuda")
+    _check(load().sgw_cv_features(ctx.ctx, _fdev(phi, "phi"), K, phi.shape[-1], int(seed),
+                                  int(first_sample), int(nsamp), _fdev(out, "x", nsamp * K)),
+           ctx.ctx)
+    return out
+
+
+def cv_cheap_moments(ctx, mlp, phi, seed, first_sample, count, chunk=65536):
+    m, v = C.c_double(), C.c_double()
+    _check(load().sgw_cv_cheap_moments(ctx.ctx, mlp.mlp, _fdev(phi, "phi"), phi.shape[0],
+                                       phi.shape[-1], int(seed), int(first_sample), int(count),
+                                       int(chunk), C.byref(m), C.byref(v)), ctx.ctx)
+    return m.value, v.value
+
+
+class Mlp:
+    """The control-variate network (FP32 masters on the device, BF16 MFMA)."""
+
+    def __init__(self, theta0, din=64, h1=256, h2=256, stream=None):
+        import torch
+        th = np.ascontiguousarray(np.asarray(theta0, dtype=np.float64))
+        self.din, self.h1, self.h2 = din, h1, h2
+        self.nparam = h1 * din + h1 + h2 * h1 + h2 + h2 + 1
+        if th.size != self.nparam:
+            raise ValueError("theta0 has the wrong size")
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        m = C.c_void_p()
+        _check_mlp(load().sgw_mlp_create(din, h1, h2, _dptr(th), C.c_void_p(stream),
+                                         C.byref(m)), None)
+        self.mlp = m
+
+    def close(self):
+        if getattr(self, "mlp", None):
+            load().sgw_mlp_destroy(self.mlp)
+            self.mlp = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_standardization(self, mean, std):
+        m = np.ascontiguousarray(np.asarray(mean, dtype=np.float64))
+        s = np.ascontiguousarray(np.asarray(std, dtype=np.float64))
+        _check_mlp(load().sgw_mlp_set_standardization(self.mlp, _dptr(m), _dptr(s)), self.mlp)
+
+    def params(self):
+        out = np.zeros(self.nparam)
+        _check_mlp(load().sgw_mlp_get_params(self.mlp, _dptr(out)), self.mlp)
+        return out
+
+    def forward(self, x, out=None):
+        import torch
+        n = x.shape[0]
+        if out is None:
+            out = torch.empty(n, dtype=torch.float32, device="cuda")
+        _check_mlp(load().sgw_mlp_forward(self.mlp, _fdev(x, "x", n * self.din), n,
+                                          _fdev(out, "g", n)), self.mlp)
+        return out
+
+    def gradient(self, x, y):
+        n = x.shape[0]
+        loss = C.c_double()
+        g = np.zeros(self.nparam)
+        _check_mlp(load().sgw_mlp_gradient(self.mlp, _fdev(x, "x", n * self.din),
+                                           _fdev(y, "y", n), n, C.byref(loss), _dptr(g)),
+                   self.mlp)
+        return loss.value, g
+
+    def adam(self, grad=None, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+        gp = None
+        if grad is not None:
+            grad = np.ascontiguousarray(np.asarray(grad, dtype=np.float64))
+            gp = _dptr(grad)
+        _check_mlp(load().sgw_mlp_adam(self.mlp, gp, lr, b1, b2, eps), self.mlp)
+
+    def train(self, x, y, steps, lr=1e-3):
+        n = x.shape[0]
+        hist = np.zeros(max(1, steps))
+        _check_mlp(load().sgw_mlp_train(self.mlp, _fdev(x, "x", n * self.din), _fdev(y, "y", n),
+                                        n, int(steps), lr, _dptr(hist)), self.mlp)
+        return hist[:steps]

@@ -1,0 +1,247 @@
+"""GPU parity of the learned control variate: features, network forward and
+gradient, Adam, training, cheap-sample moments, and the gain over the plain
+estimator on real per-sample Sigma values.
+
+Two references: the FP64 oracle (tolerances from BF16 operand rounding,
+u = 2^-9) and, for tight checks, a model of the kernels' own arithmetic in
+this file: every GEMM operand rounded to BF16 (nearest even), everything else
+in FP64."""
+import numpy as np
+import pytest
+import torch
+
+from conftest import build_oracle_h
+from oracle import cv
+from oracle import eigen
+from oracle import qp as oqp
+from oracle.grid import Grid
+from paper_2601_21005_amd import sgw, systems
+
+pytestmark = pytest.mark.gpu
+U_BF16 = 2.0 ** -9
+
+
+def bf16(a):
+    """Round to BF16 (nearest even) through FP32, returned as float64."""
+    u = np.ascontiguousarray(np.asarray(a, dtype=np.float32)).view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000).astype(np.uint32)
+    return u.view(np.float32).astype(np.float64)
+
+
+def model_forward(theta, xh, din, h1, h2):
+    W1, b1, W2, b2, w3, b3 = cv.unpack(theta, din, h1, h2)
+    a1 = np.tanh(bf16(xh) @ bf16(W1).T + b1)
+    a2 = np.tanh(bf16(a1) @ bf16(W2).T + b2)
+    return a2 @ w3 + b3[0], a1, a2
+
+
+def model_gradient(theta, xh, y, din, h1, h2):
+    W1, b1, W2, b2, w3, b3 = cv.unpack(theta, din, h1, h2)
+    g, a1, a2 = model_forward(theta, xh, din, h1, h2)
+    n = xh.shape[0]
+    dg = 2.0 * (g - y) / n
+    d2 = np.outer(dg, w3) * (1 - a2 * a2)
+    d1 = (bf16(d2) @ bf16(W2)) * (1 - a1 * a1)
+    return np.concatenate([(bf16(d1).T @ bf16(xh)).ravel(), d1.sum(0),
+                           (bf16(d2).T @ bf16(a1)).ravel(), d2.sum(0), a2.T @ dg, [dg.sum()]])
+
+
+def f32(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def blocks(v, din, h1, h2):
+    return [b.ravel() for b in cv.unpack(v, din, h1, h2)]
+
+
+# ------------------------------------------------------------------ features
+@pytest.mark.parametrize("which,K,first,nsamp", [("tiny8", 16, 0, 300), ("cfg1", 64, 1000, 70)])
+def test_features_match_oracle(which, K, first, nsamp, request):
+    """a = sqrt(dV) sum_r phi(r) s(r) with phi rounded to BF16 and FP32 sums:
+    |a_gpu - a| <= sqrt(dV) sum|phi| (u + N 2^-24), x = a^2."""
+    s, H = request.getfixturevalue(which)
+    g = H.grid
+    rs = np.random.default_rng(31)
+    phi = rs.standard_normal((K, g.N))
+    phi /= np.sqrt(g.dV * np.sum(phi * phi, axis=1))[:, None]
+    phi = phi.astype(np.float32).astype(np.float64)
+    ctx = sgw.Context(s.grid.n, s.grid.h, s.v_loc, None, precision=sgw.SGW_C64, max_nvec=4)
+    x = sgw.cv_features(ctx, f32(phi), seed=77, first_sample=first, nsamp=nsamp)
+    got = x.cpu().numpy().astype(np.float64)
+    ctx.close()
+    ref = cv.features(g, phi, 77, range(first, first + nsamp))
+    a = np.sqrt(ref)
+    da = np.sqrt(g.dV) * np.sum(np.abs(phi), axis=1) * (U_BF16 + g.N * 2.0 ** -24)
+    assert np.all(np.abs(got - ref) <= 2 * a * da[None] + da[None] ** 2)
+    # the BF16 rounding model of the kernel: only FP32 summation differs
+    model = g.dV * (bf16(phi) @ np.stack([cv.rng.white_noise_signs(
+        77, cv.rng.stream_id(cv.rng.ZETA, i, 0), g.N) for i in range(first, first + nsamp)]).T).T ** 2
+    assert np.max(np.abs(got - model)) < 1e-4 * np.max(model)
+
+
+def test_features_reject_bad_sizes(tiny8):
+    s, _ = tiny8
+    ctx = sgw.Context(s.grid.n, s.grid.h, s.v_loc, None, precision=sgw.SGW_C64, max_nvec=4)
+    phi = torch.zeros((65, s.grid.N), dtype=torch.float32, device="cuda")
+    with pytest.raises(sgw.SgwError) as e:
+        sgw.cv_features(ctx, phi, 1, 0, 4)
+    assert e.value.code == sgw.SGW_EINVAL
+    with pytest.raises(sgw.SgwError):
+        sgw.cv_features(ctx, phi[:4], 1, (1 << 20) - 2, 4)
+    ctx.close()
+
+
+# ------------------------------------------------------------------ network
+@pytest.fixture(scope="module")
+def net_case():
+    rs = np.random.default_rng(32)
+    din, h1, h2, n = 64, 256, 256, 700
+    theta = systems.mlp_init(5, din, h1, h2)
+    theta[din * h1:din * h1 + h1] = 0.1 * rs.standard_normal(h1)    # non-zero biases
+    x = rs.gamma(1.0, 1.0, size=(n, din)).astype(np.float32).astype(np.float64)
+    mean, std = cv.standardization(x)
+    y = np.tanh(x[:, 0] - 1) + 0.3 * x[:, 1] + 0.1 * rs.standard_normal(n)
+    y = y.astype(np.float32).astype(np.float64)
+    xh = ((x.astype(np.float32) - mean.astype(np.float32))
+          * (1.0 / std).astype(np.float32)).astype(np.float64)
+    return dict(theta=theta.astype(np.float32).astype(np.float64), x=x, y=y, mean=mean,
+                std=std, xh=xh, din=din, h1=h1, h2=h2)
+
+
+def make_net(c):
+    m = sgw.Mlp(c["theta"], c["din"], c["h1"], c["h2"])
+    m.set_standardization(c["mean"], c["std"])
+    return m
+
+
+def test_forward_matches_oracle(net_case):
+    c = net_case
+    m = make_net(c)
+    g = m.forward(f32(c["x"])).cpu().numpy().astype(np.float64)
+    m.close()
+    ref, _ = cv.forward(c["theta"], c["xh"])
+    mod, _, _ = model_forward(c["theta"], c["xh"], 64, 256, 256)
+    # BF16 operands: each layer's pre-activation carries ~2u relative noise
+    assert np.linalg.norm(g - ref) < 8 * U_BF16 * np.linalg.norm(ref)
+    assert np.max(np.abs(g - mod)) < 1e-4 * np.max(np.abs(ref))
+
+
+def test_gradient_matches_oracle_backprop(net_case):
+    """The device gradient against the FP64 chain rule (normwise 4e-2 per
+    parameter block from BF16 operands) and against the rounding model
+    (5e-4)."""
+    c = net_case
+    m = make_net(c)
+    L, gr = m.gradient(f32(c["x"]), f32(c["y"]))
+    m.close()
+    Lo, go = cv.loss_and_gradient(c["theta"], c["xh"], c["y"])
+    gm = model_gradient(c["theta"], c["xh"], c["y"], 64, 256, 256)
+    assert abs(L - Lo) < 4 * U_BF16 * Lo
+    for k, (a, b, mdl) in enumerate(zip(blocks(gr, 64, 256, 256), blocks(go, 64, 256, 256),
+                                        blocks(gm, 64, 256, 256))):
+        nb = np.linalg.norm(b)
+        assert np.linalg.norm(a - b) < 4e-2 * nb, k
+        assert np.linalg.norm(a - mdl) < 5e-4 * np.linalg.norm(mdl), k
+    cos = gr @ go / (np.linalg.norm(gr) * np.linalg.norm(go))
+    assert cos > 0.999
+
+
+def test_adam_steps_match_oracle(net_case):
+    """Given gradients (host FP64 inputs), three Adam steps in FP32 against
+    the oracle's FP64 Adam: relative 1e-6 of the parameters' scale."""
+    c = net_case
+    m = make_net(c)
+    rs = np.random.default_rng(33)
+    opt = cv.Adam(c["theta"].size, lr=2e-3)
+    th = c["theta"].copy()
+    for _ in range(3):
+        gvec = rs.standard_normal(th.size) * np.exp(rs.uniform(-8, 2, th.size))
+        m.adam(gvec, lr=2e-3)
+        th = opt.step(th, gvec.astype(np.float32).astype(np.float64))
+    got = m.params()
+    m.close()
+    assert np.max(np.abs(got - th)) < 1e-6 * (1 + np.max(np.abs(th)))
+
+
+def test_training_follows_oracle(net_case):
+    """200 full-batch Adam steps on the device and in the oracle from the
+    same start: both lower the loss by > 3x and end within 30% of each
+    other."""
+    c = net_case
+    m = make_net(c)
+    hist = m.train(f32(c["x"]), f32(c["y"]), 200, lr=1e-3)
+    m.close()
+    _, ho = cv.train(c["theta"], c["xh"], c["y"], 200, lr=1e-3)
+    assert abs(hist[0] - ho[0]) < 4 * U_BF16 * ho[0]
+    assert hist[-1] < hist[0] / 3 and ho[-1] < ho[0] / 3
+    assert abs(np.log(hist[-1] / ho[-1])) < np.log(1.3)
+    assert np.all(np.diff(hist[:20]) < 0)
+
+
+def test_cheap_moments_match_model(tiny8, net_case):
+    """Mean and variance of g over 3000 cheap samples: device chunks of 512
+    against the FP64 oracle (features and network)."""
+    s, H = tiny8
+    c = net_case
+    g = H.grid
+    rs = np.random.default_rng(34)
+    phi = rs.standard_normal((64, g.N))
+    phi /= np.sqrt(g.dV * np.sum(phi * phi, axis=1))[:, None]
+    phi = phi.astype(np.float32).astype(np.float64)
+    ctx = sgw.Context(s.grid.n, s.grid.h, s.v_loc, None, precision=sgw.SGW_C64, max_nvec=4)
+    m = sgw.Mlp(c["theta"])
+    x = cv.features(g, phi, 9, range(5000, 8000))
+    mean, std = cv.standardization(x)
+    m.set_standardization(mean, std)
+    mu, var = sgw.cv_cheap_moments(ctx, m, f32(phi), 9, 5000, 3000, chunk=512)
+    m.close()
+    ctx.close()
+    go, _ = cv.forward(c["theta"], (x - mean) / std)
+    assert abs(mu - go.mean()) < 0.02 * go.std()
+    assert abs(var / go.var(ddof=1) - 1) < 0.05
+
+
+# ------------------------------------------------------------------ gain
+def test_control_variate_gain_on_sgw_samples(tiny8, tiny8_eig):
+    """Plain sGW on the 8^3 system gives per-sample y_i = X_i + Re
+    Sigma_c,i(omega*) for 512 samples; a network on |<phi_k|zeta_i>|^2 over
+    the 64 lowest states, fitted on 256 of them, cuts the standard error of
+    the mean on the other 256 (with 20000 cheap samples for E[g]) and agrees
+    with the plain estimate (no fallback)."""
+    s, H = tiny8
+    e, V = tiny8_eig
+    phi_qp = V[s.n_occ - 1]
+    ctx = sgw.Context(s.grid.n, s.grid.h, s.v_loc, s.projectors, precision=sgw.SGW_C64,
+                      max_nvec=64)
+    lo, hi = ctx.bounds()
+    mu = 0.5 * (e[s.n_occ - 1] + e[s.n_occ])
+    p = dict(seed=41, n_eta=8, n_tau=30, dt=0.1, m_sub=2, mu=mu, beta=10.0, ncoef=600,
+             emin=lo, emax=hi, n_xi=64, f_g=0.125, mode=1)
+    sig, xs = [], []
+    for b in range(8):
+        si, xi, _ = ctx.sigma_estimate(phi_qp, n_zeta=64, first_sample=64 * b, **p)
+        sig.append(si)
+        xs.append(xi)
+    sig, xs = np.concatenate(sig), np.concatenate(xs)
+    gam = oqp.default_gamma(p["n_tau"], p["dt"])
+    eqp = sgw.sgw_qp_solve(sig.mean(0), p["dt"], gam, e[s.n_occ - 1], xs.mean())[0]
+    y = xs + np.array([sgw.sgw_sigma_omega(si, p["dt"], gam, eqp)[0].real for si in sig])
+    phi = f32(V[:64] / np.sqrt(H.grid.dV * np.sum(V[:64] ** 2, axis=1))[:, None])
+    x = sgw.cv_features(ctx, phi, p["seed"], 0, 512)
+    xn = x.cpu().numpy().astype(np.float64)
+    mean, std = cv.standardization(xn[:256])
+    m = sgw.Mlp(systems.mlp_init(3))
+    m.set_standardization(mean, std)
+    ym, ys = y[:256].mean(), y[:256].std()
+    m.train(x[:256].contiguous(), f32((y[:256] - ym) / ys), 300, lr=1e-3)
+    gv = m.forward(x).cpu().numpy().astype(np.float64)
+    gm, gvar = sgw.cv_cheap_moments(ctx, m, phi, p["seed"], 1000, 20000, chunk=4096)
+    m.close()
+    ctx.close()
+    r = sgw.sgw_cv_estimate(y[:256], gv[:256], y[256:], gv[256:], gm, gvar, 20000)
+    plain_B = y[256:].std(ddof=1) / np.sqrt(256)
+    print(f"\ncontrol variate: rho2 {r['rho2']:.3f}  sigma_cv {r['sigma_cv']:.3e}  "
+          f"sigma_plain(B) {plain_B:.3e}  ratio {(r['sigma_cv'] / plain_B) ** 2:.3f}  "
+          f"fallback {r['fallback']}", flush=True)
+    assert not r["fallback"]
+    assert r["sigma_cv"] < 0.9 * plain_B

@@ -103,17 +103,19 @@ def test_bounds_match_oracle(si35, tiny8):
         ctx.close()
 
 
-def test_kb_variants_bit_identical(si35, monkeypatch):
+@pytest.mark.parametrize("prec,names", [(sgw.SGW_C64, ("kb_gather", "kb_scatter")),
+                                         (sgw.SGW_C64_BF16KB, ("kb_gather_bf16", "kb_scatter_bf16"))])
+def test_kb_variants_bit_identical(si35, monkeypatch, prec, names):
     """Every autotuned KB kernel variant adds the same products in the same
     order: H psi is bitwise the same whichever variant runs."""
     s, H = si35
     rs = np.random.default_rng(9)
     x = rs.standard_normal((20, s.grid.N)) + 1j * rs.standard_normal((20, s.grid.N))
     ref = None
-    for g in range(6):
+    for g in range(4):
         for sc in range(2):
-            monkeypatch.setenv("SGW_FORCE_VARIANT", f"kb_gather={g},kb_scatter={sc}")
-            ctx = make_ctx(s, sgw.SGW_C64, max_nvec=32)
+            monkeypatch.setenv("SGW_FORCE_VARIANT", f"{names[0]}={g},{names[1]}={sc}")
+            ctx = make_ctx(s, prec, max_nvec=32)
             xd = torch.from_numpy(x).to(torch.complex64).cuda()
             yd = torch.empty_like(xd)
             ctx.apply_H(xd, yd)

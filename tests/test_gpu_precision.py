@@ -1,0 +1,180 @@
+"""Precision variants against the FP64 oracle, per result.
+
+SGW_C64 runs the whole path in complex FP32 (FP64 coefficients, norms and
+sums); SGW_C64_BF16KB additionally rounds the operands of the projector GEMMs
+(beta, psi and the mixed coefficients) to BF16, nearest even, with FP32
+accumulation.  Each result is compared with the oracle on identical inputs:
+H psi (Eq. 1), one zeta propagation step (Eq. 4), one TDH substep
+(Sec. 2.1), the Fermi filter (Eq. 3), Sigma_c(t) (Eq. 5), Sigma(omega) at the
+QP energy (Eq. 7) and the QP energy itself (Eq. 6).  The measured errors are
+printed as a table (pytest -s)."""
+import numpy as np
+import pytest
+import torch
+
+from conftest import make_ctx, norm_err, rel_err
+from oracle import chebyshev as cheb
+from oracle import qp as oqp
+from oracle.sigma import SGWParams, estimate
+from oracle.tdh import TDH
+from paper_2601_21005_amd import sgw
+
+pytestmark = pytest.mark.gpu
+HA_EV = 27.211386245988
+U_BF16 = 2.0 ** -9          # unit roundoff of BF16 (8 significant bits)
+U_F32 = 2.0 ** -24
+NAMES = {sgw.SGW_C64: "c64", sgw.SGW_C64_BF16KB: "c64+bf16kb"}
+
+
+def kb_abs_bound(H, x):
+    """Elementwise sum_p |beta_p| |E_p| dV <|beta_p|, |x|>: the KB term with
+    every product taken in absolute value."""
+    P = H.kb
+    B = abs(P.B)
+    C = (B.T @ np.abs(x).T) * H.grid.dV * np.abs(P.ekb)[:, None]
+    return (B @ C).T
+
+
+def hpsi(system, prec, x):
+    ctx = make_ctx(system, prec, max_nvec=8)
+    xd = torch.from_numpy(x).to(torch.complex64).cuda()
+    yd = torch.empty_like(xd)
+    ctx.apply_H(xd, yd)
+    out = yd.cpu().numpy().astype(np.complex128)
+    xin = xd.cpu().numpy().astype(np.complex128)
+    ctx.close()
+    return out, xin
+
+
+@pytest.mark.parametrize("which", ["tiny8", "si35"])
+def test_hpsi_bf16_within_rounding_bound(which, request):
+    """Rounding analysis of the BF16 KB term: beta (twice), psi and the mixed
+    coefficients are each rounded once (relative error <= u = 2^-9), the sums
+    run in FP32.  Elementwise |error| <= (4 u + O(u^2) + K u_32) times the KB
+    term taken in absolute value, plus the FP32 error of the local part
+    (3e-6 normwise).  The statistical size of the same error (independent
+    roundings, RMS u / sqrt(3) each) is about 1.2 u of |V_NL psi|; the test
+    also holds it below 4 u."""
+    s, H = request.getfixturevalue(which)
+    rs = np.random.default_rng(12)
+    x = rs.standard_normal((6, s.grid.N)) + 1j * rs.standard_normal((6, s.grid.N))
+    got, xin = hpsi(s, sgw.SGW_C64_BF16KB, x)
+    ref = H.apply(xin)
+    ynl = H.kb.apply(xin)
+    yabs = kb_abs_bound(H, xin)
+    err = np.abs(got - ref)
+    K = 4096                                     # longest FP32 sum (points + entries)
+    bound = (4.1 * U_BF16 + K * U_F32) * yabs
+    nrm = np.linalg.norm(ref, axis=1)
+    assert np.all(np.linalg.norm(err, axis=1) <= np.linalg.norm(bound, axis=1) + 3e-6 * nrm)
+    stat = np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ynl, axis=1)
+    assert np.all(stat < 4 * U_BF16 + 3e-6 * nrm / np.linalg.norm(ynl, axis=1)), stat
+
+
+def test_bf16_rounds_the_kb_operands(tiny8):
+    """The BF16 variant is a different computation from FP32: its KB term
+    differs from the FP32 one by about the BF16 rounding, far above FP32's."""
+    s, H = tiny8
+    rs = np.random.default_rng(13)
+    x = rs.standard_normal((3, s.grid.N)) + 1j * rs.standard_normal((3, s.grid.N))
+    a, xin = hpsi(s, sgw.SGW_C64_BF16KB, x)
+    b, _ = hpsi(s, sgw.SGW_C64, x)
+    ynl = H.kb.apply(xin)
+    d = np.linalg.norm(a - b, axis=1) / np.linalg.norm(ynl, axis=1)
+    assert np.all(d > 0.05 * U_BF16), d
+
+
+# ------------------------------------------------------------------ table
+@pytest.fixture(scope="module")
+def si35_oracle(si35):
+    """Oracle results on the 64^3 cluster for the fixed inputs of the table."""
+    s, H = si35
+    N = s.grid.N
+    rs = np.random.default_rng(21)
+    x = (rs.standard_normal((3, N)) + 1j * rs.standard_normal((3, N))).astype(np.complex64)
+    x = x.astype(np.complex128)
+    lo, hi = H.bounds()
+    prop = cheb.propagate(H, lo, hi, 0.05, x)
+    xr = rs.standard_normal((4, N)).astype(np.float32).astype(np.float64)
+    coef = cheb.fermi_coefficients(-4.65, 2.0, lo, hi, 120)
+    filt = cheb.apply_series(H, coef, lo, hi, xr)
+    eta = (0.3 * rs.standard_normal((4, N))).astype(np.float32).astype(np.complex128)
+    dv = (0.5 * np.sin(np.linspace(0, 7, N))).astype(np.float32).astype(np.float64)
+    o = TDH(H, 0.05, 2.0 / 4)
+    tdh = o.substep(*o.start(eta, dv))
+    phi = rs.standard_normal(N)
+    phi /= np.sqrt(H.grid.dV * np.sum(phi * phi))
+    p = SGWParams(seed=1002, n_zeta=2, n_eta=4, n_tau=6, dt=0.05, m_sub=1, mu=-4.65, beta=2.0,
+                  ncoef=120, emin=lo, emax=hi, n_xi=500, f_g=0.003, mode="xi")
+    sig, xx = estimate(H, phi, p)
+    eks = float(np.real(np.vdot(phi, H.apply(phi))) * H.grid.dV)
+    return dict(x=x, prop=prop, xr=xr, coef=coef, filt=filt, eta=eta, dv=dv, tdh=tdh,
+                phi=phi, p=p, sig=sig, xx=xx, eks=eks, lo=lo, hi=hi)
+
+
+ROWS = []
+
+
+@pytest.mark.parametrize("prec", [sgw.SGW_C64, sgw.SGW_C64_BF16KB])
+def test_precision_table_si35h36(si35, si35_oracle, prec):
+    s, H = si35
+    o = si35_oracle
+    N = s.grid.N
+    ctx = make_ctx(s, prec, max_nvec=16)
+    lo, hi = o["lo"], o["hi"]
+    row = {"precision": NAMES[prec]}
+    # H psi
+    xd = torch.from_numpy(o["x"]).to(torch.complex64).cuda()
+    yd = torch.empty_like(xd)
+    ctx.apply_H(xd, yd)
+    row["hpsi"] = norm_err(yd.cpu().numpy(), H.apply(o["x"]))
+    # one propagation step
+    ctx.cheb_propagate(xd, 0.05, 1, lo, hi)
+    row["prop_step"] = norm_err(xd.cpu().numpy(), o["prop"])
+    # Fermi filter, 120 terms on real vectors packed two per complex vector
+    xr = o["xr"]
+    v = torch.from_numpy(xr[0::2] + 1j * xr[1::2]).to(torch.complex64).cuda()
+    ctx.fermi_filter(v, sgw.sgw_fermi_coefficients(-4.65, 2.0, lo, hi, 120), lo, hi)
+    f = v.cpu().numpy()
+    got = np.empty_like(o["filt"])
+    got[0::2], got[1::2] = f.real, f.imag
+    row["filter"] = norm_err(got, o["filt"])
+    # one TDH substep
+    psi = torch.zeros((1, 2, 4, N), dtype=torch.complex64, device="cuda")
+    psi[0, 0] = torch.from_numpy(o["eta"]).to(torch.complex64)
+    fv, fu, fh = ctx.fields(1), ctx.fields(1), ctx.fields(1)
+    st = ctx.tdh_state(psi, fv, fu, fh, 1, 4, 2.0 / 4)
+    ctx.tdh_init(st, torch.from_numpy(o["dv"][None]).to(torch.float32).cuda())
+    ctx.tdh_step(st, 1, 0.05)
+    g = psi.cpu().numpy()
+    row["tdh_eta"] = norm_err(g[0, 0], o["tdh"][0])
+    row["tdh_deta"] = norm_err(g[0, 1], o["tdh"][1])
+    row["tdh_u"] = rel_err(fu.cpu().numpy()[0], o["tdh"][3])
+    # Sigma_c(t), X, Sigma(omega_QP), QP energy
+    p = o["p"]
+    kw = dict(seed=p.seed, n_zeta=p.n_zeta, n_eta=p.n_eta, n_tau=p.n_tau, dt=p.dt,
+              m_sub=p.m_sub, mu=p.mu, beta=p.beta, ncoef=p.ncoef, emin=lo, emax=hi,
+              n_xi=p.n_xi, f_g=p.f_g, mode=0)
+    sig, xx, _ = ctx.sigma_estimate(o["phi"], **kw)
+    ctx.close()
+    gam = oqp.default_gamma(p.n_tau, p.dt)
+    e_o = oqp.qp_solve(o["sig"].mean(0), p.dt, gam, o["eks"], o["xx"].mean())[0]
+    e_g = oqp.qp_solve(sig.mean(0), p.dt, gam, o["eks"], xx.mean())[0]
+    row["sigma_t"] = rel_err(sig, o["sig"])
+    row["x"] = rel_err(xx, o["xx"])
+    sw_o = oqp.sigma_omega(o["sig"].mean(0), p.dt, gam, e_o)
+    sw_g = oqp.sigma_omega(sig.mean(0), p.dt, gam, e_o)
+    row["sigma_w_eV"] = abs(sw_g - sw_o) * HA_EV
+    row["eqp_eV"] = abs(e_g - e_o) * HA_EV
+    ROWS.append(row)
+    print("\nprecision table row:", {k: (f"{v:.2e}" if isinstance(v, float) else v)
+                                     for k, v in row.items()}, flush=True)
+    if prec == sgw.SGW_C64:
+        # FP32 paths: 1e-6 relative per propagation step, 1e-4 eV on QP energies
+        assert row["prop_step"] < 1e-6 and row["tdh_eta"] < 1e-6 and row["tdh_deta"] < 1e-6
+        assert row["eqp_eV"] < 1e-4
+    else:
+        # reduced precision: 1 meV on QP energies; per-step errors follow the
+        # BF16 rounding of the KB term (about 1e-3 of |V_NL psi| per application)
+        assert row["prop_step"] < 1e-4 and row["tdh_eta"] < 1e-4 and row["tdh_deta"] < 1e-4
+        assert row["eqp_eV"] < 1e-3
