@@ -250,6 +250,18 @@ sgw_status sgw_sigma_omega(const double *sigma_t, int32_t n_tau, double dt, doub
  * event time (ms), the number of timed launches and the number of grid
  * points x vectors they processed, then resets the counters. */
 sgw_status sgw_kernel_timer(sgw_ctx *ctx, int32_t enable);
+
+/* HIP graphs for repeated launch sequences.  enable != 0: a Chebyshev series
+ * of at most 64 terms (the zeta propagator, Eq. 4) runs as one captured graph
+ * per set of buffers, a longer one (the filter, Eq. 3) as a captured pair of
+ * terms that reads its coefficient from device memory, and the TDH output
+ * steps 2 .. n_tau of sgw_sigma_estimate (xi mode) as one captured step
+ * whose output row comes from a device counter.  Each sequence runs eagerly
+ * the first time (autotuning and allocation happen there) and is replayed
+ * afterwards; results are bitwise the same as without graphs.  Needs a
+ * context created on a non-default stream (SGW_EINVAL otherwise); graphs are
+ * not used while the kernel timer is on.  Synchronises the stream. */
+sgw_status sgw_use_graphs(sgw_ctx *ctx, int32_t enable);
 sgw_status sgw_kernel_timer_read(sgw_ctx *ctx, double *total_ms, int64_t *launches,
                                  int64_t *points);
 

@@ -70,10 +70,88 @@ void check_ptr(const void *p, const char *what) {
   SGW_REQUIRE(((uintptr_t)p & 15) == 0, SGW_EINVAL, std::string(what) + " is not 16-byte aligned");
 }
 
+// ---------------------------------------------------------------- graphs
+// Capture the launches of `body` on the context's stream into a graph kept
+// under `key` (nothing runs during the capture); a later call with the same
+// key gets the cached executable.  The body must not allocate, synchronise
+// or autotune: callers run the same sequence eagerly first.
+template <typename F> hipGraphExec_t captured(sgw_ctx *ctx, const std::string &key, F &&body) {
+  auto it = ctx->gexec.find(key);
+  if (it != ctx->gexec.end()) return it->second;
+  SGW_HIP(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+  try {
+    body();
+  } catch (...) {
+    hipGraph_t g = nullptr;
+    (void)hipStreamEndCapture(ctx->stream, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  hipGraph_t g = nullptr;
+  SGW_HIP(hipStreamEndCapture(ctx->stream, &g));
+  hipGraphExec_t ex = nullptr;
+  const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  SGW_HIP(e);
+  ctx->gexec[key] = ex;
+  return ex;
+}
+
+std::string ptr_key(std::initializer_list<const void *> ps) {
+  std::string k;
+  char b[24];
+  for (const void *p : ps) {
+    std::snprintf(b, sizeof b, "%p|", p);
+    k += b;
+  }
+  return k;
+}
+
+std::string num_key(std::initializer_list<double> xs) {
+  std::string k;
+  char b[32];
+  for (double x : xs) {
+    std::snprintf(b, sizeof b, "%a|", x);
+    k += b;
+  }
+  return k;
+}
+
 // ---------------------------------------------------------------- Chebyshev
+// Term k of the fused recurrence on (cur = v_k, old = v_{k-1}):
+// old <- v_{k+1}, acc += coef_k v_k.  With coef_dev the coefficient is read
+// on the device at coef_dev[d_counter[0]].
+void cheb_term(sgw_ctx *ctx, void *cur, void *old, void *acc, void *tmp, void *kbC,
+               int64_t nvec, bool first, double br, double bi, double c, double invR,
+               const double *coef_dev) {
+  const int64_t N = ctx->N;
+  const double s2 = first ? 1.0 : 2.0;
+  if (ctx->has_kb) kb_gather_e(ctx, cur, nvec, N, kbC);
+  EpiArgs e;
+  e.x = cur;
+  e.vold = old;
+  e.acc = acc;
+  e.vloc = ctx->d_vloc.p;
+  e.c = c;
+  e.invR = invR;
+  e.coef_re = br;
+  e.coef_im = bi;
+  e.first = first ? 1 : 0;
+  e.scale2 = s2;
+  e.coef_dev = coef_dev;
+  e.term_dev = coef_dev ? ctx->d_counter.as<int>() : nullptr;
+  fft3d_apply(ctx, cur, tmp, nullptr, nvec, N, MUL_KIN, 0.0, PLANE_INV_CHEB, e);
+  if (ctx->has_kb) kb_scatter(ctx, kbC, nvec, old, N, s2 * invR, 0.0, nullptr, 0.0, 0.0);
+}
+
+constexpr int SHORT_SERIES = 64;   // up to this many terms a series is one graph
+
 // out = sum_n coef_n T_n(H~) v0 over nvec vectors (ld = N) with the fused
 // recurrence; v0 and w1 are overwritten.  coef interleaved (re, im).
-// Returns the vector holding v_last (for the norm check).
+// Returns the vector holding v_last (for the norm check).  Term k works on
+// cur = v0 (k even) or w1 (k odd).  With graphs on, a short series is
+// replayed whole (one graph per set of buffers and coefficients), a long
+// one as a graph of two terms that reads its coefficients from the device.
 void *cheb_series(sgw_ctx *ctx, void *v0, void *w1, void *acc, void *tmp, int64_t nvec,
                   const std::vector<double> &coef, double emin, double emax) {
   const int nc = (int)coef.size() / 2;
@@ -83,32 +161,58 @@ void *cheb_series(sgw_ctx *ctx, void *v0, void *w1, void *acc, void *tmp, int64_
     launch_scale_copy(ctx, v0, N, acc, N, nvec, coef[0], coef[1]);
     return v0;
   }
-  void *cur = v0, *old = w1;
   void *kbC = nullptr;
   if (ctx->has_kb) kbC = ctx->buf("kbC", ctx->csize() * ctx->kb.nproj * nvec).p;
-  for (int k = 0; k + 1 < nc; ++k) {
-    const bool first = (k == 0);
-    const double s2 = first ? 1.0 : 2.0;
-    const double br = coef[2 * k], bi = coef[2 * k + 1];   // term of x = v_k
-    if (ctx->has_kb) kb_gather_e(ctx, cur, nvec, N, kbC);
-    EpiArgs e;
-    e.x = cur;
-    e.vold = old;
-    e.acc = acc;
-    e.vloc = ctx->d_vloc.p;
-    e.c = c;
-    e.invR = invR;
-    e.coef_re = br;
-    e.coef_im = bi;
-    e.first = first ? 1 : 0;
-    e.scale2 = s2;
-    fft3d_apply(ctx, cur, tmp, nullptr, nvec, N, MUL_KIN, 0.0, PLANE_INV_CHEB, e);
-    if (ctx->has_kb) kb_scatter(ctx, kbC, nvec, old, N, s2 * invR, 0.0, nullptr, 0.0, 0.0);
-    std::swap(cur, old);
+  auto cur_of = [&](int k) { return (k % 2 == 0) ? v0 : w1; };
+  auto old_of = [&](int k) { return (k % 2 == 0) ? w1 : v0; };
+  auto eager = [&](int k0, int k1) {       // terms k0 .. k1 - 1, host coefficients
+    for (int k = k0; k < k1; ++k)
+      cheb_term(ctx, cur_of(k), old_of(k), acc, tmp, kbC, nvec, k == 0, coef[2 * k],
+                coef[2 * k + 1], c, invR, nullptr);
+  };
+  auto last = [&]() {
+    launch_axpy(ctx, cur_of(nc - 1), N, acc, N, nvec, coef[2 * (nc - 1)], coef[2 * (nc - 1) + 1]);
+    return cur_of(nc - 1);
+  };
+  const bool graph = ctx->graphs && !ctx->ktimer;
+  if (!graph) {
+    eager(0, nc - 1);
+    return last();
   }
-  // the last term
-  launch_axpy(ctx, cur, N, acc, N, nvec, coef[2 * (nc - 1)], coef[2 * (nc - 1) + 1]);
-  return cur;
+  const std::string base = ptr_key({v0, w1, acc, tmp, kbC}) + num_key({(double)nvec, c, invR});
+  if (nc <= SHORT_SERIES) {
+    std::string key = "series|" + base;
+    for (double x : coef) key += num_key({x});
+    auto it = ctx->gexec.find(key);
+    if (it == ctx->gexec.end()) {
+      eager(0, nc - 1);                   // this call runs eagerly, later ones replay
+      last();
+      captured(ctx, key, [&] { eager(0, nc - 1); last(); });
+    } else {
+      SGW_HIP(hipGraphLaunch(it->second, ctx->stream));
+    }
+    return cur_of(nc - 1);
+  }
+  // long series: terms 0, 1 eagerly, then pairs (even, odd) from the graph
+  DevBuf &dc = ctx->buf("cheb_coef_dev", sizeof(double) * coef.size());
+  SGW_HIP(hipMemcpyAsync(dc.p, coef.data(), sizeof(double) * coef.size(), hipMemcpyHostToDevice,
+                         ctx->stream));
+  eager(0, 2);
+  const int npair = (nc - 3) / 2;
+  if (npair > 0) {
+    const std::string key = "pair|" + base + ptr_key({dc.p, ctx->d_counter.p});
+    hipGraphExec_t ex = captured(ctx, key, [&] {
+      for (int k = 2; k < 4; ++k) {
+        cheb_term(ctx, cur_of(k), old_of(k), acc, tmp, kbC, nvec, false, 0.0, 0.0, c, invR,
+                  dc.as<double>());
+        launch_counter(ctx, 0, 1, true);
+      }
+    });
+    launch_counter(ctx, 0, 2, false);
+    for (int p = 0; p < npair; ++p) SGW_HIP(hipGraphLaunch(ex, ctx->stream));
+  }
+  eager(2 + 2 * npair, nc - 1);
+  return last();
 }
 
 // ||v_last|| <= ||v_0|| when spec(H~) lies in [-1, 1]; growth means the
@@ -273,6 +377,8 @@ sgw_status sgw_create(const sgw_grid *grid, const double *v_loc, const sgw_proje
     }
     c->stream = static_cast<hipStream_t>(hip_stream);
     c->max_nvec = max_nvec;
+    c->d_counter.ensure(64);
+    SGW_HIP(hipMemset(c->d_counter.p, 0, 64));
     c->vloc.assign(v_loc, v_loc + c->N);
     for (double v : c->vloc) SGW_REQUIRE(std::isfinite(v), SGW_EINVAL, "v_loc has a non-finite value");
     c->vmin = *std::min_element(c->vloc.begin(), c->vloc.end());
@@ -513,6 +619,17 @@ sgw_status sgw_kernel_timer(sgw_ctx *ctx, int32_t enable) {
   return guarded(ctx, [&] { ctx->ktimer = enable != 0; });
 }
 
+sgw_status sgw_use_graphs(sgw_ctx *ctx, int32_t enable) {
+  if (!ctx) return SGW_EINVAL;
+  return guarded(ctx, [&] {
+    SGW_REQUIRE(!enable || ctx->stream != nullptr, SGW_EINVAL,
+                "graphs need a context created on a non-default stream");
+    SGW_HIP(hipStreamSynchronize(ctx->stream));
+    ctx->graphs = enable != 0;
+    if (!ctx->graphs) ctx->clear_graphs();
+  });
+}
+
 sgw_status sgw_kernel_timer_read(sgw_ctx *ctx, double *total_ms, int64_t *launches,
                                  int64_t *points) {
   if (!ctx) return SGW_EINVAL;
@@ -675,7 +792,25 @@ sgw_status sgw_sigma_estimate(sgw_ctx *ctx, const sgw_sigma_params *P, const dou
       SGW_HIP(hipEventRecord(ev[3], ctx->stream));
       // 4. TDH response, stored at the output steps
       const double tau = P->dt / P->m_sub;
+      const bool tdh_graph = ctx->graphs && !ctx->ktimer && xi && nt1 > 2;
       for (int j = 1; j < nt1; ++j) {
+        if (tdh_graph && j == 2) {
+          // output steps 2 .. n_tau replay one captured step; j on the device
+          const std::string key =
+              "tdh|" + ptr_key({st.psi, st.v, st.u, st.vh0, cR, blocks, d_ksign.p}) +
+              num_key({(double)S, (double)neta, (double)P->m_sub, tau, (double)P->n_xi,
+                       (double)nseg, amp * ctx->dV, (double)nt1});
+          hipGraphExec_t ex = captured(ctx, key, [&] {
+            tdh_substeps(ctx, &st, P->m_sub, tau, false, false);
+            launch_xi_real(ctx, st.u, blocks, d_ksign.as<uint64_t>(), S, P->n_xi, nseg,
+                           amp * ctx->dV, cR, (int64_t)nt1 * P->n_xi, 0,
+                           ctx->d_counter.as<int>() + 1, P->n_xi);
+            launch_counter(ctx, 1, 1, true);
+          });
+          launch_counter(ctx, 1, 2, false);
+          for (; j < nt1; ++j) SGW_HIP(hipGraphLaunch(ex, ctx->stream));
+          break;
+        }
         tdh_substeps(ctx, &st, P->m_sub, tau, j == 1, false);
         if (xi)
           launch_xi_real(ctx, st.u, blocks, d_ksign.as<uint64_t>(), S, P->n_xi, nseg,

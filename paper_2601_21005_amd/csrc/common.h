@@ -116,6 +116,13 @@ struct sgw_ctx {
   int kb_ntile = 0, kb_nentry = 0;
   int kb_lx = 3, kb_ly = 3;          // tile extent log2 along x and y (512 points)
 
+  // HIP graphs: repeated launch sequences (Chebyshev terms, TDH output
+  // steps) captured once and replayed; step-dependent scalars live in
+  // d_counter ([0] Chebyshev term, [1] TDH output step)
+  bool graphs = false;
+  std::map<std::string, hipGraphExec_t> gexec;
+  sgw::DevBuf d_counter;
+
   // launch timer of the inverse plane pass with the Chebyshev epilogue
   bool ktimer = false;
   std::vector<hipEvent_t> kt_events;   // pairs (start, stop)
@@ -131,6 +138,7 @@ struct sgw_ctx {
   }
   ~sgw_ctx() {
     for (auto e : kt_events) (void)hipEventDestroy(e);
+    for (auto &g : gexec) (void)hipGraphExecDestroy(g.second);
   }
 
   // autotuned kernel variants: key "name/nvec" -> variant index.  Every
@@ -171,8 +179,13 @@ struct sgw_ctx {
   sgw::DevBuf &buf(const std::string &name, size_t bytes) {
     auto &p = scratch[name];
     if (!p) p.reset(new sgw::DevBuf());
+    if (bytes > p->bytes && p->p) clear_graphs();   // captured graphs hold the old address
     p->ensure(bytes);
     return *p;
+  }
+  void clear_graphs() {
+    for (auto &g : gexec) (void)hipGraphExecDestroy(g.second);
+    gexec.clear();
   }
   size_t csize() const { return dbl ? 16 : 8; }
   size_t rsize() const { return dbl ? 8 : 4; }
@@ -205,6 +218,10 @@ struct EpiArgs {
   double coef_re = 0, coef_im = 0;  // coefficient of the new term
   int first = 0;              // CHEB: v_1 = H~ v_0 (no v_{n-1} term)
   double scale2 = 2.0;        // CHEB: factor of H~ v_n (2, or 1 when first)
+  // CHEB inside a replayed graph: the coefficient is coef_dev[term_dev[0]]
+  // (interleaved re, im; FP64), read when the pass runs
+  const double *coef_dev = nullptr;
+  const int *term_dev = nullptr;
 };
 
 // Full forward+multiply+inverse 3D transform of nvec vectors of `src` (ld),

@@ -383,7 +383,8 @@ template <typename R>
 __global__ __launch_bounds__(NT) void k_xi_real(const R *u, const int *blocks,
                                                 const uint64_t *skeys, int n_xi, int nseg,
                                                 int64_t N, R amp_dv, R *out,
-                                                int64_t out_stride_s, int64_t out_off) {
+                                                int64_t out_stride_s, int64_t out_off,
+                                                const int *step_dev, int64_t step_stride) {
   const int lane = threadIdx.x & 63;
   const int64_t m = (int64_t)blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
   const int s = blockIdx.y;
@@ -399,7 +400,8 @@ __global__ __launch_bounds__(NT) void k_xi_real(const R *u, const int *blocks,
     acc += ((w >> p) & 1ull) ? -val : val;
   }
   acc = wave_sum(acc);
-  if (lane == 0) out[s * out_stride_s + out_off + m] = amp_dv * acc;
+  const int64_t off = out_off + (step_dev ? (int64_t)step_dev[0] * step_stride : 0);
+  if (lane == 0) out[s * out_stride_s + off + m] = amp_dv * acc;
 }
 
 template <typename R>
@@ -435,16 +437,18 @@ __global__ __launch_bounds__(NT) void k_xi_zeta(const cplx<R> *zeta, const R *ph
 
 void launch_xi_real(sgw_ctx *ctx, const void *u, const int *blocks, const uint64_t *d_sign_keys,
                     int S, int n_xi, int nseg, double amp_dv, void *out, int64_t out_stride_s,
-                    int64_t out_off) {
+                    int64_t out_off, const int *step_dev, int64_t step_stride) {
   const dim3 g((n_xi + 3) / 4, S);
   if (ctx->dbl)
     hipLaunchKernelGGL(k_xi_real<double>, g, dim3(NT), 0, ctx->stream,
                        static_cast<const double *>(u), blocks, d_sign_keys, n_xi, nseg, ctx->N,
-                       amp_dv, static_cast<double *>(out), out_stride_s, out_off);
+                       amp_dv, static_cast<double *>(out), out_stride_s, out_off, step_dev,
+                       step_stride);
   else
     hipLaunchKernelGGL(k_xi_real<float>, g, dim3(NT), 0, ctx->stream,
                        static_cast<const float *>(u), blocks, d_sign_keys, n_xi, nseg, ctx->N,
-                       (float)amp_dv, static_cast<float *>(out), out_stride_s, out_off);
+                       (float)amp_dv, static_cast<float *>(out), out_stride_s, out_off,
+                       step_dev, step_stride);
   SGW_HIP(hipGetLastError());
 }
 
@@ -620,6 +624,21 @@ void launch_contract_exact(sgw_ctx *ctx, const void *uto, const void *zeta, cons
                        static_cast<const float *>(phi), nt1, j, ctx->N, d_partial, nblk);
   hipLaunchKernelGGL(k_contract_exact2, dim3((S * 4 + NT - 1) / NT), dim3(NT), 0, ctx->stream,
                      d_partial, nblk, S, nt1, j, ctx->dV, d_sig);
+  SGW_HIP(hipGetLastError());
+}
+
+}  // namespace sgw
+
+namespace sgw {
+
+// device step counters of replayed graphs (vector stores from one lane)
+__global__ void k_counter(int *c, int idx, int value, int add) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) c[idx] = add ? c[idx] + value : value;
+}
+
+void launch_counter(sgw_ctx *ctx, int idx, int value, bool add) {
+  hipLaunchKernelGGL(k_counter, dim3(1), dim3(64), 0, ctx->stream,
+                     ctx->d_counter.as<int>(), idx, value, add ? 1 : 0);
   SGW_HIP(hipGetLastError());
 }
 

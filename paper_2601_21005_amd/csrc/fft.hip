@@ -66,7 +66,12 @@ __device__ __forceinline__ void epilogue(const PassArgs &a, int64_t v, int64_t r
       nv.y = s2 * w.y;
       C *vold = static_cast<C *>(a.e.vold);
       C *acc = static_cast<C *>(a.e.acc);
-      const R br = (R)a.e.coef_re, bi = (R)a.e.coef_im;
+      R br = (R)a.e.coef_re, bi = (R)a.e.coef_im;
+      if (a.e.coef_dev) {
+        const int k = a.e.term_dev[0];
+        br = (R)a.e.coef_dev[2 * k];
+        bi = (R)a.e.coef_dev[2 * k + 1];
+      }
       C s;
       if (!a.e.first) {
         const C p = vold[o];

