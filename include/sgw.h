@@ -266,6 +266,27 @@ sgw_status sgw_kernel_timer_read(sgw_ctx *ctx, double *total_ms, int64_t *launch
                                  int64_t *points);
 
 
+/* Many clusters of uneven size in one call.  Each item is one
+ * sgw_sigma_estimate on its own context; the items are ordered by an
+ * estimate of their work (grid points x log, filter, TDH and propagation
+ * vectors) and dealt, longest first, to `nworkers` host threads (each item
+ * to the least-loaded thread).  Each thread issues its items in turn, so
+ * items on contexts with different streams run concurrently on the GPU.
+ * Every item needs its own context (SGW_EINVAL otherwise).  Per item:
+ * status and wall time (ms) are written back; the call returns SGW_OK or
+ * the status of the first failed item (in item order).  phase timings are
+ * not recorded. */
+typedef struct {
+  sgw_ctx *ctx;
+  const sgw_sigma_params *params;
+  const double *phi;        /* host [N] */
+  double *sigma_t;          /* host [n_zeta][2 n_tau + 1][2] */
+  double *x;                /* host [n_zeta] */
+  sgw_status status;        /* out */
+  double ms;                /* out */
+} sgw_batch_item;
+sgw_status sgw_batch_sigma_estimate(sgw_batch_item *items, int32_t n, int32_t nworkers);
+
 /* ---------------------------------------------------------------------------
  * Learned control variate (an addition to the paper's Monte Carlo average,
  * Sec. 3: samples are averaged until the QP error bar is below 0.03 eV).

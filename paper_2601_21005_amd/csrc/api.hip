@@ -4,6 +4,9 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <chrono>
+#include <numeric>
+#include <thread>
 
 #include "common.h"
 #include "kernels.h"
@@ -885,6 +888,53 @@ sgw_status sgw_sigma_estimate(sgw_ctx *ctx, const sgw_sigma_params *P, const dou
     if (phase_ms)
       for (int i = 0; i < 6; ++i) phase_ms[i] = ph[i];
   });
+}
+
+// ------------------------------------------------------------------ batch
+sgw_status sgw_batch_sigma_estimate(sgw_batch_item *items, int32_t n, int32_t nworkers) {
+  if (!items || n < 0 || nworkers < 1) return SGW_EINVAL;
+  for (int i = 0; i < n; ++i) {
+    if (!items[i].ctx || !items[i].params) return SGW_EINVAL;
+    for (int j = 0; j < i; ++j)
+      if (items[j].ctx == items[i].ctx) return SGW_EINVAL;   // one context per item
+  }
+  // longest processing time first: cost ~ N log N x (filter terms x filter
+  // vectors + TDH substeps x TDH vectors + propagation steps x 2 x terms)
+  std::vector<double> cost(n);
+  for (int i = 0; i < n; ++i) {
+    const sgw_sigma_params *P = items[i].params;
+    const double N = (double)items[i].ctx->N;
+    const double fv = 0.5 * P->n_zeta * (1.0 + P->n_eta);
+    const double work = P->ncoef * fv + 2.0 * P->n_zeta * P->n_eta * P->n_tau * P->m_sub * 3.0 +
+                        2.0 * P->n_zeta * P->n_tau * 16.0;
+    cost[i] = N * std::log2(std::max(2.0, N)) * work;
+  }
+  std::vector<int> order(n);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  const int nw = std::max(1, std::min<int>(nworkers, n));
+  std::vector<std::vector<int>> plan(nw);
+  std::vector<double> load(nw, 0.0);
+  for (int i : order) {
+    const int w = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    plan[w].push_back(i);
+    load[w] += cost[i];
+  }
+  auto run = [&](int w) {
+    for (int i : plan[w]) {
+      sgw_batch_item &it = items[i];
+      const auto t0 = std::chrono::steady_clock::now();
+      it.status = sgw_sigma_estimate(it.ctx, it.params, it.phi, it.sigma_t, it.x, nullptr);
+      it.ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+  };
+  std::vector<std::thread> th;
+  for (int w = 1; w < nw; ++w) th.emplace_back(run, w);
+  if (nw > 0 && n > 0) run(0);
+  for (auto &t : th) t.join();
+  for (int i = 0; i < n; ++i)
+    if (items[i].status != SGW_OK) return items[i].status;
+  return SGW_OK;
 }
 
 }  // extern "C"

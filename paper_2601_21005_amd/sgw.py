@@ -25,7 +25,7 @@ EXPORTS = ["sgw_create", "sgw_destroy", "sgw_last_error", "sgw_bounds", "sgw_app
            "sgw_fermi_coefficients", "sgw_fermi_filter", "sgw_propagator_coefficients",
            "sgw_cheb_propagate", "sgw_tdh_init", "sgw_tdh_step", "sgw_sigma_estimate",
            "sgw_qp_solve", "sgw_sigma_omega", "sgw_kernel_timer", "sgw_kernel_timer_read",
-           "sgw_use_graphs", "sgw_cv_features", "sgw_mlp_create", "sgw_mlp_destroy", "sgw_mlp_last_error",
+           "sgw_use_graphs", "sgw_batch_sigma_estimate", "sgw_cv_features", "sgw_mlp_create", "sgw_mlp_destroy", "sgw_mlp_last_error",
            "sgw_mlp_set_standardization", "sgw_mlp_get_params", "sgw_mlp_forward",
            "sgw_mlp_gradient", "sgw_mlp_adam", "sgw_mlp_train", "sgw_cv_cheap_moments",
            "sgw_cv_estimate"]
@@ -60,6 +60,12 @@ class SgwSigmaParams(C.Structure):
                 ("ncoef", C.c_int32), ("emin", C.c_double), ("emax", C.c_double),
                 ("n_xi", C.c_int32), ("f_g", C.c_double), ("mode", C.c_int32),
                 ("prop_tol", C.c_double), ("n_ft", C.c_int32), ("batch", C.c_int32)]
+
+
+class SgwBatchItem(C.Structure):
+    _fields_ = [("ctx", C.c_void_p), ("params", C.POINTER(SgwSigmaParams)),
+                ("phi", C.POINTER(C.c_double)), ("sigma_t", C.POINTER(C.c_double)),
+                ("x", C.POINTER(C.c_double)), ("status", C.c_int), ("ms", C.c_double)]
 
 
 class SgwCvResult(C.Structure):
@@ -106,6 +112,7 @@ def load():
     lib.sgw_sigma_omega.argtypes = [dp, i32, d, d, dp, i32, dp]
     lib.sgw_kernel_timer.argtypes = [vp, i32]
     lib.sgw_use_graphs.argtypes = [vp, i32]
+    lib.sgw_batch_sigma_estimate.argtypes = [C.POINTER(SgwBatchItem), i32, i32]
     lib.sgw_kernel_timer_read.argtypes = [vp, dp, C.POINTER(i64), C.POINTER(i64)]
     u64, fp = C.c_uint64, C.c_void_p
     lib.sgw_cv_features.argtypes = [vp, fp, i32, i64, u64, i64, i64, fp]
@@ -303,10 +310,8 @@ class Context:
     def sigma_estimate(self, phi, seed, n_zeta, n_eta, n_tau, dt, m_sub, mu, beta, ncoef,
                        emin, emax, n_xi=10000, f_g=0.003, mode=0, prop_tol=1e-14, n_ft=0,
                        first_sample=0, batch=0):
-        p = SgwSigmaParams(int(seed), int(first_sample), int(n_zeta), int(n_eta), int(n_tau),
-                           float(dt), int(m_sub), float(mu), float(beta), int(ncoef),
-                           float(emin), float(emax), int(n_xi), float(f_g), int(mode),
-                           float(prop_tol), int(n_ft), int(batch))
+        p = sigma_params(seed, n_zeta, n_eta, n_tau, dt, m_sub, mu, beta, ncoef, emin, emax,
+                         n_xi, f_g, mode, prop_tol, n_ft, first_sample, batch)
         ph = np.ascontiguousarray(np.asarray(phi, dtype=np.float64).ravel())
         sig = np.zeros((n_zeta, 2 * n_tau + 1, 2))
         x = np.zeros(n_zeta)
@@ -430,3 +435,44 @@ class Mlp:
         _check_mlp(load().sgw_mlp_train(self.mlp, _fdev(x, "x", n * self.din), _fdev(y, "y", n),
                                         n, int(steps), lr, _dptr(hist)), self.mlp)
         return hist[:steps]
+
+
+# ------------------------------------------------------------------ batches
+def sigma_params(seed, n_zeta, n_eta, n_tau, dt, m_sub, mu, beta, ncoef, emin, emax,
+                 n_xi=10000, f_g=0.003, mode=0, prop_tol=1e-14, n_ft=0, first_sample=0,
+                 batch=0):
+    return SgwSigmaParams(int(seed), int(first_sample), int(n_zeta), int(n_eta), int(n_tau),
+                          float(dt), int(m_sub), float(mu), float(beta), int(ncoef),
+                          float(emin), float(emax), int(n_xi), float(f_g), int(mode),
+                          float(prop_tol), int(n_ft), int(batch))
+
+
+def batch_sigma_estimate(jobs, nworkers=4):
+    """jobs: list of (Context, phi, dict of sigma_estimate keywords).  Returns
+    a list of (sigma_t, x, wall ms) in job order; raises on the first failed
+    item after all have run."""
+    items = (SgwBatchItem * len(jobs))()
+    keep = []
+    outs = []
+    for i, (ctx, phi, kw) in enumerate(jobs):
+        p = sigma_params(**kw)
+        ph = np.ascontiguousarray(np.asarray(phi, dtype=np.float64).ravel())
+        sig = np.zeros((kw["n_zeta"], 2 * kw["n_tau"] + 1, 2))
+        x = np.zeros(kw["n_zeta"])
+        keep += [p, ph]
+        outs.append((sig, x))
+        items[i].ctx = ctx.ctx
+        items[i].params = C.pointer(p)
+        items[i].phi = _dptr(ph)
+        items[i].sigma_t = _dptr(sig)
+        items[i].x = _dptr(x)
+    for i in range(len(jobs)):
+        items[i].status = SGW_EINVAL           # overwritten by every item that runs
+    code = load().sgw_batch_sigma_estimate(items, len(jobs), int(nworkers))
+    if code != SGW_OK:
+        ran = [i for i in range(len(jobs)) if items[i].ms > 0]
+        bad = [i for i in ran if items[i].status != SGW_OK]
+        if bad:
+            _check(items[bad[0]].status, jobs[bad[0]][0].ctx)
+        raise SgwError(code, "batch rejected: every item needs its own context")
+    return [(o[0][..., 0] + 1j * o[0][..., 1], o[1], items[i].ms) for i, o in enumerate(outs)]

@@ -46,7 +46,8 @@ def test_struct_layouts_match_header(tmp_path):
     if not shutil.which("gcc"):
         pytest.skip("gcc not available")
     structs = {"sgw_grid": sgw.SgwGrid, "sgw_projectors": sgw.SgwProjectors,
-               "sgw_tdh_state": sgw.SgwTdhState, "sgw_sigma_params": sgw.SgwSigmaParams}
+               "sgw_tdh_state": sgw.SgwTdhState, "sgw_sigma_params": sgw.SgwSigmaParams,
+               "sgw_batch_item": sgw.SgwBatchItem, "sgw_cv_result": sgw.SgwCvResult}
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"',
              "int main(void) {"]
     for cname, py in structs.items():

@@ -77,3 +77,39 @@ def test_graphs_need_a_stream(tiny8):
         ctx.use_graphs(True)
     assert e.value.code == sgw.SGW_EINVAL
     ctx.close()
+
+
+def test_uneven_batch_matches_sequential(tiny8, tiny12l, cfg1):
+    """Three clusters of different grids (8^3 with KB, 12^3 local, 32^3
+    local) and sizes on three streams through the batch call: each result is
+    bitwise the one from its own sequential call."""
+    cases = []
+    for (s, H), neta, nz in ((tiny8, 4, 3), (tiny12l, 8, 2), (cfg1, 4, 2)):
+        st = torch.cuda.Stream()
+        ctx = ctx_on_stream(s, sgw.SGW_C64, st, max_nvec=16)
+        lo, hi = ctx.bounds()
+        rs = np.random.default_rng(s.grid.N)
+        phi = rs.standard_normal(s.grid.N)
+        phi /= np.sqrt(s.grid.h ** 3 * np.sum(phi * phi))
+        kw = dict(seed=62, n_zeta=nz, n_eta=neta, n_tau=5, dt=0.1, m_sub=1, mu=-1.0,
+                  beta=4.0, ncoef=90, emin=lo, emax=hi, n_xi=32, f_g=0.25, mode=0)
+        cases.append((ctx, phi, kw))
+    seq = [c[0].sigma_estimate(c[1], **c[2]) for c in cases]
+    bat = sgw.batch_sigma_estimate(cases, nworkers=3)
+    for (s1, x1, _), (s2, x2, ms) in zip(seq, bat):
+        assert np.array_equal(s1, s2) and np.array_equal(x1, x2)
+        assert ms > 0
+    for c in cases:
+        c[0].close()
+
+
+def test_batch_rejects_a_shared_context(tiny8):
+    s, _ = tiny8
+    ctx = make_ctx(s, sgw.SGW_C64)
+    lo, hi = ctx.bounds()
+    kw = dict(seed=1, n_zeta=1, n_eta=2, n_tau=2, dt=0.1, m_sub=1, mu=-1.0, beta=4.0,
+              ncoef=10, emin=lo, emax=hi, n_xi=8, f_g=0.25, mode=0)
+    phi = np.ones(s.grid.N)
+    with pytest.raises(sgw.SgwError):
+        sgw.batch_sigma_estimate([(ctx, phi, kw), (ctx, phi, kw)])
+    ctx.close()
