@@ -364,6 +364,15 @@ sgw_status sgw_create(const sgw_grid *grid, const double *v_loc, const sgw_proje
     c->ecut = grid->ecut > 0 ? grid->ecut : 0.0;
     c->prec = prec;
     c->dbl = dbl;
+    {
+      int dev = 0;
+      hipDeviceProp_t prop;
+      SGW_HIP(hipGetDevice(&dev));
+      SGW_HIP(hipGetDeviceProperties(&prop, dev));
+      c->arch = prop.gcnArchName;
+      const size_t colon = c->arch.find(':');           // drop feature suffixes
+      if (colon != std::string::npos) c->arch.resize(colon);
+    }
     if (const char *fc = std::getenv("SGW_FILTER_CHUNK")) c->filter_chunk = std::atoi(fc);
     if (const char *fv = std::getenv("SGW_FORCE_VARIANT")) {
       // "name=i,name=i": pin autotuned kernel variants (testing)

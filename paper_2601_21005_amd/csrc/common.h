@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <cstdio>
 #include <map>
@@ -85,6 +86,12 @@ struct KBHost {
   std::vector<double> gram;         // [nproj][nproj] S = <beta_p|beta_q>
 };
 
+// ---------------------------------------------------------------- autotuner cache
+// Process-wide map of tuned kernel choices, loaded from and saved to the JSON
+// file named by SGW_TUNE_CACHE (no file: memory only).  Thread-safe.
+bool tune_cache_lookup(const std::string &key, int &choice);
+void tune_cache_store(const std::string &key, int choice);
+
 // ---------------------------------------------------------------- context
 struct Plan;  // FFT dispatch (sizes, kernels)
 
@@ -146,31 +153,48 @@ struct sgw_ctx {
   std::map<std::string, int> tuned;
   std::map<std::string, int> forced;   // from SGW_FORCE_VARIANT="name=i,name=i"
   int64_t filter_chunk = 0;            // vectors per filter chunk (0: the whole batch)
+  // Persistent choices: with SGW_TUNE_CACHE=<file> the choice of every
+  // (arch, kernel, grid, precision, batch width) is read from and appended
+  // to a JSON object in that file, so later runs select without timing.
+  std::string arch;                    // gcnArchName of the device
+  std::string tune_key(const char *name, int64_t nvec) const {
+    return arch + "/" + name + "/" + std::to_string(nx) + "x" + std::to_string(ny) + "x" +
+           std::to_string(nz) + "/p" + std::to_string((int)prec) + "/" + std::to_string(nvec);
+  }
+  // Time every variant twice (the second run counts) and keep the lowest
+  // index whose time is within 3% of the fastest.
   template <typename F> int tune(const char *name, int64_t nvec, int nvar, F &&trial) {
     const auto fit = forced.find(name);
     if (fit != forced.end() && fit->second >= 0 && fit->second < nvar) return fit->second;
-    const std::string key = std::string(name) + "/" + std::to_string(nvec);
+    const std::string key = tune_key(name, nvec);
     const auto it = tuned.find(key);
     if (it != tuned.end()) return it->second;
+    int cached = -1;
+    if (sgw::tune_cache_lookup(key, cached) && cached >= 0 && cached < nvar) {
+      tuned[key] = cached;
+      return cached;
+    }
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
       throw sgw::Error{SGW_EHIP, "hipEventCreate failed"};
-    int best = 0;
-    float best_ms = 1e30f;
+    std::vector<float> ms(nvar, 1e30f);
     for (int i = 0; i < nvar; ++i) {
       trial(i);                               // warm-up
       (void)hipEventRecord(e0, stream);
       trial(i);
       (void)hipEventRecord(e1, stream);
       (void)hipEventSynchronize(e1);
-      float ms = 0;
-      (void)hipEventElapsedTime(&ms, e0, e1);
-      if (hipGetLastError() != hipSuccess) continue;
-      if (ms < best_ms) { best_ms = ms; best = i; }
+      float t = 0;
+      (void)hipEventElapsedTime(&t, e0, e1);
+      if (hipGetLastError() == hipSuccess) ms[i] = t;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    const float best_ms = *std::min_element(ms.begin(), ms.end());
+    int best = 0;
+    while (best + 1 < nvar && ms[best] > 1.03f * best_ms) ++best;
     tuned[key] = best;
+    sgw::tune_cache_store(key, best);
     return best;
   }
 

@@ -4,6 +4,10 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <cstdlib>
+#include <fstream>
+#include <mutex>
+#include <sstream>
 
 #include "common.h"
 
@@ -397,6 +401,75 @@ int qp_solve(const double *sig, int n_tau, double dt, double gamma, double eks, 
     }
   }
   return -1;
+}
+
+
+// ---------------------------------------------------------------- tuner cache
+// The file holds one flat JSON object {"key": choice, ...} with keys made of
+// [A-Za-z0-9_/x.:+-] only, written whole after every new entry.
+namespace {
+std::mutex g_tune_mu;
+std::map<std::string, int> g_tune;
+bool g_tune_loaded = false;
+
+const char *tune_path() {
+  const char *p = std::getenv("SGW_TUNE_CACHE");
+  return (p && *p) ? p : nullptr;
+}
+
+void tune_load_locked() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char *path = tune_path();
+  if (!path) return;
+  std::ifstream f(path);
+  if (!f) return;
+  std::stringstream ss;
+  ss << f.rdbuf();
+  const std::string t = ss.str();
+  size_t i = 0;
+  while (true) {
+    const size_t q0 = t.find('"', i);
+    if (q0 == std::string::npos) break;
+    const size_t q1 = t.find('"', q0 + 1);
+    if (q1 == std::string::npos) break;
+    const size_t colon = t.find(':', q1);
+    if (colon == std::string::npos) break;
+    char *end = nullptr;
+    const long v = std::strtol(t.c_str() + colon + 1, &end, 10);
+    if (end == t.c_str() + colon + 1) break;
+    g_tune[t.substr(q0 + 1, q1 - q0 - 1)] = (int)v;
+    i = (size_t)(end - t.c_str());
+  }
+}
+}  // namespace
+
+bool tune_cache_lookup(const std::string &key, int &choice) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  tune_load_locked();
+  const auto it = g_tune.find(key);
+  if (it == g_tune.end()) return false;
+  choice = it->second;
+  return true;
+}
+
+void tune_cache_store(const std::string &key, int choice) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  tune_load_locked();
+  g_tune[key] = choice;
+  const char *path = tune_path();
+  if (!path) return;
+  const std::string tmp = std::string(path) + ".tmp";
+  {
+    std::ofstream f(tmp, std::ios::trunc);
+    if (!f) return;                      // the cache is an optimisation: never an error
+    f << "{\n";
+    size_t n = 0;
+    for (const auto &kv : g_tune)
+      f << "  \"" << kv.first << "\": " << kv.second << (++n < g_tune.size() ? ",\n" : "\n");
+    f << "}\n";
+  }
+  std::rename(tmp.c_str(), path);
 }
 
 }  // namespace sgw

@@ -113,3 +113,33 @@ def test_batch_rejects_a_shared_context(tiny8):
     with pytest.raises(sgw.SgwError):
         sgw.batch_sigma_estimate([(ctx, phi, kw), (ctx, phi, kw)])
     ctx.close()
+
+
+def test_tune_cache_file(tmp_path):
+    """With SGW_TUNE_CACHE set, a fresh process writes its KB kernel choices
+    (keyed by arch, kernel, grid, precision and batch width) to the file, and
+    a second process reads them back and gives the same result."""
+    import json
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    path = tmp_path / "tune.json"
+    code = ("import sys, numpy as np, torch; sys.path.insert(0, %r)\n"
+            "from paper_2601_21005_amd import sgw, systems\n"
+            "s = systems.tiny_system(8, 0.7)\n"
+            "ctx = sgw.Context(8, 0.7, s.v_loc, s.projectors, precision=sgw.SGW_C64)\n"
+            "x = torch.ones((24, 512), dtype=torch.complex64, device='cuda')\n"
+            "y = torch.empty_like(x); ctx.apply_H(x, y)\n"
+            "np.save(sys.argv[1], y.cpu().numpy())\n" % root)
+    env = dict(os.environ, SGW_TUNE_CACHE=str(path))
+    outs = []
+    for k in range(2):
+        out = tmp_path / f"y{k}.npy"
+        subprocess.run([sys.executable, "-c", code, str(out)], env=env, check=True, timeout=300)
+        outs.append(np.load(out))
+        entries = json.loads(path.read_text())
+        keys = [k for k in entries if "/kb_gather/8x8x8/p1/24" in k or "/kb_scatter/8x8x8/p1/24" in k]
+        assert len(keys) == 2, entries
+        assert all(k.startswith("gfx") for k in keys)
+    assert np.array_equal(outs[0], outs[1])
