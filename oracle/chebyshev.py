@@ -9,9 +9,16 @@
 
 Readings:
 * Filter function: a Fermi function F(E) = 1 / (1 + exp(beta (E - mu))) with
-  mu mid-gap stands in for the Heaviside step (the sharp limit beta -> inf);
-  the gapped least-squares variant of the paper's reference [gapfilter] is a
-  separate, later item.
+  mu mid-gap stands in for the Heaviside step (the sharp limit beta -> inf).
+* Gapped filter (Sec. 2.1: the cutoff is spread over the band gap
+  E_HOMO <= mu <= E_LUMO instead of sitting at one mu; the coefficient
+  construction itself is in a reference the paper cites and does not
+  restate).  Reading: the Gaussian-smoothed step
+      G(E) = erfc((E - mu) / sigma) / 2,  mu = (E_HOMO + E_LUMO) / 2,
+      sigma = (E_LUMO - E_HOMO) / (2 erfcinv(2 eps)),
+  which is 1 - eps at E_HOMO and eps at E_LUMO and within eps of the step
+  everywhere outside the gap; being entire, its Chebyshev coefficients decay
+  faster than those of a Fermi function with the same edge values.
 * Coefficients by Chebyshev-Gauss quadrature with M = 4 * ncoef nodes:
       a_n = (2 - delta_n0) / M  sum_j F(c + R cos theta_j) cos(n theta_j),
       theta_j = pi (j + 1/2) / M.
@@ -22,7 +29,7 @@ Readings:
 """
 import numpy as np
 from scipy.fft import dct
-from scipy.special import expit, jv
+from scipy.special import erfc, erfcinv, expit, jv
 
 
 def fermi(E, mu, beta):
@@ -47,6 +54,34 @@ def fermi_coefficients(mu, beta, emin, emax, ncoef):
     a = y[:ncoef] / M
     a[0] *= 0.5
     return a
+
+
+def gapped_step(E, e_homo, e_lumo, eps):
+    """G(E): 1 - eps at e_homo, eps at e_lumo, erfc-shaped in between."""
+    mu = 0.5 * (e_homo + e_lumo)
+    sigma = (e_lumo - e_homo) / (2.0 * erfcinv(2.0 * eps))
+    return 0.5 * erfc((np.asarray(E, dtype=np.float64) - mu) / sigma)
+
+
+def gapped_coefficients(e_homo, e_lumo, eps, emin, emax, ncoef):
+    """a_0 .. a_{ncoef-1} of the gapped filter, same quadrature as the Fermi
+    filter."""
+    c, R = cheb_map(emin, emax)
+    M = 4 * int(ncoef)
+    theta = np.pi * (np.arange(M) + 0.5) / M
+    y = dct(gapped_step(c + R * np.cos(theta), e_homo, e_lumo, eps), type=2)
+    a = y[:ncoef] / M
+    a[0] *= 0.5
+    return a
+
+
+def tail_length(a, tol):
+    """Smallest N with sum_{n >= N} |a_n| < tol."""
+    tail = np.cumsum(np.abs(a[::-1]))[::-1]
+    ok = np.nonzero(tail < tol)[0]
+    if ok.size == 0:
+        raise ValueError("coefficients too short for the requested tolerance")
+    return int(ok[0])
 
 
 def suggested_ncoef(mu, beta, emin, emax, tol=1e-10, nmax=65536):

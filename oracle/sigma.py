@@ -55,6 +55,10 @@ class SGWParams:
     prop_tol: float = 1e-14
     n_ft: int = None
     first_sample: int = 0
+    filter: str = "fermi"     # "fermi" (mu, beta) or "gapped" (e_homo, e_lumo, eps)
+    e_homo: float = 0.0
+    e_lumo: float = 0.0
+    filter_eps: float = 1e-7
 
 
 def white_noise_sets(grid, p: SGWParams, i):
@@ -84,7 +88,10 @@ def sample_sigma(H, phi, p: SGWParams, i, return_parts=False,
     zb = zb_rng if zb is None else np.asarray(zb, dtype=np.float64)
 
     # 2. filter (both sets with the same F, Sec. 2.1)
-    a = cheb.fermi_coefficients(p.mu, p.beta, p.emin, p.emax, p.ncoef)
+    if p.filter == "gapped":
+        a = cheb.gapped_coefficients(p.e_homo, p.e_lumo, p.filter_eps, p.emin, p.emax, p.ncoef)
+    else:
+        a = cheb.fermi_coefficients(p.mu, p.beta, p.emin, p.emax, p.ncoef)
     if eta_det is None:
         filt = cheb.apply_series(H, a, p.emin, p.emax, np.vstack([zb[None], eb]))
         z_occ, eta = filt[0], filt[1:]

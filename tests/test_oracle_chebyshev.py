@@ -95,3 +95,48 @@ def test_free_particle_packet():
         var = rho @ (dd * dd)
         assert np.max(np.abs(mean)) < 1e-5
         assert np.allclose(var, s0 ** 2 + (t / (2 * s0)) ** 2, rtol=1e-6)
+
+
+def test_gapped_step_edges_and_symmetry():
+    """G(E_HOMO) = 1 - eps, G(E_LUMO) = eps, G(mu + x) = 1 - G(mu - x), and
+    G stays within eps of the step outside the gap."""
+    eh, el, eps = -0.7, -0.2, 1e-7
+    assert abs(cheb.gapped_step(eh, eh, el, eps) - (1 - eps)) < 1e-15
+    assert abs(cheb.gapped_step(el, eh, el, eps) - eps) < 1e-20
+    x = np.linspace(0, 3, 301)
+    mu = 0.5 * (eh + el)
+    assert np.allclose(cheb.gapped_step(mu + x, eh, el, eps),
+                       1 - cheb.gapped_step(mu - x, eh, el, eps), rtol=0, atol=1e-15)
+    E = np.concatenate([np.linspace(-10, eh, 500), np.linspace(el, 10, 500)])
+    step = (E < mu).astype(float)
+    assert np.max(np.abs(cheb.gapped_step(E, eh, el, eps) - step)) <= eps * (1 + 1e-12)
+
+
+def test_gapped_reconstruction_and_shorter_than_fermi():
+    """The series reproduces G to its discarded tail, and for the same edge
+    accuracy (1e-7 at the gap edges) it is shorter than the Fermi series."""
+    emin, emax, eh, el, eps = -5.0, 60.0, -0.7, -0.2, 1e-7
+    a = cheb.gapped_coefficients(eh, el, eps, emin, emax, 8192)
+    N = cheb.tail_length(a, 1e-9)
+    c, R = cheb.cheb_map(emin, emax)
+    x = np.linspace(-1, 1, 50001)
+    err = np.max(np.abs(cheb.cheb_series_scalar(a[:N], x) - cheb.gapped_step(c + R * x, eh, el, eps)))
+    assert err < 2e-9
+    beta = 2 * np.log((1 - eps) / eps) / (el - eh)       # Fermi with the same edge values
+    assert abs(cheb.fermi(el, 0.5 * (eh + el), beta) - eps) < 1e-12
+    nf = cheb.suggested_ncoef(0.5 * (eh + el), beta, emin, emax, tol=1e-9, nmax=16384)
+    assert N < 0.6 * nf, (N, nf)
+
+
+def test_gapped_filter_matches_eigendecomposition(tiny12, tiny12_eig):
+    s, H = tiny12
+    e, V = tiny12_eig
+    emin, emax = H.bounds()
+    eh, el = e[1], e[2]
+    a = cheb.gapped_coefficients(eh, el, 1e-6, emin, emax, 4096)
+    N = cheb.tail_length(a, 1e-12)
+    x = np.random.default_rng(4).standard_normal((2, H.grid.N))
+    out = cheb.apply_series(H, a[:N], emin, emax, x)
+    f = cheb.gapped_step(e, eh, el, 1e-6)
+    exact = ((x @ V.T) * H.grid.dV * f[None, :]) @ V
+    assert np.max(np.abs(out - exact)) <= 1e-11 * np.max(np.abs(x)) * 10
