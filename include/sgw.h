@@ -130,6 +130,15 @@ sgw_status sgw_apply_H(sgw_ctx *ctx, const void *psi, void *hpsi,
 sgw_status sgw_fermi_coefficients(double mu, double beta, double emin,
                                   double emax, int32_t ncoef, double *coef);
 
+/* Chebyshev coefficients of the gapped filter (Sec. 2.1: the cutoff is
+ * spread over the band gap E_HOMO <= mu <= E_LUMO): the step
+ * G(E) = erfc((E - mu)/sigma)/2, mu = (e_homo + e_lumo)/2,
+ * sigma = (e_lumo - e_homo)/(2 erfcinv(2 eps)), so G = 1 - eps at e_homo
+ * and eps at e_lumo; same quadrature as sgw_fermi_coefficients.  Needs
+ * e_homo < e_lumo and 0 < eps < 0.5.  Pure host computation. */
+sgw_status sgw_gapped_coefficients(double e_homo, double e_lumo, double eps, double emin,
+                                   double emax, int32_t ncoef, double *coef);
+
 /* In place: v[k] <- sum_{n<ncoef} coef[n] T_n((H - c)/R) v[k] (Eq. 3) for
  * k < nvec, by the three-term recurrence.  The filter is real, so complex
  * vectors may carry two real orbitals each (real and imaginary parts).
@@ -201,7 +210,7 @@ typedef struct {
   int32_t n_tau;          /* output time steps on each side of t = 0 */
   double dt;              /* output time step, a.u. */
   int32_t m_sub;          /* TDH Strang substeps per output step */
-  double mu, beta;        /* Fermi filter */
+  double mu, beta;        /* Fermi filter (filter = 0) */
   int32_t ncoef;          /* filter length */
   double emin, emax;      /* spectral interval for every Chebyshev map */
   int32_t n_xi;           /* sparse stochastic functions per sample */
@@ -211,6 +220,10 @@ typedef struct {
   int32_t n_ft;           /* time-ordering FFT length (0: smallest power of
                              two >= 4 (n_tau + 1)) */
   int32_t batch;          /* samples resident on the device at once (0: all) */
+  int32_t filter;         /* 0: Fermi (mu, beta); 1: gapped (e_homo, e_lumo,
+                             filter_eps), see sgw_gapped_coefficients */
+  double e_homo, e_lumo;  /* gapped filter: the band gap */
+  double filter_eps;      /* gapped filter: its value at the gap edges */
 } sgw_sigma_params;
 
 /* Per-sample Sigma_c,i(t_j), j = -n_tau..n_tau, and exchange X_i for the

@@ -481,6 +481,20 @@ sgw_status sgw_apply_H(sgw_ctx *ctx, const void *psi, void *hpsi, int64_t nvec, 
   });
 }
 
+sgw_status sgw_gapped_coefficients(double e_homo, double e_lumo, double eps, double emin,
+                                   double emax, int32_t ncoef, double *coef) {
+  try {
+    if (!coef || ncoef <= 0 || !std::isfinite(e_homo) || !std::isfinite(e_lumo) ||
+        !(e_lumo > e_homo) || !(eps > 0 && eps < 0.5) || !(emax > emin) ||
+        !std::isfinite(emin) || !std::isfinite(emax))
+      return SGW_EINVAL;
+    gapped_coefficients(e_homo, e_lumo, eps, emin, emax, ncoef, coef);
+    return SGW_OK;
+  } catch (...) {
+    return SGW_ENOMEM;
+  }
+}
+
 sgw_status sgw_fermi_coefficients(double mu, double beta, double emin, double emax,
                                   int32_t ncoef, double *coef) {
   try {
@@ -678,6 +692,11 @@ sgw_status sgw_sigma_estimate(sgw_ctx *ctx, const sgw_sigma_params *P, const dou
     SGW_REQUIRE(P->ncoef >= 1 && std::isfinite(P->mu) && std::isfinite(P->beta), SGW_EINVAL,
                 "bad filter");
     SGW_REQUIRE(P->mode == 0 || P->mode == 1, SGW_EINVAL, "mode must be 0 or 1");
+    SGW_REQUIRE(P->filter == 0 || P->filter == 1, SGW_EINVAL, "filter must be 0 or 1");
+    if (P->filter == 1)
+      SGW_REQUIRE(std::isfinite(P->e_homo) && std::isfinite(P->e_lumo) &&
+                      P->e_lumo > P->e_homo && P->filter_eps > 0 && P->filter_eps < 0.5,
+                  SGW_EINVAL, "gapped filter needs e_homo < e_lumo and 0 < filter_eps < 0.5");
     SGW_REQUIRE(P->prop_tol > 0, SGW_EINVAL, "prop_tol must be > 0");
     check_interval(P->emin, P->emax);
     const bool xi = P->mode == 0;
@@ -695,7 +714,11 @@ sgw_status sgw_sigma_estimate(sgw_ctx *ctx, const sgw_sigma_params *P, const dou
 
     // coefficients
     std::vector<double> a(P->ncoef), fc(2 * P->ncoef, 0.0), pb;
-    fermi_coefficients(P->mu, P->beta, P->emin, P->emax, P->ncoef, a.data());
+    if (P->filter == 1)
+      gapped_coefficients(P->e_homo, P->e_lumo, P->filter_eps, P->emin, P->emax, P->ncoef,
+                          a.data());
+    else
+      fermi_coefficients(P->mu, P->beta, P->emin, P->emax, P->ncoef, a.data());
     for (int i = 0; i < P->ncoef; ++i) fc[2 * i] = a[i];
     propagator_coefficients(P->emin, P->emax, P->dt, P->prop_tol, pb);
     // time-ordering twiddles

@@ -275,6 +275,9 @@ void build_kb(sgw_ctx *ctx, const sgw_projectors *p);
 void kb_exponential_matrix(const sgw_ctx *ctx, double tau, std::vector<double> &K);
 void fermi_coefficients(double mu, double beta, double emin, double emax, int n,
                         double *a);
+// gapped filter: erfc step, 1 - eps at e_homo and eps at e_lumo
+void gapped_coefficients(double e_homo, double e_lumo, double eps, double emin, double emax,
+                         int n, double *a);
 // b_n (interleaved re, im) of exp(-i H tau); returns the number of terms
 int propagator_coefficients(double emin, double emax, double tau, double tol,
                             std::vector<double> &re_im);

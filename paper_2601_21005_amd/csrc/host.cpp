@@ -260,15 +260,17 @@ static double fermi(double E, double mu, double beta) {
 // a_n = (2 - delta_n0)/M sum_j F(c + R cos t_j) cos(n t_j), t_j = pi (j+1/2)/M,
 // M = 4 n; cos(n t_j) by rotation, re-seeded every 64 orders from an exactly
 // reduced argument.
-void fermi_coefficients(double mu, double beta, double emin, double emax, int ncoef,
-                        double *a) {
+// a_n = (2 - delta_n0)/M sum_j f(c + R cos t_j) cos(n t_j), t_j = pi (j + 1/2)/M,
+// M = 4 ncoef; cos(n t_j) by rotation, re-seeded every 64 orders
+template <typename F>
+static void step_coefficients(F f, double emin, double emax, int ncoef, double *a) {
   const double c = 0.5 * (emax + emin), R = 0.5 * (emax - emin);
   const int64_t M = 4 * (int64_t)ncoef;
   std::vector<double> acc(ncoef, 0.0);
   for (int64_t j = 0; j < M; ++j) {
     const double th = M_PI * (j + 0.5) / (double)M;
-    const double f = fermi(c + R * std::cos(th), mu, beta);
-    if (f == 0.0) continue;
+    const double fv = f(c + R * std::cos(th));
+    if (fv == 0.0) continue;
     const double wr = std::cos(th), wi = std::sin(th);
     double cr = 1, ci = 0;
     for (int k = 0; k < ncoef; ++k) {
@@ -279,7 +281,7 @@ void fermi_coefficients(double mu, double beta, double emin, double emax, int nc
         cr = std::cos(ang);
         ci = std::sin(ang);
       }
-      acc[k] += f * cr;
+      acc[k] += fv * cr;
       const double nr = cr * wr - ci * wi;
       ci = cr * wi + ci * wr;
       cr = nr;
@@ -287,6 +289,33 @@ void fermi_coefficients(double mu, double beta, double emin, double emax, int nc
   }
   for (int k = 0; k < ncoef; ++k) a[k] = acc[k] * 2.0 / (double)M;
   a[0] *= 0.5;
+}
+
+void fermi_coefficients(double mu, double beta, double emin, double emax, int ncoef,
+                        double *a) {
+  step_coefficients([&](double E) { return fermi(E, mu, beta); }, emin, emax, ncoef, a);
+}
+
+// y with erfc(y) = t, 0 < t < 1, by bisection (erfc decreases; 200 halvings
+// of [0, 27] reach the last bit)
+static double erfc_inverse(double t) {
+  double lo = 0.0, hi = 27.0;
+  for (int i = 0; i < 200; ++i) {
+    const double mid = 0.5 * (lo + hi);
+    if (std::erfc(mid) > t) lo = mid; else hi = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+// Gapped filter: erfc((E - mu)/sigma)/2 with mu mid-gap and sigma such that
+// the step is 1 - eps at E_HOMO and eps at E_LUMO (the cutoff spread over
+// the band gap, Sec. 2.1)
+void gapped_coefficients(double e_homo, double e_lumo, double eps, double emin, double emax,
+                         int ncoef, double *a) {
+  const double mu = 0.5 * (e_homo + e_lumo);
+  const double sigma = (e_lumo - e_homo) / (2.0 * erfc_inverse(2.0 * eps));
+  step_coefficients([&](double E) { return 0.5 * std::erfc((E - mu) / sigma); }, emin, emax,
+                    ncoef, a);
 }
 
 // J_0..J_nmax(x), x >= 0, by Miller's backward recurrence

@@ -22,7 +22,7 @@ STATUS_NAMES = {0: "SGW_OK", -1: "SGW_EINVAL", -2: "SGW_ENOMEM", -3: "SGW_EHIP",
 
 # every entry point declared in include/sgw.h
 EXPORTS = ["sgw_create", "sgw_destroy", "sgw_last_error", "sgw_bounds", "sgw_apply_H",
-           "sgw_fermi_coefficients", "sgw_fermi_filter", "sgw_propagator_coefficients",
+           "sgw_fermi_coefficients", "sgw_gapped_coefficients", "sgw_fermi_filter", "sgw_propagator_coefficients",
            "sgw_cheb_propagate", "sgw_tdh_init", "sgw_tdh_step", "sgw_sigma_estimate",
            "sgw_qp_solve", "sgw_sigma_omega", "sgw_kernel_timer", "sgw_kernel_timer_read",
            "sgw_use_graphs", "sgw_batch_sigma_estimate", "sgw_cv_features", "sgw_mlp_create", "sgw_mlp_destroy", "sgw_mlp_last_error",
@@ -59,7 +59,9 @@ class SgwSigmaParams(C.Structure):
                 ("m_sub", C.c_int32), ("mu", C.c_double), ("beta", C.c_double),
                 ("ncoef", C.c_int32), ("emin", C.c_double), ("emax", C.c_double),
                 ("n_xi", C.c_int32), ("f_g", C.c_double), ("mode", C.c_int32),
-                ("prop_tol", C.c_double), ("n_ft", C.c_int32), ("batch", C.c_int32)]
+                ("prop_tol", C.c_double), ("n_ft", C.c_int32), ("batch", C.c_int32),
+                ("filter", C.c_int32), ("e_homo", C.c_double), ("e_lumo", C.c_double),
+                ("filter_eps", C.c_double)]
 
 
 class SgwBatchItem(C.Structure):
@@ -102,6 +104,7 @@ def load():
     lib.sgw_bounds.argtypes = [vp, d, dp, dp]
     lib.sgw_apply_H.argtypes = [vp, vp, vp, i64, i64]
     lib.sgw_fermi_coefficients.argtypes = [d, d, d, d, i32, dp]
+    lib.sgw_gapped_coefficients.argtypes = [d, d, d, d, d, i32, dp]
     lib.sgw_fermi_filter.argtypes = [vp, vp, i64, i64, dp, i32, d, d]
     lib.sgw_propagator_coefficients.argtypes = [d, d, d, d, i32, dp, C.POINTER(i32)]
     lib.sgw_cheb_propagate.argtypes = [vp, vp, i64, i64, d, i32, d, d, d]
@@ -171,6 +174,13 @@ def _dev(t, name):
 def sgw_fermi_coefficients(mu, beta, emin, emax, ncoef):
     out = np.zeros(int(ncoef))
     _check(load().sgw_fermi_coefficients(mu, beta, emin, emax, int(ncoef), _dptr(out)))
+    return out
+
+
+def sgw_gapped_coefficients(e_homo, e_lumo, eps, emin, emax, ncoef):
+    out = np.zeros(int(ncoef))
+    _check(load().sgw_gapped_coefficients(e_homo, e_lumo, eps, emin, emax, int(ncoef),
+                                          _dptr(out)))
     return out
 
 
@@ -307,11 +317,13 @@ class Context:
                self.ctx)
         return ms.value, n.value, pts.value
 
-    def sigma_estimate(self, phi, seed, n_zeta, n_eta, n_tau, dt, m_sub, mu, beta, ncoef,
-                       emin, emax, n_xi=10000, f_g=0.003, mode=0, prop_tol=1e-14, n_ft=0,
-                       first_sample=0, batch=0):
-        p = sigma_params(seed, n_zeta, n_eta, n_tau, dt, m_sub, mu, beta, ncoef, emin, emax,
-                         n_xi, f_g, mode, prop_tol, n_ft, first_sample, batch)
+    def sigma_estimate(self, phi, seed, n_zeta, n_eta, n_tau, dt, m_sub, ncoef, emin, emax,
+                       mu=0.0, beta=0.0, n_xi=10000, f_g=0.003, mode=0, prop_tol=1e-14, n_ft=0,
+                       first_sample=0, batch=0, filter=0, e_homo=0.0, e_lumo=0.0,
+                       filter_eps=1e-7):
+        p = sigma_params(seed, n_zeta, n_eta, n_tau, dt, m_sub, ncoef, emin, emax, mu, beta,
+                         n_xi, f_g, mode, prop_tol, n_ft, first_sample, batch, filter, e_homo,
+                         e_lumo, filter_eps)
         ph = np.ascontiguousarray(np.asarray(phi, dtype=np.float64).ravel())
         sig = np.zeros((n_zeta, 2 * n_tau + 1, 2))
         x = np.zeros(n_zeta)
@@ -438,13 +450,14 @@ class Mlp:
 
 
 # ------------------------------------------------------------------ batches
-def sigma_params(seed, n_zeta, n_eta, n_tau, dt, m_sub, mu, beta, ncoef, emin, emax,
+def sigma_params(seed, n_zeta, n_eta, n_tau, dt, m_sub, ncoef, emin, emax, mu=0.0, beta=0.0,
                  n_xi=10000, f_g=0.003, mode=0, prop_tol=1e-14, n_ft=0, first_sample=0,
-                 batch=0):
+                 batch=0, filter=0, e_homo=0.0, e_lumo=0.0, filter_eps=1e-7):
     return SgwSigmaParams(int(seed), int(first_sample), int(n_zeta), int(n_eta), int(n_tau),
                           float(dt), int(m_sub), float(mu), float(beta), int(ncoef),
                           float(emin), float(emax), int(n_xi), float(f_g), int(mode),
-                          float(prop_tol), int(n_ft), int(batch))
+                          float(prop_tol), int(n_ft), int(batch), int(filter), float(e_homo),
+                          float(e_lumo), float(filter_eps))
 
 
 def batch_sigma_estimate(jobs, nworkers=4):

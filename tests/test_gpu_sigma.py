@@ -19,10 +19,12 @@ def compare(system, H, phi, prec, **kw):
     lo, hi = ctx.bounds()
     kw.update(emin=lo, emax=hi)
     mode = kw.pop("mode", "xi")
-    sig, x, ms = ctx.sigma_estimate(phi, mode=0 if mode == "xi" else 1, **kw)
+    filt = kw.pop("filter", "fermi")
+    sig, x, ms = ctx.sigma_estimate(phi, mode=0 if mode == "xi" else 1,
+                                    filter=1 if filt == "gapped" else 0, **kw)
     ctx.close()
     kw.pop("batch", None)
-    p = SGWParams(mode=mode, **kw)
+    p = SGWParams(mode=mode, filter=filt, **kw)
     sig_o, x_o = estimate(H, phi, p)
     return sig, x, sig_o, x_o, p
 
@@ -86,3 +88,22 @@ def test_sigma_si35h36_fp32(si35):
                                     n_xi=500, f_g=0.003, mode="xi")
     assert rel_err(sig, sig_o) < 2e-4
     assert rel_err(x, x_o) < 1e-5
+
+
+@pytest.mark.parametrize("prec,tol", [(sgw.SGW_C128, 1e-9), (sgw.SGW_C64, 2e-4)])
+def test_sigma_tiny8_gapped_filter(tiny8, tiny_states, prec, tol):
+    """The gapped filter (cutoff over the HOMO-LUMO gap) through the whole
+    path, against the oracle with the same filter."""
+    s, H = tiny8
+    e, V = tiny_states
+    phi = V[s.n_occ - 1]
+    lo, hi = H.bounds()
+    eh, el = e[s.n_occ - 1], e[s.n_occ]
+    a = cheb.gapped_coefficients(eh, el, 1e-8, lo, hi, 4096)
+    n = cheb.tail_length(a, 1e-12)
+    sig, x, sig_o, x_o, p = compare(s, H, phi, prec, seed=12, n_zeta=2, n_eta=4, n_tau=5,
+                                    dt=0.2, m_sub=2, ncoef=n, n_xi=64, f_g=0.125, mode="xi",
+                                    filter="gapped", e_homo=eh, e_lumo=el, filter_eps=1e-8,
+                                    mu=0.0, beta=0.0)
+    assert rel_err(sig, sig_o) < tol
+    assert rel_err(x, x_o) < tol
