@@ -5,13 +5,21 @@ Workload: the Si35H36-shaped cluster on a 64^3 grid (h = 0.5 bohr, kinetic
 cutoff 28 Ha), local Gaussian pseudopotentials plus s/p Kleinman-Bylander
 projectors (176 projectors, 88 occupied states), N_eta = 64 stochastic
 occupied orbitals per Monte Carlo sample, TDH linear response over 400 steps
-of dt = 0.05 a.u., N_xi = 10000 sparse functions at f_g = 0.003, Fermi
-filter with mu mid-gap and beta = 28 / gap, complex FP32 bulk arithmetic.
+of dt = 0.05 a.u., N_xi = 10000 sparse functions at f_g = 0.003, the gapped
+filter (cutoff spread over the HOMO-LUMO gap, 1e-7 at the gap edges),
+complex FP32 bulk arithmetic.
 
 One step = the whole hot path (white noise, filter, TDH with xi overlaps,
 time ordering, zeta propagation, contraction) for a batch of samples, through
 sgw_sigma_estimate.  The QP energy of the HOMO and its per-sample spread give
 GPU-seconds per QP energy at +-0.03 eV.  Printed as one JSON line.
+
+Forms: "plain" (complex FP32, the value), "bf16kb_graphs" (projector GEMMs
+with BF16 operands, launch sequences replayed from HIP graphs; same samples,
+so the same spread) and, with --cv N, "control_variate": N more samples are
+split into a fit set and an evaluation set, a network on |<phi_k|zeta>|^2
+over the 64 near-gap states is trained on the fit set and its mean taken over
+--cv-cheap cheap samples.
 """
 import argparse
 import json
@@ -52,13 +60,18 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-terms", type=int, default=6,
                     help="filter terms timed for the CPU baseline sample")
+    ap.add_argument("--no-bf16", action="store_true", help="skip the BF16-KB / graphs form")
+    ap.add_argument("--cv", type=int, default=0,
+                    help="samples for the control-variate form (0: skip it)")
+    ap.add_argument("--cv-cheap", type=int, default=200000)
     return ap.parse_args()
 
 
-def suggested_ncoef(sgw, mu, beta, emin, emax, tol):
+def suggested_ncoef(sgw, e_homo, e_lumo, eps, emin, emax, tol):
+    """Length of the gapped filter whose discarded tail is below tol."""
     import numpy as np
     for nmax in (2048, 4096, 8192, 16384, 32768):
-        a = sgw.sgw_fermi_coefficients(mu, beta, emin, emax, nmax)
+        a = sgw.sgw_gapped_coefficients(e_homo, e_lumo, eps, emin, emax, nmax)
         tail = np.cumsum(np.abs(a[::-1]))[::-1]
         ok = np.nonzero(tail < tol)[0]
         if ok.size and ok[0] < nmax // 2:
@@ -86,7 +99,8 @@ def cpu_baseline(system, phi, p, n_terms, ncoef):
     eb = np.stack([rng.white_noise(p["seed"], rng.ETA, 0, l, g.N, g.dV)
                    for l in range(p["n_eta"])])
     x = np.vstack([zb[None], eb])
-    a = cheb.fermi_coefficients(p["mu"], p["beta"], p["emin"], p["emax"], n_terms)
+    a = cheb.gapped_coefficients(p["e_homo"], p["e_lumo"], p["filter_eps"], p["emin"],
+                                 p["emax"], n_terms)
     t0 = time.perf_counter()
     cheb.apply_series(H, a, p["emin"], p["emax"], x)
     t_filter = (time.perf_counter() - t0) / max(1, n_terms - 1) * (ncoef - 1)
@@ -110,6 +124,84 @@ def cpu_baseline(system, phi, p, n_terms, ncoef):
     return total, dict(filter=t_filter, tdh=t_tdh, zeta=t_zeta), workers, sample
 
 
+def bf16_form(args, s, phi, p, sigma1, sig_plain, homo, gam):
+    """The same samples with BF16 projector GEMMs and HIP-graph replay on a
+    stream of its own: time per sample and the QP shift against plain."""
+    import numpy as np
+    import torch
+    from paper_2601_21005_amd import sgw
+    st = torch.cuda.Stream()
+    ctx = sgw.Context(s.grid.n, s.grid.h, s.v_loc, s.projectors, precision=sgw.SGW_C64_BF16KB,
+                      ecut=s.ecut, max_nvec=256, stream=st.cuda_stream)
+    ctx.use_graphs(True)
+    B = args.batch
+    for w in range(args.warmup):
+        ctx.sigma_estimate(phi, n_zeta=B, first_sample=w * B, **p)
+    torch.cuda.synchronize()
+    sigs = []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        sigs.append(ctx.sigma_estimate(phi, n_zeta=B, first_sample=(args.warmup + k) * B, **p)[0])
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / (args.steps * B)
+    ctx.close()
+    sig = np.concatenate(sigs)
+    d_sigma = float(np.max(np.abs(sig - sig_plain)) / np.max(np.abs(sig_plain)))
+    return {"gpu_s_per_qp": t * (sigma1 / 0.03) ** 2, "gpu_s_per_sample": t,
+            "sigma_t_max_rel_diff_vs_plain": d_sigma}
+
+
+def cv_form(args, ctx, s, phis, ev, phi, p, homo, eg, gam, t_sample, sigma1, Z):
+    """Control variate: args.cv new samples, half to fit a network on the
+    features of their white noise, half to evaluate; E[g] over cheap
+    samples.  GPU-s per QP = (sample time x samples needed at the reduced
+    spread) + feature and training time."""
+    import numpy as np
+    import torch
+    from paper_2601_21005_amd import sgw, systems
+    n = args.cv - args.cv % 2
+    first = 4096
+    t0 = time.perf_counter()
+    sig, xs = [], []
+    for b0 in range(0, n, args.batch):
+        nb = min(args.batch, n - b0)
+        a, x, _ = ctx.sigma_estimate(phi, n_zeta=nb, first_sample=first + b0, **p)
+        sig.append(a)
+        xs.append(x)
+    torch.cuda.synchronize()
+    t_samples = time.perf_counter() - t0
+    sig, xs = np.concatenate(sig), np.concatenate(xs)
+    y = xs + np.array([sgw.sgw_sigma_omega(si, p["dt"], gam, eg)[0].real for si in sig])
+    k0 = max(0, s.n_occ - 32)
+    sel = phis[k0:k0 + 64].contiguous()
+    t1 = time.perf_counter()
+    feats = sgw.cv_features(ctx, sel.float().contiguous(), p["seed"], first, n)
+    xn = feats.cpu().numpy().astype(np.float64)
+    half = n // 2
+    mean, std = xn[:half].mean(axis=0), xn[:half].std(axis=0)
+    std[std == 0] = 1.0
+    net = sgw.Mlp(systems.mlp_init(3))
+    net.set_standardization(mean, std)
+    ym, ysd = y[:half].mean(), y[:half].std()
+    yt = torch.from_numpy(((y[:half] - ym) / ysd).astype(np.float32)).cuda()
+    net.train(feats[:half].contiguous(), yt, 400, lr=1e-3)
+    g = net.forward(feats).cpu().numpy().astype(np.float64)
+    gm, gv = sgw.cv_cheap_moments(ctx, net, sel.float().contiguous(), p["seed"], first + n,
+                                  args.cv_cheap, chunk=65536)
+    torch.cuda.synchronize()
+    t_cv = time.perf_counter() - t1
+    net.close()
+    r = sgw.sgw_cv_estimate(y[:half], g[:half], y[half:], g[half:], gm, gv, args.cv_cheap)
+    # per-sample spread of the control-variate form on the evaluation set
+    sd_cv = float(r["sigma_cv"] * np.sqrt(n - half))
+    sigma1_cv = Z * sd_cv * 27.211386245988
+    need = (sigma1_cv / 0.03) ** 2
+    return {"gpu_s_per_qp": t_sample * need + t_cv, "samples": n, "rho2": r["rho2"],
+            "fallback": r["fallback"], "sigma1_eV": sigma1_cv, "plain_sigma1_eV": sigma1,
+            "feature_and_training_s": t_cv, "cheap_samples": args.cv_cheap,
+            "sample_time_s": t_samples}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -131,16 +223,18 @@ def main():
     ctx = sgw.Context(s.grid.n, s.grid.h, s.v_loc, s.projectors, precision=sgw.SGW_C64,
                       ecut=s.ecut, max_nvec=256)
     emin, emax = ctx.bounds(0.01)
-    ev, phis, res = ksinput.lowest_states(ctx, s.n_occ + 1, emin, emax, dV)
+    nst = s.n_occ + 32 if args.cv else s.n_occ + 1
+    ev, phis, res = ksinput.lowest_states(ctx, nst, emin, emax, dV)
     homo, lumo = float(ev[s.n_occ - 1]), float(ev[s.n_occ])
     gap = lumo - homo
     phi = phis[s.n_occ - 1].cpu().numpy()
-    mu, beta = 0.5 * (homo + lumo), 28.0 / gap
-    ncoef = suggested_ncoef(sgw, mu, beta, emin, emax, 1e-7)
+    eps = 1e-7
+    ncoef = suggested_ncoef(sgw, homo, lumo, eps, emin, emax, 1e-7)
     if args.quick:
         ncoef = min(ncoef, 400)
-    p = dict(seed=1002, n_eta=args.n_eta, n_tau=args.n_tau, dt=0.05, m_sub=1, mu=mu,
-             beta=beta, ncoef=ncoef, emin=emin, emax=emax, n_xi=10000, f_g=0.003, mode=0)
+    p = dict(seed=1002, n_eta=args.n_eta, n_tau=args.n_tau, dt=0.05, m_sub=1, ncoef=ncoef,
+             emin=emin, emax=emax, n_xi=10000, f_g=0.003, mode=0, filter=1, e_homo=homo,
+             e_lumo=lumo, filter_eps=eps)
     B = args.batch
 
     for w in range(args.warmup):
@@ -182,6 +276,13 @@ def main():
     torch.cuda.synchronize()
     hpsi_rate = nv * reps * s.grid.N / (time.perf_counter() - t1)
 
+    forms = {"plain": {"gpu_s_per_qp": gpu_s_per_qp, "gpu_s_per_sample": t_sample}}
+    if not args.no_bf16:
+        forms["bf16kb_graphs"] = bf16_form(args, s, phi, p, sigma1, sig, homo, gam)
+    if args.cv:
+        forms["control_variate"] = cv_form(args, ctx, s, phis, ev, phi, p, homo, eg, gam,
+                                          t_sample, sigma1, Z)
+
     achieved = CHEB_ALGO_BYTES * k_pts / (k_ms * 1e-3) / 1e9 if k_ms > 0 else None
     line = {
         "metric": METRIC,
@@ -198,13 +299,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": "Si35H36-shaped cluster, 64^3 grid h=0.5, KB s/p "
                                "projectors, N_eta=64, TDH 400 x 0.05 au, N_xi=10000, "
-                               "f_g=0.003, Fermi filter beta=28/gap, complex FP32",
+                               "f_g=0.003, gapped filter (1e-7 at the gap edges), "
+                               "complex FP32",
                    "samples_per_step": B, "n_tau": p["n_tau"], "n_eta": p["n_eta"],
                    "ncoef": ncoef, "quick": bool(args.quick)},
         "qp": {"eps_ks_homo_eV": homo * HA_EV, "gap_eV": gap * HA_EV,
                "eqp_homo_eV": eg * HA_EV, "eqp_lin_eV": el * HA_EV, "Z": Z,
                "stat_err_eV": err, "sigma1_eV": sigma1, "samples": nsamp,
                "gpu_s_per_sample": t_sample},
+        "forms": forms,
         "hpsi_gptvec_per_s": hpsi_rate / 1e9,
         "hpsi_algo_roofline_frac": hpsi_rate * HPSI_ALGO_BYTES / (HBM_PEAK_GBS * 1e9),
         "phase_ms": {"filter": phases[0], "tdh": phases[1], "time_order": phases[2],
