@@ -129,13 +129,86 @@ __global__ __launch_bounds__(NT_FFT) void k_plane(PassArgs a) {
   __syncthreads();
   lds_fft<C, NX, NY, P, 1, false, NT_FFT>(s, twx, tid);
   lds_fft<C, NY, NX, 1, P, true, NT_FFT>(s, twy, tid);
+  constexpr int Q = (E + NT_FFT - 1) / NT_FFT;
+  if constexpr (MODE == PLANE_INV_CHEB && E % NT_FFT == 0) {
+    // all operand loads of this thread in flight at once, then the updates
+    // (the stores to vold / acc would otherwise order every later load)
+    const C *xp = static_cast<const C *>(a.e.x) + v * a.ld_x + plane;
+    C *vp = static_cast<C *>(a.e.vold) + v * a.ld_x + plane;
+    C *ap = static_cast<C *>(a.e.acc) + v * a.ld_x + plane;
+    const R *Vp = static_cast<const R *>(a.e.vloc) + plane;
+    const bool first = a.e.first != 0;
+    const R c = (R)a.e.c, iR = (R)a.e.invR, s2 = (R)a.e.scale2;
+    R br = (R)a.e.coef_re, bi = (R)a.e.coef_im;
+    if (a.e.coef_dev) {
+      const int k = a.e.term_dev[0];
+      br = (R)a.e.coef_dev[2 * k];
+      bi = (R)a.e.coef_dev[2 * k + 1];
+    }
+    // two halves keep the operands within the 4-waves-per-SIMD register budget
+    constexpr int QH = Q % 2 == 0 ? Q / 2 : Q;
 #pragma unroll
-  for (int q = 0; q < (E + NT_FFT - 1) / NT_FFT; ++q) {
-    const int e = tid + q * NT_FFT;
-    if (E % NT_FFT == 0 || e < E) {
-      C val = s[(e / NX) * P + (e % NX)];
-      if (INV) val = cconj(val);
-      epilogue<R, MODE>(a, v, plane + e, val);
+    for (int h = 0; h < Q / QH; ++h) {
+      C xs[QH], ps[QH], ss[QH];
+      R Vs[QH];
+#pragma unroll
+      for (int q = 0; q < QH; ++q) {
+        const int e = tid + (h * QH + q) * NT_FFT;
+        xs[q] = xp[e];
+        Vs[q] = Vp[e];
+        if (!first) {
+          ps[q] = vp[e];
+          ss[q] = ap[e];
+        } else {
+          ps[q].x = ps[q].y = 0;
+          ss[q].x = ss[q].y = 0;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < QH; ++q) {
+        const int e = tid + (h * QH + q) * NT_FFT;
+        const C val = cconj(s[(e / NX) * P + (e % NX)]);
+        const C x = xs[q];
+        // w = (H x - c x)/R; v_{n+1} = s2 w - v_{n-1}; acc += coef_n x
+        C nv;
+        nv.x = s2 * ((val.x + (Vs[q] - c) * x.x) * iR) - ps[q].x;
+        nv.y = s2 * ((val.y + (Vs[q] - c) * x.y) * iR) - ps[q].y;
+        C sum = ss[q];
+        sum.x += br * x.x - bi * x.y;
+        sum.y += br * x.y + bi * x.x;
+        vp[e] = nv;
+        ap[e] = sum;
+      }
+    }
+  } else if constexpr (MODE == PLANE_INV_HPSI && E % NT_FFT == 0) {
+    // H psi = (T psi) + V psi: loads first, then the stores
+    const C *xp = static_cast<const C *>(a.e.x) + v * a.ld_x + plane;
+    const R *Vp = static_cast<const R *>(a.e.vloc) + plane;
+    C *dp = static_cast<C *>(a.dst) + v * a.ld_dst + plane;
+    C xs[Q];
+    R Vs[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      xs[q] = xp[tid + q * NT_FFT];
+      Vs[q] = Vp[tid + q * NT_FFT];
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int e = tid + q * NT_FFT;
+      C val = cconj(s[(e / NX) * P + (e % NX)]);
+      val.x += Vs[q] * xs[q].x;
+      val.y += Vs[q] * xs[q].y;
+      dp[e] = val;
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int e = tid + q * NT_FFT;
+      if (E % NT_FFT == 0 || e < E) {
+        C val = s[(e / NX) * P + (e % NX)];
+        if (INV) val = cconj(val);
+        epilogue<R, MODE>(a, v, plane + e, val);
+      }
     }
   }
 }
