@@ -122,11 +122,12 @@ std::string num_key(std::initializer_list<double> xs) {
 
 // ---------------------------------------------------------------- Chebyshev
 // Term k of the fused recurrence on (cur = v_k, old = v_{k-1}):
-// old <- v_{k+1}, acc += coef_k v_k.  With coef_dev the coefficient is read
-// on the device at coef_dev[d_counter[0]].
+// old <- v_{k+1}; acc_mode 1 / 2: acc = / += b_{k-1} v_{k-1} + b_k v_k.  With
+// coef_dev the coefficients are read on the device at coef_dev[d_counter[0]]
+// and the entry before.
 void cheb_term(sgw_ctx *ctx, void *cur, void *old, void *acc, void *tmp, void *kbC,
-               int64_t nvec, bool first, double br, double bi, double c, double invR,
-               const double *coef_dev) {
+               int64_t nvec, bool first, int acc_mode, const double *bprev, const double *b,
+               double c, double invR, const double *coef_dev) {
   const int64_t N = ctx->N;
   const double s2 = first ? 1.0 : 2.0;
   if (ctx->has_kb) kb_gather_e(ctx, cur, nvec, N, kbC);
@@ -137,8 +138,9 @@ void cheb_term(sgw_ctx *ctx, void *cur, void *old, void *acc, void *tmp, void *k
   e.vloc = ctx->d_vloc.p;
   e.c = c;
   e.invR = invR;
-  e.coef_re = br;
-  e.coef_im = bi;
+  e.acc_mode = acc_mode;
+  if (bprev) { e.cprev_re = bprev[0]; e.cprev_im = bprev[1]; }
+  if (b) { e.coef_re = b[0]; e.coef_im = b[1]; }
   e.first = first ? 1 : 0;
   e.scale2 = s2;
   e.coef_dev = coef_dev;
@@ -152,9 +154,11 @@ constexpr int SHORT_SERIES = 64;   // up to this many terms a series is one grap
 // out = sum_n coef_n T_n(H~) v0 over nvec vectors (ld = N) with the fused
 // recurrence; v0 and w1 are overwritten.  coef interleaved (re, im).
 // Returns the vector holding v_last (for the norm check).  Term k works on
-// cur = v0 (k even) or w1 (k odd).  With graphs on, a short series is
-// replayed whole (one graph per set of buffers and coefficients), a long
-// one as a graph of two terms that reads its coefficients from the device.
+// cur = v0 (k even) or w1 (k odd); the accumulator takes the terms in pairs
+// on odd k (b_{k-1} v_{k-1} + b_k v_k, both complete there), and the last
+// one or two terms at the end.  With graphs on, a short series is replayed
+// whole (one graph per set of buffers and coefficients), a long one as a
+// graph of two terms that reads its coefficients from the device.
 void *cheb_series(sgw_ctx *ctx, void *v0, void *w1, void *acc, void *tmp, int64_t nvec,
                   const std::vector<double> &coef, double emin, double emax) {
   const int nc = (int)coef.size() / 2;
@@ -168,14 +172,20 @@ void *cheb_series(sgw_ctx *ctx, void *v0, void *w1, void *acc, void *tmp, int64_
   if (ctx->has_kb) kbC = ctx->buf("kbC", ctx->csize() * ctx->kb.nproj * nvec).p;
   auto cur_of = [&](int k) { return (k % 2 == 0) ? v0 : w1; };
   auto old_of = [&](int k) { return (k % 2 == 0) ? w1 : v0; };
+  auto mode_of = [&](int k) { return k % 2 == 0 ? 0 : (k == 1 ? 1 : 2); };
   auto eager = [&](int k0, int k1) {       // terms k0 .. k1 - 1, host coefficients
     for (int k = k0; k < k1; ++k)
-      cheb_term(ctx, cur_of(k), old_of(k), acc, tmp, kbC, nvec, k == 0, coef[2 * k],
-                coef[2 * k + 1], c, invR, nullptr);
+      cheb_term(ctx, cur_of(k), old_of(k), acc, tmp, kbC, nvec, k == 0, mode_of(k),
+                k > 0 ? &coef[2 * (k - 1)] : nullptr, &coef[2 * k], c, invR, nullptr);
   };
   auto last = [&]() {
-    launch_axpy(ctx, cur_of(nc - 1), N, acc, N, nvec, coef[2 * (nc - 1)], coef[2 * (nc - 1) + 1]);
-    return cur_of(nc - 1);
+    const int k = nc - 1;                  // the loop ran terms 0 .. nc - 2
+    if ((nc - 2) % 2 == 1)                 // its last term was odd: acc holds 0 .. nc - 2
+      launch_axpy(ctx, cur_of(k), N, acc, N, nvec, coef[2 * k], coef[2 * k + 1]);
+    else                                   // b_{nc-2} v_{nc-2} is still pending
+      launch_axpy2(ctx, old_of(k), cur_of(k), N, acc, nvec, coef[2 * k - 2], coef[2 * k - 1],
+                   coef[2 * k], coef[2 * k + 1], nc == 2);
+    return cur_of(k);
   };
   const bool graph = ctx->graphs && !ctx->ktimer;
   if (!graph) {
@@ -206,8 +216,8 @@ void *cheb_series(sgw_ctx *ctx, void *v0, void *w1, void *acc, void *tmp, int64_
     const std::string key = "pair|" + base + ptr_key({dc.p, ctx->d_counter.p});
     hipGraphExec_t ex = captured(ctx, key, [&] {
       for (int k = 2; k < 4; ++k) {
-        cheb_term(ctx, cur_of(k), old_of(k), acc, tmp, kbC, nvec, false, 0.0, 0.0, c, invR,
-                  dc.as<double>());
+        cheb_term(ctx, cur_of(k), old_of(k), acc, tmp, kbC, nvec, false, mode_of(k), nullptr,
+                  nullptr, c, invR, dc.as<double>());
         launch_counter(ctx, 0, 1, true);
       }
     });

@@ -239,11 +239,15 @@ struct EpiArgs {
   void *r0 = nullptr;         // real outputs per field
   void *r1 = nullptr;
   double c = 0, invR = 0;     // spectral map
-  double coef_re = 0, coef_im = 0;  // coefficient of the new term
+  // CHEB on term n (x = v_n, vold = v_{n-1}): the series takes its terms in
+  // pairs, acc (+)= b_{n-1} v_{n-1} + b_n v_n on odd n only
+  double cprev_re = 0, cprev_im = 0;  // b_{n-1}
+  double coef_re = 0, coef_im = 0;    // b_n
+  int acc_mode = 0;           // CHEB: 0 acc untouched, 1 acc = pair, 2 acc += pair
   int first = 0;              // CHEB: v_1 = H~ v_0 (no v_{n-1} term)
   double scale2 = 2.0;        // CHEB: factor of H~ v_n (2, or 1 when first)
-  // CHEB inside a replayed graph: the coefficient is coef_dev[term_dev[0]]
-  // (interleaved re, im; FP64), read when the pass runs
+  // CHEB inside a replayed graph: b_n = coef_dev[term_dev[0]] and b_{n-1} the
+  // entry before (interleaved re, im; FP64), read when the pass runs
   const double *coef_dev = nullptr;
   const int *term_dev = nullptr;
 };

@@ -72,6 +72,44 @@ void launch_axpy(sgw_ctx *ctx, const void *x, int64_t ldx, void *acc, int64_t ld
   SGW_HIP(hipGetLastError());
 }
 
+// acc (= when assign, else +=) c0 a + c1 b, in that order
+template <typename R>
+__global__ void k_axpy2(const cplx<R> *a, const cplx<R> *b, int64_t ld, cplx<R> *acc, int64_t N,
+                        R c0r, R c0i, R c1r, R c1i, int assign) {
+  const int64_t r = (int64_t)blockIdx.x * NT + threadIdx.x;
+  const int64_t v = blockIdx.y;
+  if (r >= N) return;
+  const cplx<R> x = a[v * ld + r], y = b[v * ld + r];
+  cplx<R> o;
+  o.x = o.y = 0;
+  if (!assign) o = acc[v * ld + r];
+  o.x += c0r * x.x - c0i * x.y;
+  o.y += c0r * x.y + c0i * x.x;
+  o.x += c1r * y.x - c1i * y.y;
+  o.y += c1r * y.y + c1i * y.x;
+  acc[v * ld + r] = o;
+}
+
+void launch_axpy2(sgw_ctx *ctx, const void *a, const void *b, int64_t ld, void *acc,
+                  int64_t nvec, double c0r, double c0i, double c1r, double c1i, bool assign) {
+  for (int64_t v0 = 0; v0 < nvec; v0 += 65535) {
+    const int64_t nv = std::min<int64_t>(65535, nvec - v0);
+    if (ctx->dbl)
+      hipLaunchKernelGGL(k_axpy2<double>, grid1(ctx->N, nv), dim3(NT), 0, ctx->stream,
+                         static_cast<const double2 *>(a) + v0 * ld,
+                         static_cast<const double2 *>(b) + v0 * ld, ld,
+                         static_cast<double2 *>(acc) + v0 * ld, ctx->N, c0r, c0i, c1r, c1i,
+                         assign ? 1 : 0);
+    else
+      hipLaunchKernelGGL(k_axpy2<float>, grid1(ctx->N, nv), dim3(NT), 0, ctx->stream,
+                         static_cast<const float2 *>(a) + v0 * ld,
+                         static_cast<const float2 *>(b) + v0 * ld, ld,
+                         static_cast<float2 *>(acc) + v0 * ld, ctx->N, (float)c0r, (float)c0i,
+                         (float)c1r, (float)c1i, assign ? 1 : 0);
+  }
+  SGW_HIP(hipGetLastError());
+}
+
 void launch_copy(sgw_ctx *ctx, const void *src, int64_t lds, void *dst, int64_t ldd,
                  int64_t nvec) {
   SGW_HIP(hipMemcpy2DAsync(dst, ldd * ctx->csize(), src, lds * ctx->csize(),

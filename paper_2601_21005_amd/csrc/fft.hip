@@ -51,41 +51,40 @@ __device__ __forceinline__ void epilogue(const PassArgs &a, int64_t v, int64_t r
     } break;
     case PLANE_INV_CHEB: {
       // x = v_n:  w = (H x - c x)/R ; v_{n+1} = s2 w - v_{n-1} (no v_{n-1}
-      // on the first step) ; acc += coef_n x  (acc = coef_0 x on the first
-      // step).  The projector part of H x is added to v_{n+1} afterwards, so
-      // the term of v_{n+1} enters acc on the next step, when it is x.
+      // on the first step).  The projector part of H x is added to v_{n+1}
+      // afterwards, so v_{n-1} and v_n are complete here; on odd n the pair
+      // b_{n-1} v_{n-1} + b_n v_n goes into acc.
       const int64_t o = v * a.ld_x + r;
       const C x = static_cast<const C *>(a.e.x)[o];
       const R V = static_cast<const R *>(a.e.vloc)[r];
       const R c = (R)a.e.c, iR = (R)a.e.invR, s2 = (R)a.e.scale2;
-      C w;
-      w.x = (val.x + (V - c) * x.x) * iR;
-      w.y = (val.y + (V - c) * x.y) * iR;
-      C nv;
-      nv.x = s2 * w.x;
-      nv.y = s2 * w.y;
       C *vold = static_cast<C *>(a.e.vold);
       C *acc = static_cast<C *>(a.e.acc);
-      R br = (R)a.e.coef_re, bi = (R)a.e.coef_im;
-      if (a.e.coef_dev) {
-        const int k = a.e.term_dev[0];
-        br = (R)a.e.coef_dev[2 * k];
-        bi = (R)a.e.coef_dev[2 * k + 1];
-      }
-      C s;
-      if (!a.e.first) {
-        const C p = vold[o];
-        nv.x -= p.x;
-        nv.y -= p.y;
-        s = acc[o];
-      } else {
-        s.x = 0;
-        s.y = 0;
-      }
+      C p;
+      p.x = p.y = 0;
+      if (!a.e.first) p = vold[o];
+      C nv;
+      nv.x = s2 * ((val.x + (V - c) * x.x) * iR) - p.x;
+      nv.y = s2 * ((val.y + (V - c) * x.y) * iR) - p.y;
       vold[o] = nv;
-      s.x += br * x.x - bi * x.y;
-      s.y += br * x.y + bi * x.x;
-      acc[o] = s;
+      if (a.e.acc_mode) {
+        R b0r = (R)a.e.cprev_re, b0i = (R)a.e.cprev_im, b1r = (R)a.e.coef_re, b1i = (R)a.e.coef_im;
+        if (a.e.coef_dev) {
+          const int k = a.e.term_dev[0];
+          b0r = (R)a.e.coef_dev[2 * k - 2];
+          b0i = (R)a.e.coef_dev[2 * k - 1];
+          b1r = (R)a.e.coef_dev[2 * k];
+          b1i = (R)a.e.coef_dev[2 * k + 1];
+        }
+        C sm;
+        sm.x = sm.y = 0;
+        if (a.e.acc_mode == 2) sm = acc[o];
+        sm.x += b0r * p.x - b0i * p.y;
+        sm.y += b0r * p.y + b0i * p.x;
+        sm.x += b1r * x.x - b1i * x.y;
+        sm.y += b1r * x.y + b1i * x.x;
+        acc[o] = sm;
+      }
     } break;
     case PLANE_INV_POISSON: {
       const int64_t o = v * a.N + r;
@@ -138,12 +137,15 @@ __global__ __launch_bounds__(NT_FFT) void k_plane(PassArgs a) {
     C *ap = static_cast<C *>(a.e.acc) + v * a.ld_x + plane;
     const R *Vp = static_cast<const R *>(a.e.vloc) + plane;
     const bool first = a.e.first != 0;
+    const int am = a.e.acc_mode;
     const R c = (R)a.e.c, iR = (R)a.e.invR, s2 = (R)a.e.scale2;
-    R br = (R)a.e.coef_re, bi = (R)a.e.coef_im;
-    if (a.e.coef_dev) {
+    R b0r = (R)a.e.cprev_re, b0i = (R)a.e.cprev_im, b1r = (R)a.e.coef_re, b1i = (R)a.e.coef_im;
+    if (am && a.e.coef_dev) {
       const int k = a.e.term_dev[0];
-      br = (R)a.e.coef_dev[2 * k];
-      bi = (R)a.e.coef_dev[2 * k + 1];
+      b0r = (R)a.e.coef_dev[2 * k - 2];
+      b0i = (R)a.e.coef_dev[2 * k - 1];
+      b1r = (R)a.e.coef_dev[2 * k];
+      b1i = (R)a.e.coef_dev[2 * k + 1];
     }
     // two halves keep the operands within the 4-waves-per-SIMD register budget
     constexpr int QH = Q % 2 == 0 ? Q / 2 : Q;
@@ -156,28 +158,30 @@ __global__ __launch_bounds__(NT_FFT) void k_plane(PassArgs a) {
         const int e = tid + (h * QH + q) * NT_FFT;
         xs[q] = xp[e];
         Vs[q] = Vp[e];
-        if (!first) {
-          ps[q] = vp[e];
-          ss[q] = ap[e];
-        } else {
-          ps[q].x = ps[q].y = 0;
-          ss[q].x = ss[q].y = 0;
-        }
+        ps[q].x = ps[q].y = 0;
+        ss[q].x = ss[q].y = 0;
+        if (!first) ps[q] = vp[e];
+        if (am == 2) ss[q] = ap[e];
       }
 #pragma unroll
       for (int q = 0; q < QH; ++q) {
         const int e = tid + (h * QH + q) * NT_FFT;
         const C val = cconj(s[(e / NX) * P + (e % NX)]);
-        const C x = xs[q];
-        // w = (H x - c x)/R; v_{n+1} = s2 w - v_{n-1}; acc += coef_n x
+        const C x = xs[q], pv = ps[q];
+        // w = (H x - c x)/R; v_{n+1} = s2 w - v_{n-1}; on odd n
+        // acc (+)= b_{n-1} v_{n-1} + b_n v_n
         C nv;
-        nv.x = s2 * ((val.x + (Vs[q] - c) * x.x) * iR) - ps[q].x;
-        nv.y = s2 * ((val.y + (Vs[q] - c) * x.y) * iR) - ps[q].y;
-        C sum = ss[q];
-        sum.x += br * x.x - bi * x.y;
-        sum.y += br * x.y + bi * x.x;
+        nv.x = s2 * ((val.x + (Vs[q] - c) * x.x) * iR) - pv.x;
+        nv.y = s2 * ((val.y + (Vs[q] - c) * x.y) * iR) - pv.y;
         vp[e] = nv;
-        ap[e] = sum;
+        if (am) {
+          C sm = ss[q];
+          sm.x += b0r * pv.x - b0i * pv.y;
+          sm.y += b0r * pv.y + b0i * pv.x;
+          sm.x += b1r * x.x - b1i * x.y;
+          sm.y += b1r * x.y + b1i * x.x;
+          ap[e] = sm;
+        }
       }
     }
   } else if constexpr (MODE == PLANE_INV_HPSI && E % NT_FFT == 0) {

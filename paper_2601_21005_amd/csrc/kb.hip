@@ -224,6 +224,21 @@ struct OpBF16 {
   __device__ static void put1(T *d, float x) { *d = (uint16_t)bf16_bits(x); }
 };
 
+// Workgroup -> (tile, vector block).  Consecutive workgroups go to the 8
+// XCDs in turn, so tile t is given to workgroups on XCD t % 8 only, and one
+// XCD walks all vector blocks of a tile in a row: the tile's beta rows are
+// read from memory once per XCD L2 instead of once per workgroup.
+__device__ __forceinline__ bool tile_block(int ntile, int nvb, int &t, int64_t &vb) {
+  const int b = blockIdx.x, xcd = b & 7, i = b >> 3;
+  t = xcd + 8 * (i / nvb);
+  vb = i % nvb;
+  return t < ntile;
+}
+
+inline dim3 tile_grid(int ntile, int64_t nvb) {
+  return dim3((unsigned)(8 * ((ntile + 7) / 8) * nvb));
+}
+
 template <class T> __device__ __forceinline__ u32x4 ld16(const T *p) {
   return *reinterpret_cast<const u32x4 *>(p);
 }
@@ -232,7 +247,8 @@ template <class T> __device__ __forceinline__ u32x4 ld16(const T *p) {
 template <class Op, int NVB, int MT>
 __global__ __launch_bounds__(NTK) void k_kb_gather_mma(
     const float2 *psi, int64_t ld, int64_t nvec, const int *tile_base, const int *tile_off,
-    const typename Op::T *beta, float2 *partial, int nx, int ny, int lx, int ly, float dV) {
+    const typename Op::T *beta, float2 *partial, int nx, int ny, int lx, int ly, float dV,
+    int ntile, int nvb) {
   using T = typename Op::T;
   constexpr int NC = 2 * NVB, NTL = NC / 16;
   constexpr int EL = 16 / (int)sizeof(T);           // operand elements per lane per group
@@ -241,8 +257,10 @@ __global__ __launch_bounds__(NTK) void k_kb_gather_mma(
   static_assert(4 * MT * NTL * 256 * 4 <= NC * PITCH * (int)sizeof(T),
                 "cross-wave sums exceed the tile buffer");
   __shared__ __align__(16) T sp[NC * PITCH];       // Psi tile [column][point], then the sums
-  const int t = blockIdx.y;
-  const int64_t v0 = (int64_t)blockIdx.x * NVB;
+  int t;
+  int64_t vb;
+  if (!tile_block(ntile, nvb, t, vb)) return;
+  const int64_t v0 = vb * NVB;
   const int base = tile_base[t];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, q = lane >> 4, col = lane & 15;
   const int off = tile_off[t], ne = tile_off[t + 1] - off;
@@ -330,14 +348,16 @@ template <class Op, int NVB>
 __global__ __launch_bounds__(NTK) void k_kb_scatter_mma(
     const float2 *coef, int64_t nvec, const int *tile_base, const int *tile_off,
     const int *tile_offT, const int *entry_proj, const typename Op::T *betaT, float2 *dst,
-    int64_t ld, float s1, int nx, int ny, int lx, int ly) {
+    int64_t ld, float s1, int nx, int ny, int lx, int ly, int ntile, int nvb) {
   using T = typename Op::T;
   constexpr int NC = 2 * NVB, NTL = NC / 16;
   constexpr int EL = 16 / (int)sizeof(T);
   constexpr int PE = KB_MAXE + EL;                  // LDS pitch of a coefficient column
   __shared__ __align__(16) T sc[NC * PE];          // C' [column][entry]
-  const int t = blockIdx.y;
-  const int64_t v0 = (int64_t)blockIdx.x * NVB;
+  int t;
+  int64_t vb;
+  if (!tile_block(ntile, nvb, t, vb)) return;
+  const int64_t v0 = vb * NVB;
   const int off = tile_off[t], ne = tile_off[t + 1] - off;
   const int offT = tile_offT[t], nek = tile_offT[t + 1] - offT;
   const int base = tile_base[t];
@@ -438,12 +458,12 @@ template <class Op>
 static void launch_gather_variant(int vi, dim3 g, hipStream_t st, const float2 *psi, int64_t ld,
                                   int64_t nvec, const int *tb, const int *to,
                                   const typename Op::T *beta, float2 *partial, int nx, int ny,
-                                  int lx, int ly, float dV) {
+                                  int lx, int ly, float dV, int ntile, int nvb) {
   switch (vi) {
 #define SGW_G(I, A, B)                                                                           \
   case I:                                                                                        \
     hipLaunchKernelGGL((k_kb_gather_mma<Op, A, B>), g, dim3(NTK), 0, st, psi, ld, nvec, tb, to, \
-                       beta, partial, nx, ny, lx, ly, dV);                                       \
+                       beta, partial, nx, ny, lx, ly, dV, ntile, nvb);                           \
     break;
     SGW_G(0, 8, 2) SGW_G(1, 8, 4) SGW_G(2, 16, 2) SGW_G(3, 16, 4)
 #undef SGW_G
@@ -454,13 +474,14 @@ template <class Op>
 static void launch_scatter_variant(int vi, dim3 g, hipStream_t st, const float2 *coef,
                                    int64_t nvec, const int *tb, const int *to, const int *toT,
                                    const int *ep, const typename Op::T *betaT, float2 *dst,
-                                   int64_t ld, float s1, int nx, int ny, int lx, int ly) {
+                                   int64_t ld, float s1, int nx, int ny, int lx, int ly,
+                                   int ntile, int nvb) {
   if (vi == 0)
     hipLaunchKernelGGL((k_kb_scatter_mma<Op, 8>), g, dim3(NTK), 0, st, coef, nvec, tb, to, toT,
-                       ep, betaT, dst, ld, s1, nx, ny, lx, ly);
+                       ep, betaT, dst, ld, s1, nx, ny, lx, ly, ntile, nvb);
   else
     hipLaunchKernelGGL((k_kb_scatter_mma<Op, 16>), g, dim3(NTK), 0, st, coef, nvec, tb, to,
-                       toT, ep, betaT, dst, ld, s1, nx, ny, lx, ly);
+                       toT, ep, betaT, dst, ld, s1, nx, ny, lx, ly, ntile, nvb);
 }
 
 // Operand arrays of the MFMA kernels: beta per entry [entry][512] in the
@@ -517,11 +538,12 @@ static void gather_t(sgw_ctx *ctx, const void *psi, int64_t nvec, int64_t ld, vo
       using Op = decltype(op);
       auto run = [&](int vi) {
         const int64_t nvb = (nvec + kGather[vi].nvb - 1) / kGather[vi].nvb;
-        launch_gather_variant<Op>(vi, dim3(nvb, ctx->kb_ntile), ctx->stream,
+        launch_gather_variant<Op>(vi, tile_grid(ctx->kb_ntile, nvb), ctx->stream,
                                   static_cast<const float2 *>(psi), ld, nvec,
                                   ctx->d_kb_tile_base.as<int>(), ctx->d_kb_tile_off.as<int>(),
                                   beta, reinterpret_cast<float2 *>(partial), ctx->nx, ctx->ny,
-                                  ctx->kb_lx, ctx->kb_ly, (float)ctx->dV);
+                                  ctx->kb_lx, ctx->kb_ly, (float)ctx->dV, ctx->kb_ntile,
+                                  (int)nvb);
       };
       run(ctx->tune(name, nvec, NGATHER, run));   // the gather overwrites: trials are harmless
     };
@@ -581,12 +603,12 @@ static void scatter_t(sgw_ctx *ctx, const void *coef, int64_t nvec, void *dst, i
       using Op = decltype(op);
       auto launch = [&](int vi, float s) {
         const int64_t nvb = (nvec + kScatterNvb[vi] - 1) / kScatterNvb[vi];
-        launch_scatter_variant<Op>(vi, dim3(nvb, ctx->kb_ntile), ctx->stream,
+        launch_scatter_variant<Op>(vi, tile_grid(ctx->kb_ntile, nvb), ctx->stream,
                                    static_cast<const float2 *>(coef), nvec,
                                    ctx->d_kb_tile_base.as<int>(), ctx->d_kb_tile_off.as<int>(),
                                    ctx->d_kb_tile_offT.as<int>(), ctx->d_kb_entry_proj.as<int>(),
                                    betaT, static_cast<float2 *>(dst), ld, s, ctx->nx, ctx->ny,
-                                   ctx->kb_lx, ctx->kb_ly);
+                                   ctx->kb_lx, ctx->kb_ly, ctx->kb_ntile, (int)nvb);
       };
       // trials add 0 * (B C) to dst, which leaves it unchanged
       const int vi = ctx->tune(name, nvec, NSCATTER, [&](int i) { launch(i, 0.0f); });

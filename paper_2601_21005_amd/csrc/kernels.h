@@ -14,6 +14,9 @@ void launch_scale_copy(sgw_ctx *ctx, const void *x, int64_t ldx, void *acc, int6
 // acc[v] += (cre + i cim) x[v]
 void launch_axpy(sgw_ctx *ctx, const void *x, int64_t ldx, void *acc, int64_t lda,
                  int64_t nvec, double cre, double cim);
+// acc[v] (= when assign, else +=) c0 a[v] + c1 b[v]  (common leading dimension ld)
+void launch_axpy2(sgw_ctx *ctx, const void *a, const void *b, int64_t ld, void *acc,
+                  int64_t nvec, double c0r, double c0i, double c1r, double c1i, bool assign);
 // dst[v] = src[v]
 void launch_copy(sgw_ctx *ctx, const void *src, int64_t lds, void *dst, int64_t ldd,
                  int64_t nvec);
