@@ -152,14 +152,14 @@ def bf16_form(args, s, phi, p, sigma1, sig_plain, homo, gam):
 
 
 def cv_form(args, ctx, s, phis, ev, phi, p, homo, eg, gam, t_sample, sigma1, Z):
-    """Control variate: args.cv new samples, half to fit a network on the
-    features of their white noise, half to evaluate; E[g] over cheap
-    samples.  GPU-s per QP = (sample time x samples needed at the reduced
-    spread) + feature and training time."""
+    """Control variate: args.cv new samples split 3/8 train, 1/8 validation
+    (early stopping), 1/4 fit of c (A), 1/4 evaluation (B); E[g] over
+    args.cv_cheap cheap samples.  GPU-s per QP = sample time x samples needed
+    at the reduced spread + feature and training time."""
     import numpy as np
     import torch
     from paper_2601_21005_amd import sgw, systems
-    n = args.cv - args.cv % 2
+    n = args.cv - args.cv % 8
     first = 4096
     t0 = time.perf_counter()
     sig, xs = [], []
@@ -173,30 +173,40 @@ def cv_form(args, ctx, s, phis, ev, phi, p, homo, eg, gam, t_sample, sigma1, Z):
     sig, xs = np.concatenate(sig), np.concatenate(xs)
     y = xs + np.array([sgw.sgw_sigma_omega(si, p["dt"], gam, eg)[0].real for si in sig])
     k0 = max(0, s.n_occ - 32)
-    sel = phis[k0:k0 + 64].contiguous()
+    sel = phis[k0:k0 + 64].float().contiguous()
     t1 = time.perf_counter()
-    feats = sgw.cv_features(ctx, sel.float().contiguous(), p["seed"], first, n)
+    feats = sgw.cv_features(ctx, sel, p["seed"], first, n)
     xn = feats.cpu().numpy().astype(np.float64)
-    half = n // 2
-    mean, std = xn[:half].mean(axis=0), xn[:half].std(axis=0)
+    tr, va = slice(0, 3 * n // 8), slice(3 * n // 8, n // 2)
+    A, B = slice(n // 2, 3 * n // 4), slice(3 * n // 4, n)
+    mean, std = xn[tr].mean(axis=0), xn[tr].std(axis=0)
     std[std == 0] = 1.0
+    ym, ysd = y[tr].mean(), y[tr].std()
+    yt = torch.from_numpy(((y - ym) / ysd).astype(np.float32)).cuda()
     net = sgw.Mlp(systems.mlp_init(3))
     net.set_standardization(mean, std)
-    ym, ysd = y[:half].mean(), y[:half].std()
-    yt = torch.from_numpy(((y[:half] - ym) / ysd).astype(np.float32)).cuda()
-    net.train(feats[:half].contiguous(), yt, 400, lr=1e-3)
+    best, best_loss = None, np.inf
+    for _ in range(30):
+        net.train(feats[tr].contiguous(), yt[tr].contiguous(), 10, lr=1e-3)
+        gv = net.forward(feats[va].contiguous()).cpu().numpy().astype(np.float64)
+        loss = float(np.mean((gv - (y[va] - ym) / ysd) ** 2))
+        if loss < best_loss:
+            best, best_loss = net.params(), loss
+    net.close()
+    net = sgw.Mlp(best)
+    net.set_standardization(mean, std)
     g = net.forward(feats).cpu().numpy().astype(np.float64)
-    gm, gv = sgw.cv_cheap_moments(ctx, net, sel.float().contiguous(), p["seed"], first + n,
-                                  args.cv_cheap, chunk=65536)
+    gm, gv = sgw.cv_cheap_moments(ctx, net, sel, p["seed"], first + n, args.cv_cheap, chunk=65536)
     torch.cuda.synchronize()
     t_cv = time.perf_counter() - t1
     net.close()
-    r = sgw.sgw_cv_estimate(y[:half], g[:half], y[half:], g[half:], gm, gv, args.cv_cheap)
-    # per-sample spread of the control-variate form on the evaluation set
-    sd_cv = float(r["sigma_cv"] * np.sqrt(n - half))
+    r = sgw.sgw_cv_estimate(y[A], g[A], y[B], g[B], gm, gv, args.cv_cheap)
+    nB = B.stop - B.start
+    sd_cv = float(r["sigma_cv"] * np.sqrt(nB))       # per-sample spread of the CV form
     sigma1_cv = Z * sd_cv * 27.211386245988
-    need = (sigma1_cv / 0.03) ** 2
-    return {"gpu_s_per_qp": t_sample * need + t_cv, "samples": n, "rho2": r["rho2"],
+    plain_sd = float(np.std(y[B], ddof=1))
+    return {"gpu_s_per_qp": t_sample * (sigma1_cv / 0.03) ** 2 + t_cv, "samples": n,
+            "rho2_A": r["rho2"], "variance_ratio_B": (sd_cv / plain_sd) ** 2,
             "fallback": r["fallback"], "sigma1_eV": sigma1_cv, "plain_sigma1_eV": sigma1,
             "feature_and_training_s": t_cv, "cheap_samples": args.cv_cheap,
             "sample_time_s": t_samples}
