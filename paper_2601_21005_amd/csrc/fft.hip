@@ -345,6 +345,8 @@ template <typename R, int N> constexpr bool plane_fits() {
 }
 
 template <int N> constexpr int pencil_tx() { return N % 16 == 0 ? 16 : N % 8 == 0 ? 8 : 4; }
+// wider pencils (rows of 32 complex) where the length allows them
+template <int N> constexpr int pencil_tx_wide() { return N % 32 == 0 ? 32 : pencil_tx<N>(); }
 template <int N> constexpr int xlines_nl() { return N >= 2048 ? 1 : 2048 / N; }
 
 template <typename R, int N, int MODE> static void launch_plane(dim3 g, hipStream_t st,
@@ -371,6 +373,9 @@ template <typename R, int N> struct Kernels {
   static void pencil(dim3 g, hipStream_t st, const PassArgs &a) {
     hipLaunchKernelGGL((k_pencil<R, N, pencil_tx<N>()>), g, dim3(NT_FFT), 0, st, a);
   }
+  static void pencil_wide(dim3 g, hipStream_t st, const PassArgs &a) {
+    hipLaunchKernelGGL((k_pencil<R, N, pencil_tx_wide<N>()>), g, dim3(NT_FFT), 0, st, a);
+  }
   static void xlines(dim3 g, hipStream_t st, const PassArgs &a) {
     switch (a.mode) {
       case PLANE_FWD: launch_xlines<R, N, PLANE_FWD>(g, st, a); break;
@@ -383,6 +388,7 @@ template <typename R, int N> struct Kernels {
   }
   static constexpr bool has_plane = plane_fits<R, N>();
   static constexpr int tx = pencil_tx<N>();
+  static constexpr int tx_wide = pencil_tx_wide<N>();
   static constexpr int nl = xlines_nl<N>();
 };
 
@@ -390,13 +396,15 @@ struct SizeOps {
   void (*plane)(dim3, hipStream_t, const PassArgs &);
   void (*pencil)(dim3, hipStream_t, const PassArgs &);
   void (*xlines)(dim3, hipStream_t, const PassArgs &);
+  void (*pencil_wide)(dim3, hipStream_t, const PassArgs &);
   bool has_plane;
-  int tx, nl;
+  int tx, nl, tx_wide;
 };
 
 template <typename R, int N> SizeOps make_ops() {
   return SizeOps{&Kernels<R, N>::plane, &Kernels<R, N>::pencil, &Kernels<R, N>::xlines,
-                 Kernels<R, N>::has_plane, Kernels<R, N>::tx, Kernels<R, N>::nl};
+                 &Kernels<R, N>::pencil_wide, Kernels<R, N>::has_plane, Kernels<R, N>::tx,
+                 Kernels<R, N>::nl, Kernels<R, N>::tx_wide};
 }
 
 template <typename R> bool get_ops(int n, SizeOps &o) {
@@ -468,7 +476,15 @@ void fft3d_apply_t(sgw_ctx *ctx, const void *src, void *tmp, void *dst, int64_t 
     // z: forward, multiply, inverse
     PassArgs pz = a;
     pz.dst = tmpv; pz.ld_dst = N; pz.axis = 2; pz.tw0 = twz; pz.inverse = 0; pz.mul = mul;
-    oz.pencil(dim3((ctx->nx / oz.tx) * ctx->ny, nv), st, pz);
+    // z pencils: rows of 32 complex when the lengths allow it (SGW_FORCE_VARIANT
+    // pencil=0 keeps rows of 16); every column is the same 1D transform either way
+    const auto fp = ctx->forced.find("pencil");
+    const bool wide = oz.tx_wide != oz.tx && ctx->nx % oz.tx_wide == 0 &&
+                      (fp == ctx->forced.end() || fp->second != 0);
+    if (wide)
+      oz.pencil_wide(dim3((ctx->nx / oz.tx_wide) * ctx->ny, nv), st, pz);
+    else
+      oz.pencil(dim3((ctx->nx / oz.tx) * ctx->ny, nv), st, pz);
     SGW_HIP(hipGetLastError());
     // inverse xy with the epilogue
     PassArgs b = a;

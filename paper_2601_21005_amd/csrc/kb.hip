@@ -208,6 +208,10 @@ struct OpF32 {
   __device__ static void put2(T *d, float x, float y) {
     *reinterpret_cast<float2 *>(d) = make_float2(x, y);
   }
+  __device__ static u32x4 pack(const float *e) {      // 4 values -> one operand
+    return u32x4{__float_as_uint(e[0]), __float_as_uint(e[1]), __float_as_uint(e[2]),
+                 __float_as_uint(e[3])};
+  }
   __device__ static void put1(T *d, float x) { *d = x; }
 };
 
@@ -222,6 +226,10 @@ struct OpBF16 {
     *reinterpret_cast<uint32_t *>(d) = bf16_bits(x) | (bf16_bits(y) << 16);
   }
   __device__ static void put1(T *d, float x) { *d = (uint16_t)bf16_bits(x); }
+  __device__ static u32x4 pack(const float *e) {      // 8 values -> one operand (RNE)
+    return u32x4{bf16_bits(e[0]) | (bf16_bits(e[1]) << 16), bf16_bits(e[2]) | (bf16_bits(e[3]) << 16),
+                 bf16_bits(e[4]) | (bf16_bits(e[5]) << 16), bf16_bits(e[6]) | (bf16_bits(e[7]) << 16)};
+  }
 };
 
 // Workgroup -> (tile, vector block).  Consecutive workgroups go to the 8
@@ -243,7 +251,12 @@ template <class T> __device__ __forceinline__ u32x4 ld16(const T *p) {
   return *reinterpret_cast<const u32x4 *>(p);
 }
 
-// partial[off + e][v] = dV sum_p beta_e(p) psi_v(p) for the entries e of tile t
+// partial[off + e][v] = dV sum_p beta_e(p) psi_v(p) for the entries e of tile t.
+// The B operand of lane (q, col) in K group g is EL consecutive tile points
+// (consecutive x, so EL consecutive complex values in memory) of the real
+// (col even) or imaginary (col odd) part of vector v0 + 8 n + col / 2: the
+// lane reads them straight from memory (lanes col and col ^ 1 read the same
+// bytes in the same instruction) -- no staging in LDS.
 template <class Op, int NVB, int MT>
 __global__ __launch_bounds__(NTK) void k_kb_gather_mma(
     const float2 *psi, int64_t ld, int64_t nvec, const int *tile_base, const int *tile_off,
@@ -252,11 +265,8 @@ __global__ __launch_bounds__(NTK) void k_kb_gather_mma(
   using T = typename Op::T;
   constexpr int NC = 2 * NVB, NTL = NC / 16;
   constexpr int EL = 16 / (int)sizeof(T);           // operand elements per lane per group
-  constexpr int PITCH = KB_TP + EL;                 // 16 B of padding: conflict-free 16 B reads
   constexpr int NG = 128 / Op::GK;                  // K groups of one wave (128 points)
-  static_assert(4 * MT * NTL * 256 * 4 <= NC * PITCH * (int)sizeof(T),
-                "cross-wave sums exceed the tile buffer");
-  __shared__ __align__(16) T sp[NC * PITCH];       // Psi tile [column][point], then the sums
+  __shared__ __align__(16) float red[4 * MT * NTL * 256];   // cross-wave sums
   int t;
   int64_t vb;
   if (!tile_block(ntile, nvb, t, vb)) return;
@@ -264,36 +274,27 @@ __global__ __launch_bounds__(NTK) void k_kb_gather_mma(
   const int base = tile_base[t];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, q = lane >> 4, col = lane & 15;
   const int off = tile_off[t], ne = tile_off[t + 1] - off;
-  {
-    // thread tid owns the tile points 2 tid and 2 tid + 1 (neighbours along x):
-    // every load of the NVB vectors is issued before the first store
-    const int64_t r0 = tile_point(base, 2 * tid, nx, ny, lx, ly);
-    float2 v[NVB][2];
-#pragma unroll
-    for (int vl = 0; vl < NVB; ++vl) {
-      if (v0 + vl < nvec) {
-        const float2 *s = psi + (v0 + vl) * ld + r0;
-        v[vl][0] = s[0];
-        v[vl][1] = s[1];
-      } else {
-        v[vl][0] = v[vl][1] = make_float2(0.f, 0.f);
-      }
-    }
-#pragma unroll
-    for (int vl = 0; vl < NVB; ++vl) {
-      Op::put2(sp + (2 * vl) * PITCH + 2 * tid, v[vl][0].x, v[vl][1].x);
-      Op::put2(sp + (2 * vl + 1) * PITCH + 2 * tid, v[vl][0].y, v[vl][1].y);
-    }
-  }
-  __syncthreads();
   // B operands of this wave's quarter of K, kept in registers for all entries
   u32x4 b[NG][NTL];
 #pragma unroll
-  for (int g = 0; g < NG; ++g)
+  for (int n = 0; n < NTL; ++n) {
+    const int64_t v = v0 + 8 * n + (col >> 1);
+    const bool ok = v < nvec;
+    const float2 *src = psi + (ok ? v : 0) * ld;
 #pragma unroll
-    for (int n = 0; n < NTL; ++n)
-      b[g][n] = ld16(sp + (16 * n + col) * PITCH + 128 * w + g * Op::GK + EL * q);
-  float *red = reinterpret_cast<float *>(sp);       // [w][j][n][lane][4]
+    for (int g = 0; g < NG; ++g) {
+      const int p = 128 * w + g * Op::GK + EL * q;  // EL consecutive points along x
+      const float4 *s4 = reinterpret_cast<const float4 *>(src + tile_point(base, p, nx, ny, lx, ly));
+      float e[EL];
+#pragma unroll
+      for (int h = 0; h < EL / 2; ++h) {
+        const float4 z = ok ? s4[h] : make_float4(0.f, 0.f, 0.f, 0.f);
+        e[2 * h] = (col & 1) ? z.y : z.x;
+        e[2 * h + 1] = (col & 1) ? z.w : z.z;
+      }
+      b[g][n] = Op::pack(e);
+    }
+  }
   for (int mg = 0; mg < ne; mg += 16 * MT) {
     f32x4 acc[MT][NTL];
 #pragma unroll
@@ -315,7 +316,6 @@ __global__ __launch_bounds__(NTK) void k_kb_gather_mma(
 #pragma unroll
           for (int n = 0; n < NTL; ++n) Op::mma(acc[j][n], a[j], b[g][n]);
     }
-    __syncthreads();                                // B operands loaded / last sums read
 #pragma unroll
     for (int j = 0; j < MT; ++j)
 #pragma unroll
@@ -381,6 +381,36 @@ __global__ __launch_bounds__(NTK) void k_kb_scatter_mma(
     }
   }
   __syncthreads();
+  // destinations of this lane: lanes col and col ^ 1 hold the real and
+  // imaginary columns of vector 8 n + col / 2 at the points 4 q + r of each
+  // M tile; they will swap halves so that each lane owns two complete values
+  // at two neighbouring points (even lane: r = 0, 1; odd lane: r = 2, 3)
+  const int odd = col & 1;
+  const int vcol = col >> 1;
+  float2 *ptr[8][NTL];
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+#pragma unroll
+    for (int n = 0; n < NTL; ++n) {
+      const int vl = 8 * n + vcol;
+      const int pb = 16 * (8 * w + j) + 4 * q + 2 * odd;
+      ptr[j][n] = v0 + vl < nvec ? dst + (v0 + vl) * ld + tile_point(base, pb, nx, ny, lx, ly)
+                                 : nullptr;
+    }
+  // with one N tile the old destination values are loaded before the K loop,
+  // so their memory latency overlaps the products
+  constexpr bool PREFETCH = NTL == 1;
+  float2 o[8][NTL][2];
+  if constexpr (PREFETCH) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+#pragma unroll
+      for (int n = 0; n < NTL; ++n)
+        if (ptr[j][n]) {
+          o[j][n][0] = ptr[j][n][0];
+          o[j][n][1] = ptr[j][n][1];
+        }
+  }
   // wave w owns the M tiles (16 points each) 8 w .. 8 w + 7
   f32x4 acc[8][NTL];
 #pragma unroll
@@ -407,14 +437,7 @@ __global__ __launch_bounds__(NTK) void k_kb_scatter_mma(
 #pragma unroll
     for (int n = 0; n < NTL; ++n) b_cur[n] = b_nxt[n];
   }
-  // Epilogue from the accumulators.  Lanes col and col ^ 1 hold the real and
-  // imaginary columns of vector 8 n + col / 2 at the points 4 q + r; they swap
-  // halves so that each lane owns two complete values at two neighbouring
-  // points (even lane: r = 0, 1; odd lane: r = 2, 3).
-  const int odd = col & 1;
-  const int vcol = col >> 1;
   float2 c[8][NTL][2];
-  float2 *ptr[8][NTL];
 #pragma unroll
   for (int j = 0; j < 8; ++j)
 #pragma unroll
@@ -424,20 +447,17 @@ __global__ __launch_bounds__(NTK) void k_kb_scatter_mma(
       const float x1 = __shfl_xor(odd ? d[1] : d[3], 1, 64);
       c[j][n][0] = odd ? make_float2(x0, d[2]) : make_float2(d[0], x0);
       c[j][n][1] = odd ? make_float2(x1, d[3]) : make_float2(d[1], x1);
-      const int vl = 8 * n + vcol;
-      const int pb = 16 * (8 * w + j) + 4 * q + 2 * odd;
-      ptr[j][n] = v0 + vl < nvec ? dst + (v0 + vl) * ld + tile_point(base, pb, nx, ny, lx, ly)
-                                 : nullptr;
     }
-  float2 o[8][NTL][2];
+  if constexpr (!PREFETCH) {
 #pragma unroll
-  for (int j = 0; j < 8; ++j)
+    for (int j = 0; j < 8; ++j)
 #pragma unroll
-    for (int n = 0; n < NTL; ++n)
-      if (ptr[j][n]) {
-        o[j][n][0] = ptr[j][n][0];
-        o[j][n][1] = ptr[j][n][1];
-      }
+      for (int n = 0; n < NTL; ++n)
+        if (ptr[j][n]) {
+          o[j][n][0] = ptr[j][n][0];
+          o[j][n][1] = ptr[j][n][1];
+        }
+  }
 #pragma unroll
   for (int j = 0; j < 8; ++j)
 #pragma unroll
@@ -534,6 +554,8 @@ static void gather_t(sgw_ctx *ctx, const void *psi, int64_t nvec, int64_t ld, vo
   C *partial = ctx->buf("kb_partial", sizeof(C) * (size_t)ctx->kb_nentry * nvec).as<C>();
   SGW_REQUIRE(ctx->kb_ntile <= 65535, SGW_EUNSUPPORTED, "KB gather: too many tiles");
   if constexpr (sizeof(R) == 4) {
+    SGW_REQUIRE(ld % 2 == 0, SGW_EUNSUPPORTED,
+                "projectors in complex FP32 need an even leading dimension");
     auto go = [&](auto op, const char *name, const auto *beta) {
       using Op = decltype(op);
       auto run = [&](int vi) {
