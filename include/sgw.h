@@ -117,8 +117,9 @@ sgw_status sgw_bounds(sgw_ctx *ctx, double pad, double *emin, double *emax);
 
 /* hpsi[v] = H psi[v] for v < nvec (Eq. 1; Sec. 2.2: FFT pair for the
  * kinetic term, potential diagonal in r).  psi and hpsi are device batches
- * with leading dimension ld; they must not overlap. *  With projectors in a complex-FP32 precision, ld must be even (the
- * projector kernels read 16-byte operands); otherwise SGW_EUNSUPPORTED. */
+ * with leading dimension ld; they must not overlap.  With projectors in a
+ * complex-FP32 precision, ld must be even (the projector kernels read
+ * 16-byte operands); otherwise SGW_EUNSUPPORTED. */
 sgw_status sgw_apply_H(sgw_ctx *ctx, const void *psi, void *hpsi,
                        int64_t nvec, int64_t ld);
 
