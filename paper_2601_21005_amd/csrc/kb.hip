@@ -316,6 +316,10 @@ __global__ __launch_bounds__(NTK) void k_kb_gather_mma(
 #pragma unroll
           for (int n = 0; n < NTL; ++n) Op::mma(acc[j][n], a[j], b[g][n]);
     }
+    // a barrier between the last products and the LDS writes of their
+    // accumulators (without it the <8, 2> instantiation read some
+    // accumulators before their last product had landed)
+    __syncthreads();
 #pragma unroll
     for (int j = 0; j < MT; ++j)
 #pragma unroll
