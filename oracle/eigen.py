@@ -38,3 +38,44 @@ def lowest_states(H, k, tol=1e-10, v0_seed=7):
     order = np.argsort(e)
     e, V = e[order], V[:, order]
     return e, V.T / np.sqrt(H.grid.dV)
+
+
+def lanczos_bounds(H, k, seed=0, pad=0.01):
+    """Spectral interval of H from k Lanczos steps (the paper finds the
+    interval by shifted power iteration, Sec. 2.1; Lanczos is the Krylov
+    method that gives both ends from one sequence).
+
+    Start: the +-1 white-noise vector of stream (BOUNDS, 0, 0), unit norm in
+    the plain Euclidean sense.  Steps: w = H v_j - alpha_j v_j - beta_j v_{j-1},
+    alpha_j = <v_j, H v_j>, beta_{j+1} = |w|, no reorthogonalisation (it does
+    not move the extreme Ritz values).  Ritz values theta and residual norms
+    r = beta_k |y_last| of the k x k tridiagonal; every Ritz value lies within
+    r of an eigenvalue.  The interval is
+        [theta_min - r_min - pad w, theta_max + r_max + pad w],
+    w = theta_max - theta_min, each end clipped to the rigorous bounds of
+    ``H.bounds(0)`` (Weyl plus Gershgorin), which it can only narrow."""
+    from scipy.linalg import eigh_tridiagonal
+    from . import rng
+    N = H.grid.N
+    v = rng.white_noise_signs(seed, rng.stream_id(rng.BOUNDS, 0, 0), N)
+    v = v / np.linalg.norm(v)
+    v_prev = np.zeros(N)
+    alpha, beta = [], []
+    b = 0.0
+    for _ in range(k):
+        w = H.apply(v)
+        a = float(v @ w)
+        w = w - a * v - b * v_prev
+        b = float(np.linalg.norm(w))
+        alpha.append(a)
+        beta.append(b)
+        if b == 0.0:
+            break
+        v_prev, v = v, w / b
+    theta, Y = eigh_tridiagonal(np.array(alpha), np.array(beta[:-1]))
+    r = beta[-1] * np.abs(Y[-1, :])
+    lo_w, hi_w = H.bounds(0.0)
+    width = theta[-1] - theta[0]
+    lo = max(lo_w, theta[0] - r[0] - pad * width)
+    hi = min(hi_w, theta[-1] + r[-1] + pad * width)
+    return lo, hi

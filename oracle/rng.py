@@ -33,6 +33,7 @@ ZETA = 1        # white noise zeta-bar_i (one per Monte Carlo sample)
 ETA = 2         # white noise eta-bar_{i,l}
 XI_SUPPORT = 3  # segment positions of the sparse xi_{i,m}
 XI_SIGN = 4     # point signs of the sparse xi_{i,m}
+BOUNDS = 5      # start vector of the Lanczos estimate of the spectral interval
 
 
 def sm64(x):

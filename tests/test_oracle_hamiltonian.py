@@ -93,3 +93,40 @@ def test_cluster_projector_count_and_occupation():
     s = systems.si35h36()
     assert s.projectors.nproj == 35 * 4 + 36
     assert s.n_occ == 88
+
+
+def test_lanczos_bounds_enclose_and_converge(tiny8, tiny8_eig):
+    """40 Lanczos steps on the 8^3 system: the interval encloses the dense
+    spectrum, its ends lie within 2% of the spectral width of the extreme
+    eigenvalues, and it is inside the rigorous bounds."""
+    from oracle import eigen
+    s, H = tiny8
+    e, _ = tiny8_eig
+    lo, hi = eigen.lanczos_bounds(H, 40, seed=3, pad=0.01)
+    w = e[-1] - e[0]
+    assert lo <= e[0] and hi >= e[-1]
+    assert e[0] - lo < 0.02 * w and hi - e[-1] < 0.02 * w
+    lw, hw = H.bounds(0.0)
+    assert lw <= lo and hi <= hw
+
+
+def test_lanczos_ritz_values_are_exact_for_a_diagonal_operator():
+    """On a 3-level operator every Krylov space of dimension >= 3 holds the
+    three eigenvectors' span: the Ritz values are the eigenvalues."""
+    import numpy as np
+    from oracle import eigen
+    from oracle.grid import Grid
+
+    class Diag:
+        def __init__(self):
+            self.grid = Grid(4, h=1.0)
+            self.d = np.repeat([-2.0, 0.5, 3.0], [20, 20, 24])
+
+        def apply(self, x):
+            return self.d * x
+
+        def bounds(self, pad=0.0):
+            return -10.0, 10.0
+
+    lo, hi = eigen.lanczos_bounds(Diag(), 6, seed=1, pad=0.0)
+    assert abs(lo + 2.0) < 1e-10 and abs(hi - 3.0) < 1e-10
