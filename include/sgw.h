@@ -115,6 +115,20 @@ const char *sgw_last_error(const sgw_ctx *ctx);
  * enclosing interval serves the Chebyshev maps that follow. */
 sgw_status sgw_bounds(sgw_ctx *ctx, double pad, double *emin, double *emax);
 
+/* Spectral interval from k Lanczos steps on the device (the paper finds the
+ * interval by shifted power iteration, Sec. 2.1; Lanczos gives both ends from
+ * one Krylov sequence).  Start: the +-1 white noise of RNG stream (kind 5,
+ * sample 0, l 0) for `seed`, unit Euclidean norm; no reorthogonalisation;
+ * FP64 dot products.  With theta the Ritz values of the k x k tridiagonal
+ * and r = beta_k |y_last| their residual norms,
+ *   emin = theta_min - r_min - pad (theta_max - theta_min),
+ *   emax = theta_max + r_max + pad (theta_max - theta_min),
+ * each clipped to the rigorous interval of sgw_bounds(pad = 0), which it can
+ * only narrow.  The ends are estimates: a Chebyshev recurrence that grows
+ * on such an interval reports SGW_EDIVERGED.  2 <= k <= 1000.  Synchronous. */
+sgw_status sgw_lanczos_bounds(sgw_ctx *ctx, int32_t k, uint64_t seed, double pad, double *emin,
+                              double *emax);
+
 /* hpsi[v] = H psi[v] for v < nvec (Eq. 1; Sec. 2.2: FFT pair for the
  * kinetic term, potential diagonal in r).  psi and hpsi are device batches
  * with leading dimension ld; they must not overlap.  With projectors in a

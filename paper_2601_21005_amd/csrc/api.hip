@@ -333,6 +333,45 @@ void check_state(sgw_ctx *ctx, const sgw_tdh_state *st) {
   (void)ctx;
 }
 
+// Rigorous interval [min V + min(0, min E) s, T_max + max V + max(0, max E) s]
+// (s: Gershgorin bound of the projector Gram matrix), widened by pad times
+// its width on each side.
+void weyl_bounds(sgw_ctx *ctx, double pad, double &emin, double &emax) {
+  double lo = 0, hi = 0;
+  if (ctx->has_kb) {
+    const double s = kb_lambda_bound(ctx);
+    const double emn = *std::min_element(ctx->kb.ekb.begin(), ctx->kb.ekb.end());
+    const double emx = *std::max_element(ctx->kb.ekb.begin(), ctx->kb.ekb.end());
+    lo = std::min(0.0, emn) * s;
+    hi = std::max(0.0, emx) * s;
+  }
+  const double a = ctx->vmin + lo, b = ctx->tmax + ctx->vmax + hi;
+  const double w = b - a;
+  emin = a - pad * w;
+  emax = b + pad * w;
+}
+
+// y = H x for nvec vectors (ld), in chunks of max_nvec
+void apply_h(sgw_ctx *ctx, const void *psi, void *hpsi, int64_t nvec, int64_t ld) {
+  const int64_t chunk = ctx->max_nvec;
+  void *tmp = ctx->buf("tmp", ctx->csize() * ctx->N * chunk).p;
+  for (int64_t v0 = 0; v0 < nvec; v0 += chunk) {
+    const int64_t nv = std::min(chunk, nvec - v0);
+    const char *x = static_cast<const char *>(psi) + v0 * ld * ctx->csize();
+    char *y = static_cast<char *>(hpsi) + v0 * ld * ctx->csize();
+    void *kbC = nullptr;
+    if (ctx->has_kb) {
+      kbC = ctx->buf("kbC", ctx->csize() * ctx->kb.nproj * nv).p;
+      kb_gather_e(ctx, x, nv, ld, kbC);
+    }
+    EpiArgs e;
+    e.x = x;
+    e.vloc = ctx->d_vloc.p;
+    fft3d_apply(ctx, x, tmp, y, nv, ld, MUL_KIN, 0.0, PLANE_INV_HPSI, e);
+    if (ctx->has_kb) kb_scatter(ctx, kbC, nv, y, ld, 1.0, 0.0, nullptr, 0.0, 0.0);
+  }
+}
+
 int next_pow2(int n) {
   int p = 1;
   while (p < n) p *= 2;
@@ -448,18 +487,7 @@ sgw_status sgw_bounds(sgw_ctx *ctx, double pad, double *emin, double *emax) {
   return guarded(ctx, [&] {
     SGW_REQUIRE(emin && emax, SGW_EINVAL, "emin/emax NULL");
     SGW_REQUIRE(pad >= 0 && std::isfinite(pad), SGW_EINVAL, "pad must be >= 0");
-    double lo = 0, hi = 0;
-    if (ctx->has_kb) {
-      const double s = kb_lambda_bound(ctx);
-      const double emn = *std::min_element(ctx->kb.ekb.begin(), ctx->kb.ekb.end());
-      const double emx = *std::max_element(ctx->kb.ekb.begin(), ctx->kb.ekb.end());
-      lo = std::min(0.0, emn) * s;
-      hi = std::max(0.0, emx) * s;
-    }
-    const double a = ctx->vmin + lo, b = ctx->tmax + ctx->vmax + hi;
-    const double w = b - a;
-    *emin = a - pad * w;
-    *emax = b + pad * w;
+    weyl_bounds(ctx, pad, *emin, *emax);
   });
 }
 
@@ -471,23 +499,67 @@ sgw_status sgw_apply_H(sgw_ctx *ctx, const void *psi, void *hpsi, int64_t nvec, 
     check_ptr(psi, "psi");
     check_ptr(hpsi, "hpsi");
     SGW_REQUIRE(psi != hpsi, SGW_EINVAL, "psi and hpsi must not overlap");
-    const int64_t chunk = ctx->max_nvec;
-    void *tmp = ctx->buf("tmp", ctx->csize() * ctx->N * chunk).p;
-    for (int64_t v0 = 0; v0 < nvec; v0 += chunk) {
-      const int64_t nv = std::min(chunk, nvec - v0);
-      const char *x = static_cast<const char *>(psi) + v0 * ld * ctx->csize();
-      char *y = static_cast<char *>(hpsi) + v0 * ld * ctx->csize();
-      void *kbC = nullptr;
-      if (ctx->has_kb) {
-        kbC = ctx->buf("kbC", ctx->csize() * ctx->kb.nproj * nv).p;
-        kb_gather_e(ctx, x, nv, ld, kbC);
-      }
-      EpiArgs e;
-      e.x = x;
-      e.vloc = ctx->d_vloc.p;
-      fft3d_apply(ctx, x, tmp, y, nv, ld, MUL_KIN, 0.0, PLANE_INV_HPSI, e);
-      if (ctx->has_kb) kb_scatter(ctx, kbC, nv, y, ld, 1.0, 0.0, nullptr, 0.0, 0.0);
+    apply_h(ctx, psi, hpsi, nvec, ld);
+  });
+}
+
+sgw_status sgw_lanczos_bounds(sgw_ctx *ctx, int32_t k, uint64_t seed, double pad, double *emin,
+                              double *emax) {
+  if (!ctx) return SGW_EINVAL;
+  return guarded(ctx, [&] {
+    SGW_REQUIRE(emin && emax, SGW_EINVAL, "emin/emax NULL");
+    SGW_REQUIRE(k >= 2 && k <= 1000, SGW_EINVAL, "k must be in 2..1000");
+    SGW_REQUIRE(pad >= 0 && std::isfinite(pad), SGW_EINVAL, "pad must be >= 0");
+    const int64_t N = ctx->N;
+    const size_t cs = ctx->csize();
+    void *v = ctx->buf("lz_v", cs * N).p, *vp = ctx->buf("lz_vp", cs * N).p;
+    void *w = ctx->buf("lz_w", cs * N).p;
+    double *d = ctx->buf("lz_dot", sizeof(double)).as<double>();
+    auto fetch = [&]() {
+      double x = 0;
+      SGW_HIP(hipMemcpyAsync(&x, d, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+      SGW_HIP(hipStreamSynchronize(ctx->stream));
+      return x;
+    };
+    // start: +-1 white noise of stream (BOUNDS, 0, 0), unit Euclidean norm
+    const uint64_t key = rng_key(seed, rng_stream(RNG_BOUNDS, 0, 0));
+    DevBuf &dk = ctx->buf("lz_key", sizeof(uint64_t));
+    SGW_HIP(hipMemcpyAsync(dk.p, &key, sizeof key, hipMemcpyHostToDevice, ctx->stream));
+    launch_fill_noise(ctx, dk.as<uint64_t>(), 1, v);
+    launch_norm2(ctx, v, N, 1, d);
+    launch_scale_copy(ctx, v, N, v, N, 1, 1.0 / std::sqrt(fetch()), 0.0);
+    launch_scale_copy(ctx, v, N, vp, N, 1, 0.0, 0.0);
+    std::vector<double> alpha, beta;
+    double b = 0;
+    for (int j = 0; j < k; ++j) {
+      apply_h(ctx, v, w, 1, N);
+      launch_redot(ctx, v, w, N, 1, d);
+      const double a = fetch();
+      launch_axpy(ctx, v, N, w, N, 1, -a, 0.0);
+      launch_axpy(ctx, vp, N, w, N, 1, -b, 0.0);
+      launch_norm2(ctx, w, N, 1, d);
+      b = std::sqrt(fetch());
+      SGW_REQUIRE(std::isfinite(a) && std::isfinite(b), SGW_EDIVERGED, "Lanczos produced a non-finite value");
+      alpha.push_back(a);
+      beta.push_back(b);
+      if (b == 0) break;
+      launch_copy(ctx, v, N, vp, N, 1);
+      launch_scale_copy(ctx, w, N, v, N, 1, 1.0 / b, 0.0);
     }
+    const int n = (int)alpha.size();
+    std::vector<double> T((size_t)n * n, 0.0), vals, vecs;
+    for (int i = 0; i < n; ++i) {
+      T[(size_t)i * n + i] = alpha[i];
+      if (i + 1 < n) T[(size_t)i * n + i + 1] = T[(size_t)(i + 1) * n + i] = beta[i];
+    }
+    jacobi_eigen(n, T, vals, vecs);
+    const double r0 = beta[n - 1] * std::fabs(vecs[(size_t)(n - 1) * n + 0]);
+    const double r1 = beta[n - 1] * std::fabs(vecs[(size_t)(n - 1) * n + n - 1]);
+    const double width = vals[n - 1] - vals[0];
+    double lo_w = 0, hi_w = 0;
+    weyl_bounds(ctx, 0.0, lo_w, hi_w);
+    *emin = std::max(lo_w, vals[0] - r0 - pad * width);
+    *emax = std::min(hi_w, vals[n - 1] + r1 + pad * width);
   });
 }
 

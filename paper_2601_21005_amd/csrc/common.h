@@ -274,6 +274,10 @@ void kb_scatter(sgw_ctx *ctx, const void *coef, int64_t nvec, void *dst, int64_t
 void kb_upload_operands(sgw_ctx *ctx);
 
 // host utilities (host.cpp)
+// eigenvalues (ascending) and eigenvectors (columns, row-major) of a small
+// symmetric matrix (row-major, destroyed)
+void jacobi_eigen(int n, std::vector<double> &a, std::vector<double> &vals,
+                  std::vector<double> &vecs);
 void build_kb(sgw_ctx *ctx, const sgw_projectors *p);
 // K (complex, [nproj][nproj] interleaved) with exp(-i tau V_NL) = I + dV B K B^T
 void kb_exponential_matrix(const sgw_ctx *ctx, double tau, std::vector<double> &K);

@@ -501,4 +501,57 @@ void tune_cache_store(const std::string &key, int choice) {
   std::rename(tmp.c_str(), path);
 }
 
+
+// ---------------------------------------------------------------- small eigenproblems
+// Eigenvalues (ascending) and eigenvectors of a symmetric n x n matrix by
+// cyclic Jacobi rotations (Rutishauser's form); a: row-major, destroyed;
+// vecs: row-major, column i is the eigenvector of vals[i].
+void jacobi_eigen(int n, std::vector<double> &a, std::vector<double> &vals,
+                  std::vector<double> &vecs) {
+  vecs.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) vecs[(size_t)i * n + i] = 1.0;
+  double scale = 0;
+  for (double x : a) scale = std::max(scale, std::fabs(x));
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) off += a[(size_t)p * n + q] * a[(size_t)p * n + q];
+    if (off <= 1e-60 * scale * scale + 1e-300) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = a[(size_t)p * n + q];
+        if (std::fabs(apq) < 1e-300) continue;
+        const double th = (a[(size_t)q * n + q] - a[(size_t)p * n + p]) / (2.0 * apq);
+        const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
+        for (int r = 0; r < n; ++r) {          // columns p, q
+          const double arp = a[(size_t)r * n + p], arq = a[(size_t)r * n + q];
+          a[(size_t)r * n + p] = c * arp - sn * arq;
+          a[(size_t)r * n + q] = sn * arp + c * arq;
+        }
+        for (int r = 0; r < n; ++r) {          // rows p, q
+          const double apr = a[(size_t)p * n + r], aqr = a[(size_t)q * n + r];
+          a[(size_t)p * n + r] = c * apr - sn * aqr;
+          a[(size_t)q * n + r] = sn * apr + c * aqr;
+        }
+        for (int r = 0; r < n; ++r) {
+          const double vrp = vecs[(size_t)r * n + p], vrq = vecs[(size_t)r * n + q];
+          vecs[(size_t)r * n + p] = c * vrp - sn * vrq;
+          vecs[(size_t)r * n + q] = sn * vrp + c * vrq;
+        }
+      }
+  }
+  std::vector<int> idx(n);
+  for (int i = 0; i < n; ++i) idx[i] = i;
+  std::sort(idx.begin(), idx.end(),
+            [&](int x, int y) { return a[(size_t)x * n + x] < a[(size_t)y * n + y]; });
+  std::vector<double> v2((size_t)n * n);
+  vals.resize(n);
+  for (int i = 0; i < n; ++i) {
+    vals[i] = a[(size_t)idx[i] * n + idx[i]];
+    for (int r = 0; r < n; ++r) v2[(size_t)r * n + i] = vecs[(size_t)r * n + idx[i]];
+  }
+  vecs.swap(v2);
+}
+
 }  // namespace sgw

@@ -12,7 +12,10 @@
 
 namespace sgw {
 
-enum RngKind : uint64_t { RNG_ZETA = 1, RNG_ETA = 2, RNG_XI_SUPPORT = 3, RNG_XI_SIGN = 4 };
+enum RngKind : uint64_t {
+  RNG_ZETA = 1, RNG_ETA = 2, RNG_XI_SUPPORT = 3, RNG_XI_SIGN = 4,
+  RNG_BOUNDS = 5   // start vector of the Lanczos interval
+};
 
 __host__ __device__ __forceinline__ uint64_t sm64(uint64_t x) {
   uint64_t z = x + 0x9E3779B97F4A7C15ull;

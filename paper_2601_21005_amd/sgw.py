@@ -21,7 +21,8 @@ STATUS_NAMES = {0: "SGW_OK", -1: "SGW_EINVAL", -2: "SGW_ENOMEM", -3: "SGW_EHIP",
                 -4: "SGW_EDIVERGED", -5: "SGW_ENOROOT", -6: "SGW_EUNSUPPORTED"}
 
 # every entry point declared in include/sgw.h
-EXPORTS = ["sgw_create", "sgw_destroy", "sgw_last_error", "sgw_bounds", "sgw_apply_H",
+EXPORTS = ["sgw_create", "sgw_destroy", "sgw_last_error", "sgw_bounds", "sgw_lanczos_bounds",
+           "sgw_apply_H",
            "sgw_fermi_coefficients", "sgw_gapped_coefficients", "sgw_fermi_filter", "sgw_propagator_coefficients",
            "sgw_cheb_propagate", "sgw_tdh_init", "sgw_tdh_step", "sgw_sigma_estimate",
            "sgw_qp_solve", "sgw_sigma_omega", "sgw_kernel_timer", "sgw_kernel_timer_read",
@@ -102,6 +103,7 @@ def load():
     lib.sgw_last_error.argtypes = [vp]
     lib.sgw_last_error.restype = C.c_char_p
     lib.sgw_bounds.argtypes = [vp, d, dp, dp]
+    lib.sgw_lanczos_bounds.argtypes = [vp, i32, C.c_uint64, d, dp, dp]
     lib.sgw_apply_H.argtypes = [vp, vp, vp, i64, i64]
     lib.sgw_fermi_coefficients.argtypes = [d, d, d, d, i32, dp]
     lib.sgw_gapped_coefficients.argtypes = [d, d, d, d, d, i32, dp]
@@ -277,6 +279,12 @@ class Context:
     def bounds(self, pad=0.01):
         a, b = C.c_double(), C.c_double()
         _check(load().sgw_bounds(self.ctx, pad, C.byref(a), C.byref(b)), self.ctx)
+        return a.value, b.value
+
+    def lanczos_bounds(self, k=40, seed=0, pad=0.01):
+        a, b = C.c_double(), C.c_double()
+        _check(load().sgw_lanczos_bounds(self.ctx, int(k), int(seed), pad, C.byref(a),
+                                         C.byref(b)), self.ctx)
         return a.value, b.value
 
     def apply_H(self, psi, hpsi):

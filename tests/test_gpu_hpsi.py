@@ -125,3 +125,32 @@ def test_kb_variants_bit_identical(si35, monkeypatch, prec, names):
                 ref = out
             else:
                 assert np.array_equal(out, ref), (g, sc)
+
+
+def test_lanczos_bounds_match_oracle(tiny8, tiny8_eig):
+    """40 Lanczos steps from the same start vector on the device (C128) and
+    in the oracle give the same interval, and it encloses the spectrum."""
+    from oracle import eigen
+    s, H = tiny8
+    e, _ = tiny8_eig
+    ctx = make_ctx(s, sgw.SGW_C128)
+    lo, hi = ctx.lanczos_bounds(40, seed=3, pad=0.01)
+    ctx.close()
+    lo_o, hi_o = eigen.lanczos_bounds(H, 40, seed=3, pad=0.01)
+    w = e[-1] - e[0]
+    assert abs(lo - lo_o) < 1e-6 * w and abs(hi - hi_o) < 1e-6 * w
+    assert lo <= e[0] and hi >= e[-1]
+
+
+def test_lanczos_bounds_si35h36_fp32(si35):
+    """On the 64^3 cluster in complex FP32 the Lanczos interval encloses the
+    extreme eigenvalues (-8.0305409, 28.0, from FP64 Lanczos to 1e-6) and is
+    at least 10% narrower than the rigorous one."""
+    s, H = si35
+    ctx = make_ctx(s, sgw.SGW_C64)
+    lo, hi = ctx.lanczos_bounds(60, seed=1, pad=0.01)
+    lw, hw = ctx.bounds(0.0)
+    ctx.close()
+    assert lo <= -8.0305409 and hi >= 27.99999
+    assert lw <= lo and hi <= hw
+    assert hi - lo < 0.9 * (hw - lw)
