@@ -140,7 +140,7 @@ void build_kb(sgw_ctx *ctx, const sgw_projectors *P) {
     }
   int maxe = 0;
   for (int t = 0; t < ntile; ++t) maxe = std::max(maxe, kb.tile_off[t + 1] - kb.tile_off[t]);
-  SGW_REQUIRE(maxe <= 256, SGW_EUNSUPPORTED, "more than 256 projectors meet one 8^3 tile");
+  SGW_REQUIRE(maxe <= 256, SGW_EUNSUPPORTED, "more than 256 projectors meet one 512-point tile");
   // entries grouped per projector, ascending entry id
   kb.proj_off.assign(np + 1, 0);
   for (int e = 0; e < nentry; ++e) kb.proj_off[kb.entry_proj[e] + 1]++;

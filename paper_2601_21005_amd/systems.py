@@ -159,18 +159,30 @@ def cluster_model(species, pos, n=64, h=0.5, ecut=28.0, params=None,
     g = GridSpec(n, h)
     L = g.L
     pos = np.asarray(pos, dtype=np.float64) + 0.5 * L
-    r = grid_coords(g)
-    v = np.zeros(g.N)
+    v = np.zeros((n, n, n))                  # [z][y][x]
     l, m, rc, ekb, begin = [], [], [], [], [0]
     for sp_, R in zip(species, pos):
         prm = params[sp_]
-        d = _min_image(r - R, L)
-        v -= prm["A"] * np.exp(-np.sum(d * d, axis=1) / (2.0 * prm["s"] ** 2))
+        # each well on the periodic grid points within 8 widths of its atom
+        # (the tail left out is below 1e-13 of the depth)
+        reach = int(np.ceil(8.0 * prm["s"] / h))
+        ax = []
+        for a in range(3):
+            c = int(np.floor(R[a] / h))
+            idx = np.arange(c - reach, c + reach + 2)
+            if idx.size >= n:
+                idx = np.arange(n)
+            d = _min_image(idx * h - R[a], L) if idx.size == n else idx * h - R[a]
+            ax.append((np.mod(idx, n), d))
+        (ix, dx), (iy, dy), (iz, dz) = ax
+        d2 = dz[:, None, None] ** 2 + dy[None, :, None] ** 2 + dx[None, None, :] ** 2
+        v[np.ix_(iz, iy, ix)] -= prm["A"] * np.exp(-d2 / (2.0 * prm["s"] ** 2))
         l.append(0); m.append(0); rc.append(prm["rc"]); ekb.append(prm["e_s"])
         if prm["e_p"] is not None:
             for a in range(3):
                 l.append(1); m.append(a); rc.append(prm["rc"]); ekb.append(prm["e_p"])
         begin.append(len(l))
+    v = v.ravel()
     proj = ProjectorSpec(pos=pos, proj_begin=np.array(begin, dtype=np.int32),
                          l=np.array(l, dtype=np.int32), m=np.array(m, dtype=np.int32),
                          rc=np.array(rc, dtype=np.float64),
@@ -183,6 +195,14 @@ def cluster_model(species, pos, n=64, h=0.5, ecut=28.0, params=None,
 def si35h36(seed=1002, n=64, h=0.5, ecut=28.0):
     species, pos = si_cluster(35, seed=seed)
     return cluster_model(species, pos, n=n, h=h, ecut=ecut, name="Si35H36")
+
+
+def si357h204(seed=1003, n=128, h=0.6, ecut=28.0):
+    """Stand-in for the Si353H196 cluster on a 128^3 grid (h = 0.6 bohr):
+    357 Si atoms is the atom-centred shell closure nearest 353; 204 H caps,
+    1632 projectors, 816 occupied states."""
+    species, pos = si_cluster(357, seed=seed)
+    return cluster_model(species, pos, n=n, h=h, ecut=ecut, name="Si357H204")
 
 
 def tiny_system(n=8, h=0.7, with_kb=True, n_occ=2):
