@@ -27,6 +27,8 @@ def main():
     ap.add_argument("--n-tau", type=int, default=100)
     ap.add_argument("--dt", type=float, default=0.05)
     ap.add_argument("--n", type=int, default=128)
+    ap.add_argument("--window", type=float, default=0.3,
+                    help="minimum width (Ha) of the filter's transition window")
     args = ap.parse_args()
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     import torch
@@ -52,17 +54,23 @@ def main():
           f"(states {time.perf_counter() - t1:.1f} s, max residual {res.max():.1e})", flush=True)
     states = {"HOMO": (phis[s.n_occ - 1].cpu().numpy(), homo),
               "LUMO": (phis[s.n_occ].cpu().numpy(), lumo)}
-    a = sgw.sgw_gapped_coefficients(homo, lumo, 1e-7, emin, emax, 16384)
+    # The model's gap at this size is far smaller than the real cluster's, so
+    # the filter's transition is spread over a window of at least
+    # args.window Ha centred mid-gap -- the same filter in every precision.
+    mid, half = 0.5 * (homo + lumo), max(0.5 * (lumo - homo), 0.5 * args.window)
+    eh, el = mid - half, mid + half
+    a = sgw.sgw_gapped_coefficients(eh, el, 1e-7, emin, emax, 16384)
     tail = np.cumsum(np.abs(a[::-1]))[::-1]
     ncoef = int(np.nonzero(tail < 1e-7)[0][0])
     p = dict(seed=1003, n_eta=args.n_eta, n_tau=args.n_tau, dt=args.dt, m_sub=1, ncoef=ncoef,
-             emin=emin, emax=emax, n_xi=10000, f_g=0.003, mode=0, filter=1, e_homo=homo,
-             e_lumo=lumo, filter_eps=1e-7)
+             emin=emin, emax=emax, n_xi=10000, f_g=0.003, mode=0, filter=1, e_homo=eh,
+             e_lumo=el, filter_eps=1e-7)
     gam = 3.0 / (args.n_tau * args.dt)
     out = {"system": s.name, "grid": list(s.grid.n) if hasattr(s.grid.n, "__len__") else s.grid.n,
            "h": s.grid.h, "projectors": int(len(s.projectors.l)), "n_occ": s.n_occ,
            "samples": args.n_zeta, "n_eta": args.n_eta, "n_tau": args.n_tau, "ncoef": ncoef,
-           "interval_Ha": [emin, emax], "results": {}}
+           "interval_Ha": [emin, emax], "homo_lumo_Ha": [homo, lumo],
+           "filter_window_Ha": [eh, el], "results": {}}
     c64.close()
     for prec, name in ((sgw.SGW_C128, "c128"), (sgw.SGW_C64, "c64"),
                        (sgw.SGW_C64_BF16KB, "c64_bf16kb")):
