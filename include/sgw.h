@@ -51,9 +51,12 @@ typedef enum {
 typedef enum {
   SGW_C128 = 0,           /* complex double throughout */
   SGW_C64 = 1,            /* complex float; FP64 coefficients and sums */
-  SGW_C64_BF16KB = 2      /* as SGW_C64, but the projector GEMMs take their operands
+  SGW_C64_BF16KB = 2,     /* as SGW_C64, but the projector GEMMs take their operands
                            * (beta, psi, the mixed coefficients) rounded to BF16
                            * (nearest even) with FP32 accumulation on MFMA */
+  SGW_C64_BF16X2KB = 3    /* as SGW_C64_BF16KB, but psi and the mixed coefficients
+                           * enter as two BF16 terms (hi + lo, two MFMAs); beta is
+                           * one BF16 term */
 } sgw_precision;
 
 /* Grid (Eq. 1 on a Fourier grid, Sec. 2.2).  ecut > 0 clips the kinetic

@@ -394,8 +394,9 @@ sgw_status sgw_create(const sgw_grid *grid, const double *v_loc, const sgw_proje
   sgw_status st = guarded(nullptr, [&] {
     SGW_REQUIRE(out != nullptr, SGW_EINVAL, "out is NULL");
     SGW_REQUIRE(grid != nullptr && v_loc != nullptr, SGW_EINVAL, "grid or v_loc is NULL");
-    SGW_REQUIRE(prec == SGW_C128 || prec == SGW_C64 || prec == SGW_C64_BF16KB, SGW_EINVAL,
-                "unknown precision");
+    SGW_REQUIRE(prec == SGW_C128 || prec == SGW_C64 || prec == SGW_C64_BF16KB ||
+                    prec == SGW_C64_BF16X2KB,
+                SGW_EINVAL, "unknown precision");
     SGW_REQUIRE(grid->nx > 0 && grid->ny > 0 && grid->nz > 0, SGW_EINVAL, "grid sizes must be > 0");
     SGW_REQUIRE(grid->h > 0 && std::isfinite(grid->h), SGW_EINVAL, "grid spacing must be > 0");
     SGW_REQUIRE(std::isfinite(grid->ecut), SGW_EINVAL, "ecut not finite");

@@ -173,7 +173,8 @@ __global__ __launch_bounds__(NTK) void k_kb_scatter(const cplx<R> *coef, int64_t
 // (M = projector entries, K = 512 points, N = 2 NVB real columns = NVB
 // complex vectors) and the scatter  D[p][c] = sum_e beta[e][p] C'[e][c]
 // (M = 512 points, K = entries padded to 32).  The operands are stored in
-// FP32 (SGW_C64) or in BF16 rounded to nearest even (SGW_C64_BF16KB); the
+// FP32 (SGW_C64) or in BF16 rounded to nearest even (SGW_C64_BF16KB; with
+// SGW_C64_BF16X2KB the psi / coefficient operand as two BF16 terms); the
 // accumulation is FP32 either way.  A lane feeds 16 contiguous bytes of A and
 // of B per group of K values:
 //   FP32: four v_mfma_f32_16x16x4f32, K group 16, lane l holds the K slots
@@ -199,6 +200,7 @@ __host__ __device__ __forceinline__ uint32_t bf16_bits(float f) {
 struct OpF32 {
   using T = float;
   static constexpr int GK = 16;
+  static constexpr bool SPLIT = false;
   __device__ static void mma(f32x4 &acc, const u32x4 &a, const u32x4 &b) {
     acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a[0]), __uint_as_float(b[0]), acc, 0, 0, 0);
     acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a[1]), __uint_as_float(b[1]), acc, 0, 0, 0);
@@ -218,6 +220,7 @@ struct OpF32 {
 struct OpBF16 {
   using T = uint16_t;
   static constexpr int GK = 32;
+  static constexpr bool SPLIT = false;
   __device__ static void mma(f32x4 &acc, const u32x4 &a, const u32x4 &b) {
     acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
                                                   __builtin_bit_cast(bf16x8, b), acc, 0, 0, 0);
@@ -229,6 +232,31 @@ struct OpBF16 {
   __device__ static u32x4 pack(const float *e) {      // 8 values -> one operand (RNE)
     return u32x4{bf16_bits(e[0]) | (bf16_bits(e[1]) << 16), bf16_bits(e[2]) | (bf16_bits(e[3]) << 16),
                  bf16_bits(e[4]) | (bf16_bits(e[5]) << 16), bf16_bits(e[6]) | (bf16_bits(e[7]) << 16)};
+  }
+};
+
+__device__ __forceinline__ float bf16_value(uint32_t b) { return __uint_as_float(b << 16); }
+
+// BF16 products with the state-vector operand (psi in the gather, the mixed
+// coefficients in the scatter) carried as two BF16 terms hi + lo, hi = RNE(x),
+// lo = RNE(x - hi): two MFMAs per operand pair, the split operand exact to
+// about 2^-17; beta stays one BF16 term.
+struct OpBF16x2 : OpBF16 {
+  static constexpr bool SPLIT = true;
+  __device__ static void pack2(const float *e, u32x4 &hi, u32x4 &lo) {
+    uint32_t h[8], l[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      h[i] = bf16_bits(e[i]);
+      l[i] = bf16_bits(e[i] - bf16_value(h[i]));
+    }
+    hi = u32x4{h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16), h[6] | (h[7] << 16)};
+    lo = u32x4{l[0] | (l[1] << 16), l[2] | (l[3] << 16), l[4] | (l[5] << 16), l[6] | (l[7] << 16)};
+  }
+  __device__ static void put1x2(T *dhi, T *dlo, float x) {
+    const uint32_t h = bf16_bits(x);
+    *dhi = (uint16_t)h;
+    *dlo = (uint16_t)bf16_bits(x - bf16_value(h));
   }
 };
 
@@ -276,6 +304,7 @@ __global__ __launch_bounds__(NTK) void k_kb_gather_mma(
   const int off = tile_off[t], ne = tile_off[t + 1] - off;
   // B operands of this wave's quarter of K, kept in registers for all entries
   u32x4 b[NG][NTL];
+  u32x4 blo[Op::SPLIT ? NG : 1][Op::SPLIT ? NTL : 1];
 #pragma unroll
   for (int n = 0; n < NTL; ++n) {
     const int64_t v = v0 + 8 * n + (col >> 1);
@@ -292,7 +321,8 @@ __global__ __launch_bounds__(NTK) void k_kb_gather_mma(
         e[2 * h] = (col & 1) ? z.y : z.x;
         e[2 * h + 1] = (col & 1) ? z.w : z.z;
       }
-      b[g][n] = Op::pack(e);
+      if constexpr (Op::SPLIT) Op::pack2(e, b[g][n], blo[g][n]);
+      else b[g][n] = Op::pack(e);
     }
   }
   for (int mg = 0; mg < ne; mg += 16 * MT) {
@@ -314,7 +344,10 @@ __global__ __launch_bounds__(NTK) void k_kb_gather_mma(
       for (int j = 0; j < MT; ++j)
         if (mg + 16 * j < ne)
 #pragma unroll
-          for (int n = 0; n < NTL; ++n) Op::mma(acc[j][n], a[j], b[g][n]);
+          for (int n = 0; n < NTL; ++n) {
+            Op::mma(acc[j][n], a[j], b[g][n]);
+            if constexpr (Op::SPLIT) Op::mma(acc[j][n], a[j], blo[g][n]);
+          }
     }
     // a barrier between the last products and the LDS writes of their
     // accumulators (without it the <8, 2> instantiation read some
@@ -357,7 +390,7 @@ __global__ __launch_bounds__(NTK) void k_kb_scatter_mma(
   constexpr int NC = 2 * NVB, NTL = NC / 16;
   constexpr int EL = 16 / (int)sizeof(T);
   constexpr int PE = KB_MAXE + EL;                  // LDS pitch of a coefficient column
-  __shared__ __align__(16) T sc[NC * PE];          // C' [column][entry]
+  __shared__ __align__(16) T sc[(Op::SPLIT ? 2 : 1) * NC * PE];   // C' [column][entry] (hi, lo)
   int t;
   int64_t vb;
   if (!tile_block(ntile, nvb, t, vb)) return;
@@ -379,8 +412,13 @@ __global__ __launch_bounds__(NTK) void k_kb_scatter_mma(
     for (int u = 0; u < 4; ++u) {
       const int idx = i0 + u * NTK + tid, el = idx / NVB, vl = idx % NVB;
       if (el < nek) {
-        Op::put1(sc + (2 * vl) * PE + el, val[u].x);
-        Op::put1(sc + (2 * vl + 1) * PE + el, val[u].y);
+        if constexpr (Op::SPLIT) {
+          Op::put1x2(sc + (2 * vl) * PE + el, sc + NC * PE + (2 * vl) * PE + el, val[u].x);
+          Op::put1x2(sc + (2 * vl + 1) * PE + el, sc + NC * PE + (2 * vl + 1) * PE + el, val[u].y);
+        } else {
+          Op::put1(sc + (2 * vl) * PE + el, val[u].x);
+          Op::put1(sc + (2 * vl + 1) * PE + el, val[u].y);
+        }
       }
     }
   }
@@ -422,12 +460,16 @@ __global__ __launch_bounds__(NTK) void k_kb_scatter_mma(
 #pragma unroll
     for (int n = 0; n < NTL; ++n) acc[j][n] = f32x4{0.f, 0.f, 0.f, 0.f};
   const T *bt = betaT + (int64_t)offT * KB_TP + (int64_t)(128 * w + col) * nek + EL * q;
-  u32x4 a_cur[8], a_nxt[8], b_cur[NTL], b_nxt[NTL];
-  auto load_group = [&](int k0, u32x4 *a, u32x4 *b) {
+  constexpr int NS = Op::SPLIT ? 2 : 1;            // B terms (hi, lo)
+  u32x4 a_cur[8], a_nxt[8], b_cur[NS][NTL], b_nxt[NS][NTL];
+  auto load_group = [&](int k0, u32x4 *a, u32x4 (*b)[NTL]) {
 #pragma unroll
     for (int j = 0; j < 8; ++j) a[j] = ld16(bt + (int64_t)(16 * j) * nek + k0);
 #pragma unroll
-    for (int n = 0; n < NTL; ++n) b[n] = ld16(sc + (16 * n + col) * PE + k0 + EL * q);
+    for (int h = 0; h < NS; ++h)
+#pragma unroll
+      for (int n = 0; n < NTL; ++n)
+        b[h][n] = ld16(sc + h * NC * PE + (16 * n + col) * PE + k0 + EL * q);
   };
   if (nek > 0) load_group(0, a_cur, b_cur);
   for (int k0 = 0; k0 < nek; k0 += Op::GK) {
@@ -435,11 +477,15 @@ __global__ __launch_bounds__(NTK) void k_kb_scatter_mma(
 #pragma unroll
     for (int j = 0; j < 8; ++j)
 #pragma unroll
-      for (int n = 0; n < NTL; ++n) Op::mma(acc[j][n], a_cur[j], b_cur[n]);
+      for (int n = 0; n < NTL; ++n)
+#pragma unroll
+        for (int h = 0; h < NS; ++h) Op::mma(acc[j][n], a_cur[j], b_cur[h][n]);
 #pragma unroll
     for (int j = 0; j < 8; ++j) a_cur[j] = a_nxt[j];
 #pragma unroll
-    for (int n = 0; n < NTL; ++n) b_cur[n] = b_nxt[n];
+    for (int h = 0; h < NS; ++h)
+#pragma unroll
+      for (int n = 0; n < NTL; ++n) b_cur[h][n] = b_nxt[h][n];
   }
   float2 c[8][NTL][2];
 #pragma unroll
@@ -525,7 +571,7 @@ void kb_upload_operands(sgw_ctx *ctx) {
   }
   upload(ctx->d_kb_tile_offT, offT.data(), offT.size());
   const size_t nT = (size_t)offT[nt] * KB_TP;
-  const bool bf = ctx->prec == SGW_C64_BF16KB;
+  const bool bf = ctx->prec == SGW_C64_BF16KB || ctx->prec == SGW_C64_BF16X2KB;
   auto fill_T = [&](auto *out, auto conv) {
     for (int t = 0; t < nt; ++t) {
       const int e0 = kb.tile_off[t], ne = kb.tile_off[t + 1] - e0, nek = offT[t + 1] - offT[t];
@@ -575,6 +621,8 @@ static void gather_t(sgw_ctx *ctx, const void *psi, int64_t nvec, int64_t ld, vo
     };
     if (ctx->prec == SGW_C64_BF16KB)
       go(OpBF16{}, "kb_gather_bf16", ctx->d_kb_beta16.as<uint16_t>());
+    else if (ctx->prec == SGW_C64_BF16X2KB)
+      go(OpBF16x2{}, "kb_gather_bf16x2", ctx->d_kb_beta16.as<uint16_t>());
     else
       go(OpF32{}, "kb_gather", ctx->d_kb_beta.as<float>());
   } else {
@@ -642,6 +690,8 @@ static void scatter_t(sgw_ctx *ctx, const void *coef, int64_t nvec, void *dst, i
     };
     if (ctx->prec == SGW_C64_BF16KB)
       go(OpBF16{}, "kb_scatter_bf16", ctx->d_kb_betaT.as<uint16_t>());
+    else if (ctx->prec == SGW_C64_BF16X2KB)
+      go(OpBF16x2{}, "kb_scatter_bf16x2", ctx->d_kb_betaT.as<uint16_t>());
     else
       go(OpF32{}, "kb_scatter", ctx->d_kb_betaT.as<float>());
     SGW_HIP(hipGetLastError());

@@ -73,7 +73,7 @@ def main():
            "filter_window_Ha": [eh, el], "results": {}}
     c64.close()
     for prec, name in ((sgw.SGW_C128, "c128"), (sgw.SGW_C64, "c64"),
-                       (sgw.SGW_C64_BF16KB, "c64_bf16kb")):
+                       (sgw.SGW_C64_BF16KB, "c64_bf16kb"), (sgw.SGW_C64_BF16X2KB, "c64_bf16x2kb")):
         ctx = ctx_of(prec)
         for st, (phi, eks) in states.items():
             t2 = time.perf_counter()
@@ -91,7 +91,7 @@ def main():
     for st, r in out["results"].items():
         ref = r["c128"]
         s_ref = np.array(ref["sigma_t"][0]) + 1j * np.array(ref["sigma_t"][1])
-        for name in ("c64", "c64_bf16kb"):
+        for name in ("c64", "c64_bf16kb", "c64_bf16x2kb"):
             s_x = np.array(r[name]["sigma_t"][0]) + 1j * np.array(r[name]["sigma_t"][1])
             summary[f"{st}_{name}"] = {
                 "d_eqp_meV": 1e3 * abs(r[name]["eqp_eV"] - ref["eqp_eV"]),

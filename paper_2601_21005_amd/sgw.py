@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libsgw.so")
 
 SGW_OK, SGW_EINVAL, SGW_ENOMEM, SGW_EHIP, SGW_EDIVERGED, SGW_ENOROOT, SGW_EUNSUPPORTED = \
     0, -1, -2, -3, -4, -5, -6
-SGW_C128, SGW_C64, SGW_C64_BF16KB = 0, 1, 2
+SGW_C128, SGW_C64, SGW_C64_BF16KB, SGW_C64_BF16X2KB = 0, 1, 2, 3
 
 STATUS_NAMES = {0: "SGW_OK", -1: "SGW_EINVAL", -2: "SGW_ENOMEM", -3: "SGW_EHIP",
                 -4: "SGW_EDIVERGED", -5: "SGW_ENOROOT", -6: "SGW_EUNSUPPORTED"}

@@ -104,7 +104,9 @@ def test_bounds_match_oracle(si35, tiny8):
 
 
 @pytest.mark.parametrize("prec,names", [(sgw.SGW_C64, ("kb_gather", "kb_scatter")),
-                                         (sgw.SGW_C64_BF16KB, ("kb_gather_bf16", "kb_scatter_bf16"))])
+                                         (sgw.SGW_C64_BF16KB, ("kb_gather_bf16", "kb_scatter_bf16")),
+                                         (sgw.SGW_C64_BF16X2KB,
+                                          ("kb_gather_bf16x2", "kb_scatter_bf16x2"))])
 def test_kb_variants_bit_identical(si35, monkeypatch, prec, names):
     """Every autotuned KB kernel variant adds the same products in the same
     order: H psi is bitwise the same whichever variant runs."""

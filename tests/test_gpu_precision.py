@@ -23,7 +23,8 @@ pytestmark = pytest.mark.gpu
 HA_EV = 27.211386245988
 U_BF16 = 2.0 ** -9          # unit roundoff of BF16 (8 significant bits)
 U_F32 = 2.0 ** -24
-NAMES = {sgw.SGW_C64: "c64", sgw.SGW_C64_BF16KB: "c64+bf16kb"}
+NAMES = {sgw.SGW_C64: "c64", sgw.SGW_C64_BF16KB: "c64+bf16kb",
+         sgw.SGW_C64_BF16X2KB: "c64+bf16x2kb"}
 
 
 def kb_abs_bound(H, x):
@@ -53,16 +54,43 @@ def bf16(a):
     return u.view(np.float32).astype(np.float64)
 
 
-def kb_bf16_model(H, x):
-    """The KB term as the BF16 kernels define it: beta and psi rounded to BF16
-    for the gather, E C rounded to BF16 for the scatter, all sums exact."""
+def kb_bf16_model(H, x, split=False):
+    """The KB term as the BF16 kernels define it: beta rounded to BF16; psi
+    for the gather and E C for the scatter rounded to BF16 too (split=False)
+    or kept whole (split=True: their two-term BF16 form is exact to ~2^-17);
+    all sums exact."""
     P = H.kb
     Bb = P.B.copy()
     Bb.data = bf16(Bb.data)
-    xb = bf16(x.real) + 1j * bf16(x.imag)
+    xb = x if split else bf16(x.real) + 1j * bf16(x.imag)
     C = (Bb.T @ xb.T) * H.grid.dV * P.ekb[:, None]          # [np][nvec]
-    Cb = bf16(C.real) + 1j * bf16(C.imag)
+    Cb = C if split else bf16(C.real) + 1j * bf16(C.imag)
     return (Bb @ Cb).T
+
+
+@pytest.mark.parametrize("which", ["tiny8", "si35"])
+def test_hpsi_bf16x2_within_rounding_bound(which, request):
+    """Split variant: only beta is rounded (twice used, u each) -> |error| <=
+    (2 u + K 2^-17 + K u_32) times the absolute-value KB term; against the
+    model with rounded beta and exact state operands, 2e-5 of that term."""
+    s, H = request.getfixturevalue(which)
+    rs = np.random.default_rng(14)
+    x = rs.standard_normal((6, s.grid.N)) + 1j * rs.standard_normal((6, s.grid.N))
+    ctx = make_ctx(s, sgw.SGW_C64_BF16X2KB, max_nvec=8)
+    xd = torch.from_numpy(x).to(torch.complex64).cuda()
+    yd = torch.empty_like(xd)
+    ctx.apply_H(xd, yd)
+    got = yd.cpu().numpy().astype(np.complex128)
+    xin = xd.cpu().numpy().astype(np.complex128)
+    ctx.close()
+    ref = H.apply(xin)
+    yabs = kb_abs_bound(H, xin)
+    nrm = np.linalg.norm(ref, axis=1)
+    bound = (2.1 * U_BF16 + 4096 * 2.0 ** -17 + 4096 * U_F32) * yabs
+    assert np.all(np.linalg.norm(got - ref, axis=1) <= np.linalg.norm(bound, axis=1) + 3e-6 * nrm)
+    model = H.apply_local(xin) + kb_bf16_model(H, xin, split=True)
+    dm = np.linalg.norm(got - model, axis=1)
+    assert np.all(dm <= 2e-5 * np.linalg.norm(yabs, axis=1) + 3e-6 * nrm), dm
 
 
 @pytest.mark.parametrize("which", ["tiny8", "si35"])
@@ -134,7 +162,7 @@ def si35_oracle(si35):
 ROWS = []
 
 
-@pytest.mark.parametrize("prec", [sgw.SGW_C64, sgw.SGW_C64_BF16KB])
+@pytest.mark.parametrize("prec", [sgw.SGW_C64, sgw.SGW_C64_BF16KB, sgw.SGW_C64_BF16X2KB])
 def test_precision_table_si35h36(si35, si35_oracle, prec):
     s, H = si35
     o = si35_oracle
