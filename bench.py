@@ -14,9 +14,10 @@ time ordering, zeta propagation, contraction) for a batch of samples, through
 sgw_sigma_estimate.  The QP energy of the HOMO and its per-sample spread give
 GPU-seconds per QP energy at +-0.03 eV.  Printed as one JSON line.
 
-Forms: "plain" (complex FP32, the value), "bf16kb_graphs" (projector GEMMs
-with BF16 operands, launch sequences replayed from HIP graphs; same samples,
-so the same spread) and, with --cv N, "control_variate": N more samples are
+Forms: "plain" (complex FP32, the value), "bf16kb_graphs" and
+"bf16x2kb_graphs" (projector GEMMs with BF16 operands, plain or with the
+state operand split into two BF16 terms; launch sequences replayed from HIP
+graphs; same samples, so the same spread) and, with --cv N, "control_variate": N more samples are
 split into a fit set and an evaluation set, a network on |<phi_k|zeta>|^2
 over the 64 near-gap states is trained on the fit set and its mean taken over
 --cv-cheap cheap samples.
@@ -124,14 +125,15 @@ def cpu_baseline(system, phi, p, n_terms, ncoef):
     return total, dict(filter=t_filter, tdh=t_tdh, zeta=t_zeta), workers, sample
 
 
-def bf16_form(args, s, phi, p, sigma1, sig_plain, homo, gam):
-    """The same samples with BF16 projector GEMMs and HIP-graph replay on a
-    stream of its own: time per sample and the QP shift against plain."""
+def bf16_form(args, s, phi, p, sigma1, sig_plain, homo, gam, precision):
+    """The same samples with BF16 projector GEMMs (plain or split) and
+    HIP-graph replay on a stream of its own: time per sample and the largest
+    Sigma_c(t) difference from the plain form."""
     import numpy as np
     import torch
     from paper_2601_21005_amd import sgw
     st = torch.cuda.Stream()
-    ctx = sgw.Context(s.grid.n, s.grid.h, s.v_loc, s.projectors, precision=sgw.SGW_C64_BF16KB,
+    ctx = sgw.Context(s.grid.n, s.grid.h, s.v_loc, s.projectors, precision=precision,
                       ecut=s.ecut, max_nvec=256, stream=st.cuda_stream)
     ctx.use_graphs(True)
     B = args.batch
@@ -290,7 +292,10 @@ def main():
 
     forms = {"plain": {"gpu_s_per_qp": gpu_s_per_qp, "gpu_s_per_sample": t_sample}}
     if not args.no_bf16:
-        forms["bf16kb_graphs"] = bf16_form(args, s, phi, p, sigma1, sig, homo, gam)
+        forms["bf16kb_graphs"] = bf16_form(args, s, phi, p, sigma1, sig, homo, gam,
+                                           sgw.SGW_C64_BF16KB)
+        forms["bf16x2kb_graphs"] = bf16_form(args, s, phi, p, sigma1, sig, homo, gam,
+                                             sgw.SGW_C64_BF16X2KB)
     if args.cv:
         forms["control_variate"] = cv_form(args, ctx, s, phis, ev, phi, p, homo, eg, gam,
                                           t_sample, sigma1, Z)
