@@ -205,6 +205,29 @@ def si357h204(seed=1003, n=128, h=0.6, ecut=28.0):
     return cluster_model(species, pos, n=n, h=h, ecut=ecut, name="Si357H204")
 
 
+SHELLS = (5, 17, 29, 35, 47, 71, 87, 99, 123, 147)     # atom-centred shell closures
+BATCH_SIZES = (40, 48, 56, 64, 80, 96, 112)            # FFT lengths for the uneven batch
+
+
+def uneven_batch(count=32, seed=1004, h=0.6, margin=8.0, ecut=28.0):
+    """Uneven batch of H-capped Si clusters: for each of ``count`` clusters a
+    seeded shell size from SHELLS (5 to 147 Si), its own jitter seed, the
+    smallest grid in BATCH_SIZES whose box holds the cluster with ``margin``
+    bohr on every side (at most 112^3), and a seeded number of stochastic
+    orbitals from (16, 32, 64, 128).  Returns a list of (System, n_eta)."""
+    rs = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        n_si = int(SHELLS[rs.integers(len(SHELLS))])
+        species, pos = si_cluster(n_si, seed=seed + 1 + i)
+        radius = float(np.max(np.linalg.norm(pos, axis=1)))
+        n = next((m for m in BATCH_SIZES if m * h >= 2 * (radius + margin)), BATCH_SIZES[-1])
+        neta = int((16, 32, 64, 128)[rs.integers(4)])
+        out.append((cluster_model(species, pos, n=n, h=h, ecut=ecut,
+                                  name=f"Si{n_si}H{species.count('H')}"), neta))
+    return out
+
+
 def tiny_system(n=8, h=0.7, with_kb=True, n_occ=2):
     """Small periodic test system (8^3 or 12^3 points): two Gaussian wells
     and, optionally, one s and one p_x KB projector."""
