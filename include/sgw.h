@@ -304,7 +304,10 @@ sgw_status sgw_kernel_timer_read(sgw_ctx *ctx, double *total_ms, int64_t *launch
  * vectors) and dealt, longest first, to `nworkers` host threads (each item
  * to the least-loaded thread).  Each thread issues its items in turn, so
  * items on contexts with different streams run concurrently on the GPU.
- * Every item needs its own context (SGW_EINVAL otherwise).  Per item:
+ * Every item needs its own context (SGW_EINVAL otherwise).  Contexts with
+ * graphs on replay the graphs they already hold and capture no new ones
+ * inside the batch (a sequence without a graph runs eagerly, with the same
+ * result): run each such context once before the batch.  Per item:
  * status and wall time (ms) are written back; the call returns SGW_OK or
  * the status of the first failed item (in item order).  phase timings are
  * not recorded. */

@@ -64,9 +64,9 @@ def main():
     torch.cuda.synchronize()
     t_seq = time.perf_counter() - t1
     print(f"sequential: {t_seq:.2f} s", flush=True)
-    for ctx, _, _ in jobs:
+    for ctx, phi, kw in jobs:                                   # capture the graphs
         ctx.use_graphs(True)
-    sgw.batch_sigma_estimate(jobs, nworkers=args.workers)      # captures the graphs
+        ctx.sigma_estimate(phi, **kw)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     bat = sgw.batch_sigma_estimate(jobs, nworkers=args.workers)

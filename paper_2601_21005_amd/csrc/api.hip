@@ -17,6 +17,10 @@ using namespace sgw;
 namespace {
 
 thread_local std::string g_create_error;
+// set on the worker threads of sgw_batch_sigma_estimate: they replay graphs
+// that a context already holds but capture none (a capture on one thread
+// does not mix with allocations and copies that other workers issue)
+thread_local bool g_no_capture = false;
 
 template <typename F> sgw_status guarded(sgw_ctx *ctx, F &&f) {
   try {
@@ -41,11 +45,14 @@ template <typename F> sgw_status guarded(sgw_ctx *ctx, F &&f) {
 void upload_real(sgw_ctx *ctx, DevBuf &b, const double *src, size_t n) {
   b.ensure(n * ctx->rsize());
   if (ctx->dbl) {
-    SGW_HIP(hipMemcpy(b.p, src, n * 8, hipMemcpyHostToDevice));
+    SGW_HIP(hipMemcpyAsync(b.p, src, n * 8, hipMemcpyHostToDevice, ctx->stream));
   } else {
     std::vector<float> f(src, src + n);
-    SGW_HIP(hipMemcpy(b.p, f.data(), n * 4, hipMemcpyHostToDevice));
+    SGW_HIP(hipMemcpyAsync(b.p, f.data(), n * 4, hipMemcpyHostToDevice, ctx->stream));
+    SGW_HIP(hipStreamSynchronize(ctx->stream));   // f goes out of scope
+    return;
   }
+  SGW_HIP(hipStreamSynchronize(ctx->stream));
 }
 
 void upload_cplx(sgw_ctx *ctx, DevBuf &b, const double *re_im, size_t n) {
@@ -81,6 +88,7 @@ void check_ptr(const void *p, const char *what) {
 template <typename F> hipGraphExec_t captured(sgw_ctx *ctx, const std::string &key, F &&body) {
   auto it = ctx->gexec.find(key);
   if (it != ctx->gexec.end()) return it->second;
+  if (g_no_capture) return nullptr;                // caller runs eagerly
   SGW_HIP(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
   try {
     body();
@@ -200,7 +208,7 @@ void *cheb_series(sgw_ctx *ctx, void *v0, void *w1, void *acc, void *tmp, int64_
     if (it == ctx->gexec.end()) {
       eager(0, nc - 1);                   // this call runs eagerly, later ones replay
       last();
-      captured(ctx, key, [&] { eager(0, nc - 1); last(); });
+      if (!g_no_capture) captured(ctx, key, [&] { eager(0, nc - 1); last(); });
     } else {
       SGW_HIP(hipGraphLaunch(it->second, ctx->stream));
     }
@@ -221,8 +229,12 @@ void *cheb_series(sgw_ctx *ctx, void *v0, void *w1, void *acc, void *tmp, int64_
         launch_counter(ctx, 0, 1, true);
       }
     });
-    launch_counter(ctx, 0, 2, false);
-    for (int p = 0; p < npair; ++p) SGW_HIP(hipGraphLaunch(ex, ctx->stream));
+    if (ex) {
+      launch_counter(ctx, 0, 2, false);
+      for (int p = 0; p < npair; ++p) SGW_HIP(hipGraphLaunch(ex, ctx->stream));
+    } else {
+      eager(2, 2 + 2 * npair);
+    }
   }
   eager(2 + 2 * npair, nc - 1);
   return last();
@@ -925,9 +937,11 @@ sgw_status sgw_sigma_estimate(sgw_ctx *ctx, const sgw_sigma_params *P, const dou
                            ctx->d_counter.as<int>() + 1, P->n_xi);
             launch_counter(ctx, 1, 1, true);
           });
-          launch_counter(ctx, 1, 2, false);
-          for (; j < nt1; ++j) SGW_HIP(hipGraphLaunch(ex, ctx->stream));
-          break;
+          if (ex) {
+            launch_counter(ctx, 1, 2, false);
+            for (; j < nt1; ++j) SGW_HIP(hipGraphLaunch(ex, ctx->stream));
+            break;
+          }
         }
         tdh_substeps(ctx, &st, P->m_sub, tau, j == 1, false);
         if (xi)
@@ -1036,6 +1050,9 @@ sgw_status sgw_batch_sigma_estimate(sgw_batch_item *items, int32_t n, int32_t nw
     load[w] += cost[i];
   }
   auto run = [&](int w) {
+    const bool prev = g_no_capture;
+    g_no_capture = true;
+    struct Restore { bool v; ~Restore() { g_no_capture = v; } } restore{prev};
     for (int i : plan[w]) {
       sgw_batch_item &it = items[i];
       const auto t0 = std::chrono::steady_clock::now();
