@@ -257,6 +257,23 @@ sgw_status sgw_sigma_estimate(sgw_ctx *ctx, const sgw_sigma_params *params,
                               const double *phi, double *sigma_t, double *x,
                               double *phase_ms);
 
+/* Several quasiparticle states in one pass (Sec. 3 computes the HOMO and the
+ * LUMO of each system, Table 3).  The white noise, the filtered zeta and
+ * eta sets (Eq. 3), the xi sets and the zeta propagation (Eq. 4) do not
+ * depend on phi and are computed once; each state k gets its own kick
+ * v_H[phi_k zeta-bar], TDH response (one tangent copy of every eta per
+ * state, beside one shared unperturbed copy), time ordering and contraction
+ * (Eq. 5), and its exchange from the shared eta.  State k's results are those
+ * of sgw_sigma_estimate with phi_k and the same params: bitwise for k = 0 and
+ * up to rounding for k > 0 (its response field shares a complex Poisson FFT
+ * with another state's).  phi: host [nstate][N_g]; sigma_t: host
+ * [nstate][n_zeta][2 n_tau + 1][2]; x: host [nstate][n_zeta]; 1 <= nstate
+ * <= SGW_MAX_STATES (SGW_EINVAL otherwise). */
+#define SGW_MAX_STATES 8
+sgw_status sgw_sigma_estimate_states(sgw_ctx *ctx, const sgw_sigma_params *params,
+                                     int32_t nstate, const double *phi, double *sigma_t,
+                                     double *x, double *phase_ms);
+
 /* QP energy from the sample-mean Sigma_c(t_j) (host [2 n_tau + 1][2]):
  *   Sigma(w) = dt sum_j w_j e^{-gamma^2 t_j^2/2} e^{i w t_j} Sigma(t_j)
  * (Eq. 7, trapezoid weights), Z = 1/(1 - d Re Sigma/dw (eps_ks)),

@@ -304,34 +304,51 @@ void poisson(sgw_ctx *ctx, const void *rho, int64_t S, PlaneMode mode, void *r0,
   fft3d_apply(ctx, rho, tmp, nullptr, S, ctx->N, MUL_COUL, 0.0, mode, e);
 }
 
-// One or more Strang substeps; the local half steps of consecutive substeps
-// are merged (a = tau).  `open`: the state is synchronised at entry (first
-// half step a = tau/2); `close`: apply the closing half step.
-void tdh_substeps(sgw_ctx *ctx, sgw_tdh_state *st, int nsub, double tau, bool open,
+// Potentials of the TDH densities: rho[0] = n + i dn_0 gives r0 (v, or vh0
+// at the start) and u_0; rho[b] = dn_{2b-1} + i dn_{2b} gives u_{2b-1}, u_{2b}.
+void tdh_potentials(sgw_ctx *ctx, const void *rho, int64_t S, int nk, PlaneMode m0, void *r0,
+                    void *u, const void *vh0) {
+  const size_t cs = ctx->csize(), rs = ctx->rsize();
+  const int64_t N = ctx->N;
+  poisson(ctx, rho, S, m0, r0, u, vh0);
+  for (int b = 1; 2 * b - 1 < nk; ++b) {
+    char *ub = static_cast<char *>(u);
+    poisson(ctx, static_cast<const char *>(rho) + cs * N * S * b, S, PLANE_INV_SPLIT,
+            ub + rs * N * S * (2 * b - 1), 2 * b < nk ? ub + rs * N * S * (2 * b) : nullptr,
+            nullptr);
+  }
+}
+
+// One or more Strang substeps for nk response states;  the local half steps
+// of consecutive substeps are merged (a = tau).  `open`: the state is
+// synchronised at entry (first half step a = tau/2); `close`: apply the
+// closing half step.
+void tdh_substeps(sgw_ctx *ctx, sgw_tdh_state *st, int nk, int nsub, double tau, bool open,
                   bool close) {
-  const int64_t S = st->nsample, nv = 2 * (int64_t)st->nsample * st->neta;
+  const int64_t S = st->nsample, nv = (1 + nk) * (int64_t)st->nsample * st->neta;
   void *tmp = ctx->buf("tdh_tmp", ctx->csize() * ctx->N * nv).p;
-  void *rho = ctx->buf("tdh_rho", ctx->csize() * ctx->N * S).p;
+  void *rho = ctx->buf("tdh_rho", ctx->csize() * ctx->N * S * (1 + nk / 2)).p;
   for (int k = 0; k < nsub; ++k) {
-    launch_tdh_local(ctx, st->psi, st->v, st->u, st->nsample, st->neta,
+    launch_tdh_local(ctx, st->psi, st->v, st->u, st->nsample, st->neta, nk,
                      (k == 0 && open) ? 0.5 * tau : tau);
     if (ctx->has_kb) kb_exp_apply(ctx, st->psi, nv, 0.5 * tau);
     fft3d_apply(ctx, st->psi, tmp, st->psi, nv, ctx->N, MUL_PROP, tau, PLANE_INV_STORE,
                 EpiArgs());
     if (ctx->has_kb) kb_exp_apply(ctx, st->psi, nv, 0.5 * tau);
-    launch_tdh_density(ctx, st->psi, rho, st->nsample, st->neta, st->weight);
-    poisson(ctx, rho, S, PLANE_INV_POISSON, st->v, st->u, st->vh0);
+    launch_tdh_density(ctx, st->psi, rho, st->nsample, st->neta, nk, st->weight);
+    tdh_potentials(ctx, rho, S, nk, PLANE_INV_POISSON, st->v, st->u, st->vh0);
   }
-  if (close) launch_tdh_local(ctx, st->psi, st->v, st->u, st->nsample, st->neta, 0.5 * tau);
+  if (close)
+    launch_tdh_local(ctx, st->psi, st->v, st->u, st->nsample, st->neta, nk, 0.5 * tau);
 }
 
-void tdh_start(sgw_ctx *ctx, sgw_tdh_state *st, const void *dv) {
+void tdh_start(sgw_ctx *ctx, sgw_tdh_state *st, int nk, const void *dv) {
   const int64_t S = st->nsample;
-  void *rho = ctx->buf("tdh_rho", ctx->csize() * ctx->N * S).p;
-  launch_tdh_tangent(ctx, st->psi, dv, st->nsample, st->neta);
+  void *rho = ctx->buf("tdh_rho", ctx->csize() * ctx->N * S * (1 + nk / 2)).p;
+  launch_tdh_tangent(ctx, st->psi, dv, st->nsample, st->neta, nk);
   launch_bcast_real(ctx, ctx->d_vloc.p, st->v, st->nsample);
-  launch_tdh_density(ctx, st->psi, rho, st->nsample, st->neta, st->weight);
-  poisson(ctx, rho, S, PLANE_INV_SPLIT, st->vh0, st->u, nullptr);
+  launch_tdh_density(ctx, st->psi, rho, st->nsample, st->neta, nk, st->weight);
+  tdh_potentials(ctx, rho, S, nk, PLANE_INV_SPLIT, st->vh0, st->u, nullptr);
 }
 
 void check_state(sgw_ctx *ctx, const sgw_tdh_state *st) {
@@ -689,7 +706,7 @@ sgw_status sgw_tdh_init(sgw_ctx *ctx, sgw_tdh_state *st, const void *dv) {
   return guarded(ctx, [&] {
     check_state(ctx, st);
     check_ptr(dv, "dv");
-    tdh_start(ctx, st, dv);
+    tdh_start(ctx, st, 1, dv);
   });
 }
 
@@ -699,7 +716,7 @@ sgw_status sgw_tdh_step(sgw_ctx *ctx, sgw_tdh_state *st, int32_t nsub, double dt
     check_state(ctx, st);
     SGW_REQUIRE(nsub >= 0 && std::isfinite(dt_sub), SGW_EINVAL, "bad nsub or dt_sub");
     if (nsub == 0) return;
-    tdh_substeps(ctx, st, nsub, dt_sub, true, true);
+    tdh_substeps(ctx, st, 1, nsub, dt_sub, true, true);
   });
 }
 
@@ -774,9 +791,18 @@ sgw_status sgw_kernel_timer_read(sgw_ctx *ctx, double *total_ms, int64_t *launch
 // ------------------------------------------------------------------ Sigma
 sgw_status sgw_sigma_estimate(sgw_ctx *ctx, const sgw_sigma_params *P, const double *phi,
                               double *sigma_t, double *x_out, double *phase_ms) {
+  return sgw_sigma_estimate_states(ctx, P, 1, phi, sigma_t, x_out, phase_ms);
+}
+
+sgw_status sgw_sigma_estimate_states(sgw_ctx *ctx, const sgw_sigma_params *P, int32_t nstate,
+                                     const double *phi, double *sigma_t, double *x_out,
+                                     double *phase_ms) {
   if (!ctx) return SGW_EINVAL;
   return guarded(ctx, [&] {
     SGW_REQUIRE(P && phi && sigma_t && x_out, SGW_EINVAL, "NULL argument");
+    SGW_REQUIRE(nstate >= 1 && nstate <= SGW_MAX_STATES, SGW_EINVAL,
+                "nstate must be in 1..SGW_MAX_STATES");
+    const int K = nstate;
     const int64_t N = ctx->N;
     SGW_REQUIRE(P->n_zeta > 0 && P->first_sample >= 0, SGW_EINVAL, "n_zeta must be > 0");
     SGW_REQUIRE(P->n_eta > 0 && P->n_eta % 2 == 0, SGW_EINVAL, "n_eta must be even and > 0");
@@ -799,7 +825,8 @@ sgw_status sgw_sigma_estimate(sgw_ctx *ctx, const sgw_sigma_params *P, const dou
       SGW_REQUIRE(N % 32 == 0, SGW_EINVAL, "xi mode needs N_g divisible by 32");
       SGW_REQUIRE(P->n_xi >= 1 && P->f_g > 0 && P->f_g <= 1, SGW_EINVAL, "bad n_xi or f_g");
     }
-    for (int64_t r = 0; r < N; ++r) SGW_REQUIRE(std::isfinite(phi[r]), SGW_EINVAL, "phi not finite");
+    for (int64_t r = 0; r < K * N; ++r)
+      SGW_REQUIRE(std::isfinite(phi[r]), SGW_EINVAL, "phi not finite");
     const int nt1 = P->n_tau + 1;
     const int nft = P->n_ft > 0 ? P->n_ft : next_pow2(4 * nt1);
     SGW_REQUIRE(nft >= 2 * nt1, SGW_EINVAL, "n_ft < 2 (n_tau + 1)");
@@ -824,8 +851,9 @@ sgw_status sgw_sigma_estimate(sgw_ctx *ctx, const sgw_sigma_params *P, const dou
     }
     DevBuf &d_tw = ctx->buf("to_tw", cs * nft);
     upload_cplx(ctx, d_tw, tw.data(), nft);
-    DevBuf &d_phi = ctx->buf("phi", rs * N);
-    upload_real(ctx, d_phi, phi, N);
+    DevBuf &d_phi = ctx->buf("phi", rs * N * K);
+    upload_real(ctx, d_phi, phi, (size_t)K * N);
+    auto phi_of = [&](int k) { return static_cast<const char *>(d_phi.p) + rs * N * k; };
     const int nseg = xi ? std::max(1, (int)std::floor(P->f_g * N / 32.0 + 0.5)) : 0;
     SGW_REQUIRE(!xi || nseg <= N / 32, SGW_EINVAL, "f_g too large");
     const double amp = xi ? 1.0 / std::sqrt(P->n_xi * (32.0 * nseg / N) * ctx->dV) : 0.0;
@@ -885,39 +913,51 @@ sgw_status sgw_sigma_estimate(sgw_ctx *ctx, const sgw_sigma_params *P, const dou
           SGW_REQUIRE(std::isfinite(v) && v <= bound, SGW_EDIVERGED,
                       "filter recurrence grew: [emin, emax] does not enclose spec(H)");
       }
-      // 3. unpack, kick potential, exchange, TDH start
-      void *psi = ctx->buf("tdh_psi", cs * N * 2 * neta * S).p;
+      // 3. unpack, kick potentials, exchange (per state), TDH start.  psi
+      // holds per sample the eta set and one tangent copy per state.
+      void *psi = ctx->buf("tdh_psi", cs * N * (1 + K) * neta * S).p;
       void *zeta = ctx->buf("zeta", cs * N * 2 * S).p;
-      void *kick = ctx->buf("kick", cs * N * S).p;
-      UnpackArgs ua;
-      ua.filt = FA; ua.keys = d_keys.as<uint64_t>(); ua.phi = d_phi.p; ua.psi = psi;
-      ua.zeta = zeta; ua.kick = kick; ua.xsrc = F0; ua.S = S; ua.neta = neta;
-      launch_unpack(ctx, ua);
-      void *dv = ctx->buf("dv", rs * N * S).p;
-      poisson(ctx, kick, S, PLANE_INV_SPLIT, dv, nullptr, nullptr);
+      char *kick = static_cast<char *>(ctx->buf("kick", cs * N * S * K).p);
       const int64_t nxf = (int64_t)S * neta / 2;
-      fft3d_apply(ctx, F0, FT, F1, nxf, N, MUL_COUL, 0.0, PLANE_INV_STORE, EpiArgs());
-      DevBuf &d_xd = ctx->buf("xdots", sizeof(double) * nxf);
-      launch_redot(ctx, F0, F1, N, nxf, d_xd.as<double>());
-      std::vector<double> xd(nxf);
-      SGW_HIP(hipMemcpyAsync(xd.data(), d_xd.p, sizeof(double) * nxf, hipMemcpyDeviceToHost, ctx->stream));
+      DevBuf &d_xd = ctx->buf("xdots", sizeof(double) * nxf * K);
+      for (int k = 0; k < K; ++k) {
+        UnpackArgs ua;
+        ua.filt = FA; ua.keys = d_keys.as<uint64_t>(); ua.phi = phi_of(k);
+        ua.psi = k == 0 ? psi : nullptr; ua.zeta = k == 0 ? zeta : nullptr;
+        ua.kick = kick + cs * N * S * k; ua.xsrc = F0; ua.S = S; ua.neta = neta;
+        ua.ncopy = 1 + K;
+        launch_unpack(ctx, ua);
+        fft3d_apply(ctx, F0, FT, F1, nxf, N, MUL_COUL, 0.0, PLANE_INV_STORE, EpiArgs());
+        launch_redot(ctx, F0, F1, N, nxf, d_xd.as<double>() + nxf * k);
+      }
+      void *dv = ctx->buf("dv", rs * N * S * K).p;
+      poisson(ctx, kick, (int64_t)S * K, PLANE_INV_SPLIT, dv, nullptr, nullptr);
+      std::vector<double> xd(nxf * K);
+      SGW_HIP(hipMemcpyAsync(xd.data(), d_xd.p, sizeof(double) * nxf * K, hipMemcpyDeviceToHost,
+                             ctx->stream));
       sgw_tdh_state st;
       st.nsample = S; st.neta = neta; st.weight = 2.0 / neta; st.psi = psi;
       st.v = ctx->buf("tdh_v", rs * N * S).p;
-      st.u = ctx->buf("tdh_u", rs * N * S).p;
+      st.u = ctx->buf("tdh_u", rs * N * S * K).p;
       st.vh0 = ctx->buf("tdh_vh0", rs * N * S).p;
-      tdh_start(ctx, &st, dv);
+      tdh_start(ctx, &st, K, dv);
+      // u and the stored rows of state k
+      const size_t cr_state = rs * (size_t)S * nt1 * n_inner;
+      auto u_of = [&](int k) { return static_cast<const char *>(st.u) + rs * N * S * k; };
       int *blocks = nullptr;
       void *cR = nullptr;
       if (xi) {
         blocks = ctx->buf("xi_blocks", sizeof(int) * (size_t)S * P->n_xi * nseg).as<int>();
         launch_xi_supports(ctx, d_ksup.as<uint64_t>(), S, P->n_xi, nseg, blocks);
-        cR = ctx->buf("xi_cR", rs * (size_t)S * nt1 * P->n_xi).p;
-        launch_xi_real(ctx, st.u, blocks, d_ksign.as<uint64_t>(), S, P->n_xi, nseg, amp * ctx->dV,
-                       cR, (int64_t)nt1 * P->n_xi, 0);
+        cR = ctx->buf("xi_cR", cr_state * K).p;
+        for (int k = 0; k < K; ++k)
+          launch_xi_real(ctx, u_of(k), blocks, d_ksign.as<uint64_t>(), S, P->n_xi, nseg,
+                         amp * ctx->dV, static_cast<char *>(cR) + cr_state * k,
+                         (int64_t)nt1 * P->n_xi, 0);
       } else {
-        cR = ctx->buf("U", rs * (size_t)S * nt1 * N).p;
-        SGW_HIP(hipMemcpy2DAsync(cR, rs * N * nt1, st.u, rs * N, rs * N, S, hipMemcpyDeviceToDevice, ctx->stream));
+        cR = ctx->buf("U", cr_state * K).p;
+        SGW_HIP(hipMemcpy2DAsync(cR, rs * N * nt1, st.u, rs * N, rs * N, (size_t)S * K,
+                                 hipMemcpyDeviceToDevice, ctx->stream));
       }
       SGW_HIP(hipEventRecord(ev[3], ctx->stream));
       // 4. TDH response, stored at the output steps
@@ -929,12 +969,13 @@ sgw_status sgw_sigma_estimate(sgw_ctx *ctx, const sgw_sigma_params *P, const dou
           const std::string key =
               "tdh|" + ptr_key({st.psi, st.v, st.u, st.vh0, cR, blocks, d_ksign.p}) +
               num_key({(double)S, (double)neta, (double)P->m_sub, tau, (double)P->n_xi,
-                       (double)nseg, amp * ctx->dV, (double)nt1});
+                       (double)nseg, amp * ctx->dV, (double)nt1, (double)K});
           hipGraphExec_t ex = captured(ctx, key, [&] {
-            tdh_substeps(ctx, &st, P->m_sub, tau, false, false);
-            launch_xi_real(ctx, st.u, blocks, d_ksign.as<uint64_t>(), S, P->n_xi, nseg,
-                           amp * ctx->dV, cR, (int64_t)nt1 * P->n_xi, 0,
-                           ctx->d_counter.as<int>() + 1, P->n_xi);
+            tdh_substeps(ctx, &st, K, P->m_sub, tau, false, false);
+            for (int k = 0; k < K; ++k)
+              launch_xi_real(ctx, u_of(k), blocks, d_ksign.as<uint64_t>(), S, P->n_xi, nseg,
+                             amp * ctx->dV, static_cast<char *>(cR) + cr_state * k,
+                             (int64_t)nt1 * P->n_xi, 0, ctx->d_counter.as<int>() + 1, P->n_xi);
             launch_counter(ctx, 1, 1, true);
           });
           if (ex) {
@@ -943,22 +984,26 @@ sgw_status sgw_sigma_estimate(sgw_ctx *ctx, const sgw_sigma_params *P, const dou
             break;
           }
         }
-        tdh_substeps(ctx, &st, P->m_sub, tau, j == 1, false);
+        tdh_substeps(ctx, &st, K, P->m_sub, tau, j == 1, false);
         if (xi)
-          launch_xi_real(ctx, st.u, blocks, d_ksign.as<uint64_t>(), S, P->n_xi, nseg,
-                         amp * ctx->dV, cR, (int64_t)nt1 * P->n_xi, (int64_t)j * P->n_xi);
+          for (int k = 0; k < K; ++k)
+            launch_xi_real(ctx, u_of(k), blocks, d_ksign.as<uint64_t>(), S, P->n_xi, nseg,
+                           amp * ctx->dV, static_cast<char *>(cR) + cr_state * k,
+                           (int64_t)nt1 * P->n_xi, (int64_t)j * P->n_xi);
         else
           SGW_HIP(hipMemcpy2DAsync(static_cast<char *>(cR) + rs * N * j, rs * N * nt1, st.u, rs * N,
-                                   rs * N, S, hipMemcpyDeviceToDevice, ctx->stream));
+                                   rs * N, (size_t)S * K, hipMemcpyDeviceToDevice, ctx->stream));
       }
       SGW_HIP(hipEventRecord(ev[4], ctx->stream));
       // 5. time ordering
-      void *cto = ctx->buf("cTO", cs * (size_t)S * nt1 * n_inner).p;
-      SGW_REQUIRE(launch_time_order(ctx, cR, cto, (int64_t)S * n_inner, n_inner, nt1, nft, d_tw.p),
+      const size_t cto_state = cs * (size_t)S * nt1 * n_inner;
+      char *cto = static_cast<char *>(ctx->buf("cTO", cto_state * K).p);
+      SGW_REQUIRE(launch_time_order(ctx, cR, cto, (int64_t)K * S * n_inner, n_inner, nt1, nft,
+                                    d_tw.p),
                   SGW_EUNSUPPORTED, "time-ordering length not built");
       SGW_HIP(hipEventRecord(ev[5], ctx->stream));
       // 6. zeta propagation and contraction, Eq. (4), Eq. (5)
-      double *d_sig = ctx->buf("sig", sizeof(double) * 4 * S * nt1).as<double>();
+      double *d_sig = ctx->buf("sig", sizeof(double) * 4 * S * nt1 * K).as<double>();
       void *zb = ctx->buf("z_b", cs * N * 2 * S).p, *zacc = ctx->buf("z_acc", cs * N * 2 * S).p;
       void *zt = ctx->buf("z_tmp", cs * N * 2 * S).p;
       void *dp = nullptr, *dtl = nullptr;
@@ -975,22 +1020,27 @@ sgw_status sgw_sigma_estimate(sgw_ctx *ctx, const sgw_sigma_params *P, const dou
           cheb_series(ctx, zc, zb, zacc, zt, 2 * S, pb, P->emin, P->emax);
           std::swap(zc, zacc);
         }
-        if (xi) {
-          launch_xi_zeta(ctx, zc, d_phi.p, blocks, d_ksign.as<uint64_t>(), S, P->n_xi, nseg,
-                         amp * ctx->dV, dp, dtl);
-          launch_contract_xi(ctx, cto, dp, dtl, S, P->n_xi, nt1, j, d_sig);
-        } else {
-          launch_contract_exact(ctx, cto, zc, d_phi.p, S, nt1, j, partial, d_sig);
+        for (int k = 0; k < K; ++k) {
+          double *sig_k = d_sig + (size_t)4 * S * nt1 * k;
+          if (xi) {
+            launch_xi_zeta(ctx, zc, phi_of(k), blocks, d_ksign.as<uint64_t>(), S, P->n_xi, nseg,
+                           amp * ctx->dV, dp, dtl);
+            launch_contract_xi(ctx, cto + cto_state * k, dp, dtl, S, P->n_xi, nt1, j, sig_k);
+          } else {
+            launch_contract_exact(ctx, cto + cto_state * k, zc, phi_of(k), S, nt1, j, partial,
+                                  sig_k);
+          }
         }
       }
       SGW_HIP(hipEventRecord(ev[6], ctx->stream));
-      std::vector<double> sig(4 * (size_t)S * nt1);
+      std::vector<double> sig(4 * (size_t)S * nt1 * K);
       SGW_HIP(hipMemcpyAsync(sig.data(), d_sig, sizeof(double) * sig.size(), hipMemcpyDeviceToHost, ctx->stream));
       SGW_HIP(hipStreamSynchronize(ctx->stream));
       // assemble
+      for (int k = 0; k < K; ++k)
       for (int s = 0; s < S; ++s) {
-        double *o = sigma_t + (size_t)(b0 + s) * 2 * (2 * P->n_tau + 1);
-        const double *g = sig.data() + (size_t)s * nt1 * 4;
+        double *o = sigma_t + ((size_t)k * P->n_zeta + b0 + s) * 2 * (2 * P->n_tau + 1);
+        const double *g = sig.data() + ((size_t)k * S + s) * nt1 * 4;
         for (int j = 1; j < nt1; ++j) {
           o[2 * (P->n_tau + j)] = g[4 * j];
           o[2 * (P->n_tau + j) + 1] = g[4 * j + 1];
@@ -1000,8 +1050,8 @@ sgw_status sgw_sigma_estimate(sgw_ctx *ctx, const sgw_sigma_params *P, const dou
         o[2 * P->n_tau] = 0.5 * (g[0] + g[2]);
         o[2 * P->n_tau + 1] = 0.5 * (g[1] + g[3]);
         double xs = 0;
-        for (int k = 0; k < neta / 2; ++k) xs += xd[(size_t)s * (neta / 2) + k];
-        x_out[b0 + s] = -ctx->dV * xs / neta;
+        for (int q = 0; q < neta / 2; ++q) xs += xd[(size_t)nxf * k + (size_t)s * (neta / 2) + q];
+        x_out[(size_t)k * P->n_zeta + b0 + s] = -ctx->dV * xs / neta;
       }
       float t;
       SGW_HIP(hipEventElapsedTime(&t, ev[1], ev[2])); ph[0] += t;

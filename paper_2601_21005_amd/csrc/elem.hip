@@ -245,17 +245,21 @@ __global__ void k_unpack(UnpackArgs a, int64_t N, R amp) {
   const R zocc = real_component<R>(filt, q0, N, r);
   const R zb = noise_bit(a.keys[q0], r) ? -amp : amp;
   const R ph = static_cast<const R *>(a.phi)[r];
-  C *zeta = static_cast<C *>(a.zeta) + s * 2 * N;
-  zeta[r] = cmake<C>(zb - zocc, 0);
-  zeta[N + r] = cmake<C>(zocc, 0);
+  if (a.zeta) {
+    C *zeta = static_cast<C *>(a.zeta) + s * 2 * N;
+    zeta[r] = cmake<C>(zb - zocc, 0);
+    zeta[N + r] = cmake<C>(zocc, 0);
+  }
   static_cast<C *>(a.kick)[s * N + r] = cmake<C>(ph * zb, 0);
-  C *psi = static_cast<C *>(a.psi) + s * 2 * a.neta * N;
+  C *psi = a.psi ? static_cast<C *>(a.psi) + s * a.ncopy * a.neta * N : nullptr;
   C *xs = static_cast<C *>(a.xsrc) + s * (a.neta / 2) * N;
   for (int l = 0; l < a.neta; l += 2) {
     const R e0 = real_component<R>(filt, q0 + 1 + l, N, r);
     const R e1 = real_component<R>(filt, q0 + 2 + l, N, r);
-    psi[(int64_t)l * N + r] = cmake<C>(e0, 0);
-    psi[(int64_t)(l + 1) * N + r] = cmake<C>(e1, 0);
+    if (psi) {
+      psi[(int64_t)l * N + r] = cmake<C>(e0, 0);
+      psi[(int64_t)(l + 1) * N + r] = cmake<C>(e1, 0);
+    }
     xs[(int64_t)(l / 2) * N + r] = cmake<C>(ph * e0, ph * e1);
   }
 }
@@ -272,62 +276,92 @@ void launch_unpack(sgw_ctx *ctx, const UnpackArgs &a) {
 }
 
 // ============================================================ TDH
-// psi[s][1][l] = -i dv_s psi[s][0][l]
+// A sample's block holds 1 + K copies of its N_eta orbitals, psi[s][c][l]:
+// c = 0 the unperturbed eta, c = 1 + k the tangent delta-eta of state k,
+// whose response field is u[k][s].  K = 1 is the single-state layout.
+
+// psi[s][1 + k][l] = -i dv[k][s] psi[s][0][l]
 template <typename R>
-__global__ void k_tdh_tangent(cplx<R> *psi, const R *dv, int neta, int64_t N) {
+__global__ void k_tdh_tangent(cplx<R> *psi, const R *dv, int neta, int nk, int64_t N) {
   const int64_t r = (int64_t)blockIdx.x * NT + threadIdx.x;
-  const int64_t s = blockIdx.y;
+  const int64_t s = blockIdx.y, S = gridDim.y;
   if (r >= N) return;
-  const R d = dv[s * N + r];
-  cplx<R> *p0 = psi + s * 2 * neta * N;
-  cplx<R> *p1 = p0 + (int64_t)neta * N;
-  for (int l = 0; l < neta; ++l) {
-    const cplx<R> e = p0[(int64_t)l * N + r];
-    p1[(int64_t)l * N + r] = cmake<cplx<R>>(d * e.y, -d * e.x);
+  cplx<R> *p0 = psi + s * (1 + nk) * neta * N;
+  for (int k = 0; k < nk; ++k) {
+    const R d = dv[(k * S + s) * N + r];
+    cplx<R> *p1 = p0 + (int64_t)(1 + k) * neta * N;
+    for (int l = 0; l < neta; ++l) {
+      const cplx<R> e = p0[(int64_t)l * N + r];
+      p1[(int64_t)l * N + r] = cmake<cplx<R>>(d * e.y, -d * e.x);
+    }
   }
 }
 
 // Local step of length a:  eta <- e^{-i V a} eta,
-// delta-eta <- e^{-i V a} (delta-eta - i a u eta)
+// delta-eta_k <- e^{-i V a} (delta-eta_k - i a u_k eta)
 template <typename R>
-__global__ void k_tdh_local(cplx<R> *psi, const R *v, const R *u, int neta, int64_t N, R a) {
+__global__ void k_tdh_local(cplx<R> *psi, const R *v, const R *u, int neta, int nk, int64_t N,
+                            R a) {
   const int64_t r = (int64_t)blockIdx.x * NT + threadIdx.x;
-  const int64_t s = blockIdx.y;
+  const int64_t s = blockIdx.y, S = gridDim.y;
   if (r >= N) return;
   R sn, cs;
   const R ph = v[s * N + r] * a;
   if constexpr (sizeof(R) == 4) sincosf(ph, &sn, &cs);
   else sincos(ph, &sn, &cs);
-  const R au = a * u[s * N + r];
-  cplx<R> *p0 = psi + s * 2 * neta * N;
-  cplx<R> *p1 = p0 + (int64_t)neta * N;
+  R au[SGW_MAX_STATES];
+#pragma unroll
+  for (int k = 0; k < SGW_MAX_STATES; ++k) au[k] = k < nk ? a * u[(k * S + s) * N + r] : (R)0;
+  cplx<R> *p0 = psi + s * (1 + nk) * neta * N;
   for (int l = 0; l < neta; ++l) {
     const cplx<R> e = p0[(int64_t)l * N + r];
-    cplx<R> d = p1[(int64_t)l * N + r];
-    d.x += au * e.y;      // - i a u eta
-    d.y -= au * e.x;
-    // multiply by (cs - i sn)
+#pragma unroll
+    for (int k = 0; k < SGW_MAX_STATES; ++k) {
+      if (k < nk) {
+        cplx<R> *p1 = p0 + (int64_t)(1 + k) * neta * N;
+        cplx<R> d = p1[(int64_t)l * N + r];
+        d.x += au[k] * e.y;      // - i a u eta
+        d.y -= au[k] * e.x;
+        // multiply by (cs - i sn)
+        p1[(int64_t)l * N + r] = cmake<cplx<R>>(cs * d.x + sn * d.y, cs * d.y - sn * d.x);
+      }
+    }
     p0[(int64_t)l * N + r] = cmake<cplx<R>>(cs * e.x + sn * e.y, cs * e.y - sn * e.x);
-    p1[(int64_t)l * N + r] = cmake<cplx<R>>(cs * d.x + sn * d.y, cs * d.y - sn * d.x);
   }
 }
 
-// rho[s] = w sum_l |eta_l|^2 + i w sum_l 2 Re(conj(eta_l) delta-eta_l)
+// n = w sum_l |eta_l|^2,  dn_k = 2 w sum_l Re(conj(eta_l) delta-eta_k,l), packed
+// as complex fields for the Poisson solve: rho[0][s] = n + i dn_0 and, for
+// b >= 1, rho[b][s] = dn_{2b-1} + i dn_{2b} (0 past the last state).
 template <typename R>
-__global__ void k_tdh_density(const cplx<R> *psi, cplx<R> *rho, int neta, int64_t N, R w) {
+__global__ void k_tdh_density(const cplx<R> *psi, cplx<R> *rho, int neta, int nk, int64_t N,
+                              R w) {
   const int64_t r = (int64_t)blockIdx.x * NT + threadIdx.x;
-  const int64_t s = blockIdx.y;
+  const int64_t s = blockIdx.y, S = gridDim.y;
   if (r >= N) return;
-  const cplx<R> *p0 = psi + s * 2 * neta * N;
-  const cplx<R> *p1 = p0 + (int64_t)neta * N;
-  R n = 0, dn = 0;
+  const cplx<R> *p0 = psi + s * (1 + nk) * neta * N;
+  R n = 0, dn[SGW_MAX_STATES];
+#pragma unroll
+  for (int k = 0; k < SGW_MAX_STATES; ++k) dn[k] = 0;
   for (int l = 0; l < neta; ++l) {
     const cplx<R> e = p0[(int64_t)l * N + r];
-    const cplx<R> d = p1[(int64_t)l * N + r];
     n += e.x * e.x + e.y * e.y;
-    dn += e.x * d.x + e.y * d.y;
+#pragma unroll
+    for (int k = 0; k < SGW_MAX_STATES; ++k) {
+      if (k < nk) {
+        const cplx<R> d = p0[(int64_t)((1 + k) * neta + l) * N + r];
+        dn[k] += e.x * d.x + e.y * d.y;
+      }
+    }
   }
-  rho[s * N + r] = cmake<cplx<R>>(w * n, (R)2 * w * dn);
+  rho[s * N + r] = cmake<cplx<R>>(w * n, (R)2 * w * dn[0]);
+#pragma unroll
+  for (int b = 1; b <= SGW_MAX_STATES / 2; ++b) {
+    if (2 * b - 1 < nk) {
+      const R hi = 2 * b < nk ? (R)2 * w * dn[2 * b < SGW_MAX_STATES ? 2 * b : 0] : (R)0;
+      rho[(b * S + s) * N + r] = cmake<cplx<R>>((R)2 * w * dn[2 * b - 1], hi);
+    }
+  }
 }
 
 template <typename R>
@@ -336,37 +370,40 @@ __global__ void k_bcast_real(const R *src, R *dst, int64_t N) {
   if (r < N) dst[(int64_t)blockIdx.y * N + r] = src[r];
 }
 
-void launch_tdh_tangent(sgw_ctx *ctx, void *psi, const void *dv, int S, int neta) {
+void launch_tdh_tangent(sgw_ctx *ctx, void *psi, const void *dv, int S, int neta, int nk) {
   if (ctx->dbl)
     hipLaunchKernelGGL(k_tdh_tangent<double>, grid1(ctx->N, S), dim3(NT), 0, ctx->stream,
-                       static_cast<double2 *>(psi), static_cast<const double *>(dv), neta, ctx->N);
+                       static_cast<double2 *>(psi), static_cast<const double *>(dv), neta, nk,
+                       ctx->N);
   else
     hipLaunchKernelGGL(k_tdh_tangent<float>, grid1(ctx->N, S), dim3(NT), 0, ctx->stream,
-                       static_cast<float2 *>(psi), static_cast<const float *>(dv), neta, ctx->N);
+                       static_cast<float2 *>(psi), static_cast<const float *>(dv), neta, nk,
+                       ctx->N);
   SGW_HIP(hipGetLastError());
 }
 
 void launch_tdh_local(sgw_ctx *ctx, void *psi, const void *v, const void *u, int S, int neta,
-                      double a) {
+                      int nk, double a) {
   if (ctx->dbl)
     hipLaunchKernelGGL(k_tdh_local<double>, grid1(ctx->N, S), dim3(NT), 0, ctx->stream,
                        static_cast<double2 *>(psi), static_cast<const double *>(v),
-                       static_cast<const double *>(u), neta, ctx->N, a);
+                       static_cast<const double *>(u), neta, nk, ctx->N, a);
   else
     hipLaunchKernelGGL(k_tdh_local<float>, grid1(ctx->N, S), dim3(NT), 0, ctx->stream,
                        static_cast<float2 *>(psi), static_cast<const float *>(v),
-                       static_cast<const float *>(u), neta, ctx->N, (float)a);
+                       static_cast<const float *>(u), neta, nk, ctx->N, (float)a);
   SGW_HIP(hipGetLastError());
 }
 
-void launch_tdh_density(sgw_ctx *ctx, const void *psi, void *rho, int S, int neta, double w) {
+void launch_tdh_density(sgw_ctx *ctx, const void *psi, void *rho, int S, int neta, int nk,
+                        double w) {
   if (ctx->dbl)
     hipLaunchKernelGGL(k_tdh_density<double>, grid1(ctx->N, S), dim3(NT), 0, ctx->stream,
-                       static_cast<const double2 *>(psi), static_cast<double2 *>(rho), neta,
+                       static_cast<const double2 *>(psi), static_cast<double2 *>(rho), neta, nk,
                        ctx->N, w);
   else
     hipLaunchKernelGGL(k_tdh_density<float>, grid1(ctx->N, S), dim3(NT), 0, ctx->stream,
-                       static_cast<const float2 *>(psi), static_cast<float2 *>(rho), neta,
+                       static_cast<const float2 *>(psi), static_cast<float2 *>(rho), neta, nk,
                        ctx->N, (float)w);
   SGW_HIP(hipGetLastError());
 }

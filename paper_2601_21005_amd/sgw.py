@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(HERE, "libsgw.so")
 SGW_OK, SGW_EINVAL, SGW_ENOMEM, SGW_EHIP, SGW_EDIVERGED, SGW_ENOROOT, SGW_EUNSUPPORTED = \
     0, -1, -2, -3, -4, -5, -6
 SGW_C128, SGW_C64, SGW_C64_BF16KB, SGW_C64_BF16X2KB = 0, 1, 2, 3
+SGW_MAX_STATES = 8
 
 STATUS_NAMES = {0: "SGW_OK", -1: "SGW_EINVAL", -2: "SGW_ENOMEM", -3: "SGW_EHIP",
                 -4: "SGW_EDIVERGED", -5: "SGW_ENOROOT", -6: "SGW_EUNSUPPORTED"}
@@ -25,6 +26,7 @@ EXPORTS = ["sgw_create", "sgw_destroy", "sgw_last_error", "sgw_bounds", "sgw_lan
            "sgw_apply_H",
            "sgw_fermi_coefficients", "sgw_gapped_coefficients", "sgw_fermi_filter", "sgw_propagator_coefficients",
            "sgw_cheb_propagate", "sgw_tdh_init", "sgw_tdh_step", "sgw_sigma_estimate",
+           "sgw_sigma_estimate_states",
            "sgw_qp_solve", "sgw_sigma_omega", "sgw_kernel_timer", "sgw_kernel_timer_read",
            "sgw_use_graphs", "sgw_batch_sigma_estimate", "sgw_cv_features", "sgw_mlp_create", "sgw_mlp_destroy", "sgw_mlp_last_error",
            "sgw_mlp_set_standardization", "sgw_mlp_get_params", "sgw_mlp_forward",
@@ -338,6 +340,27 @@ class Context:
         ms = np.zeros(6)
         _check(load().sgw_sigma_estimate(self.ctx, C.byref(p), _dptr(ph), _dptr(sig), _dptr(x),
                                          _dptr(ms)), self.ctx)
+        return sig[..., 0] + 1j * sig[..., 1], x, ms
+
+    def sigma_estimate_states(self, phis, seed, n_zeta, n_eta, n_tau, dt, m_sub, ncoef, emin,
+                              emax, mu=0.0, beta=0.0, n_xi=10000, f_g=0.003, mode=0,
+                              prop_tol=1e-14, n_ft=0, first_sample=0, batch=0, filter=0,
+                              e_homo=0.0, e_lumo=0.0, filter_eps=1e-7):
+        """sigma_estimate for several orbitals phis [K][N] that share the
+        filtered sets, xi sets and zeta propagation; returns Sigma [K][n_zeta]
+        [2 n_tau + 1], X [K][n_zeta] and the phase times."""
+        p = sigma_params(seed, n_zeta, n_eta, n_tau, dt, m_sub, ncoef, emin, emax, mu, beta,
+                         n_xi, f_g, mode, prop_tol, n_ft, first_sample, batch, filter, e_homo,
+                         e_lumo, filter_eps)
+        ph = np.ascontiguousarray(np.asarray(phis, dtype=np.float64))
+        K = ph.shape[0]
+        if ph.ndim != 2 or ph.shape[1] != self.N:
+            raise ValueError("phis must have shape [K][N_g]")
+        sig = np.zeros((K, n_zeta, 2 * n_tau + 1, 2))
+        x = np.zeros((K, n_zeta))
+        ms = np.zeros(6)
+        _check(load().sgw_sigma_estimate_states(self.ctx, C.byref(p), K, _dptr(ph), _dptr(sig),
+                                                _dptr(x), _dptr(ms)), self.ctx)
         return sig[..., 0] + 1j * sig[..., 1], x, ms
 
 

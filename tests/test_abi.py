@@ -69,3 +69,10 @@ def test_struct_layouts_match_header(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(py), cname
         for f, _ in py._fields_:
             assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
+
+
+def test_max_states_matches_header():
+    import re
+    from paper_2601_21005_amd import sgw
+    m = re.search(r"#define\s+SGW_MAX_STATES\s+(\d+)", open(HEADER).read())
+    assert m and int(m.group(1)) == sgw.SGW_MAX_STATES
