@@ -62,6 +62,8 @@ def parse():
     ap.add_argument("--cpu-terms", type=int, default=6,
                     help="filter terms timed for the CPU baseline sample")
     ap.add_argument("--no-bf16", action="store_true", help="skip the BF16-KB / graphs form")
+    ap.add_argument("--no-states", action="store_true",
+                    help="skip the HOMO + LUMO shared-pass form")
     ap.add_argument("--cv", type=int, default=0,
                     help="samples for the control-variate form (0: skip it)")
     ap.add_argument("--cv-cheap", type=int, default=200000)
@@ -151,6 +153,43 @@ def bf16_form(args, s, phi, p, sigma1, sig_plain, homo, gam, precision):
     d_sigma = float(np.max(np.abs(sig - sig_plain)) / np.max(np.abs(sig_plain)))
     return {"gpu_s_per_qp": t * (sigma1 / 0.03) ** 2, "gpu_s_per_sample": t,
             "sigma_t_max_rel_diff_vs_plain": d_sigma}
+
+
+def states_form(args, ctx, phi2, p, homo, lumo, gam, t_sample):
+    """HOMO and LUMO from one shared pass over the same samples: time per
+    sample against two single-state runs, both QP energies, and the gap with
+    its error bar from the per-sample differences (both states see every
+    random set of a sample, so their noise is correlated)."""
+    import numpy as np
+    import torch
+    from paper_2601_21005_amd import sgw
+    B = args.batch
+    for w in range(args.warmup):
+        ctx.sigma_estimate_states(phi2, n_zeta=B, first_sample=w * B, **p)
+    torch.cuda.synchronize()
+    sigs, xs = [], []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        sig, x, _ = ctx.sigma_estimate_states(phi2, n_zeta=B, first_sample=(args.warmup + k) * B,
+                                              **p)
+        sigs.append(sig)
+        xs.append(x)
+    torch.cuda.synchronize()
+    sig, x = np.concatenate(sigs, axis=1), np.concatenate(xs, axis=1)
+    n = sig.shape[1]
+    t = (time.perf_counter() - t0) / n
+    out, y = {}, []
+    for k, (name, eks) in enumerate((("homo", homo), ("lumo", lumo))):
+        eq, _, Z = sgw.sgw_qp_solve(sig[k].mean(0), p["dt"], gam, eks, x[k].mean())
+        re_i = np.array([sgw.sgw_sigma_omega(si, p["dt"], gam, eq)[0].real for si in sig[k]])
+        y.append(Z * (x[k] + re_i))
+        out[f"eqp_{name}_eV"] = eq * HA_EV
+    out["qp_gap_eV"] = out["eqp_lumo_eV"] - out["eqp_homo_eV"]
+    out["gap_err_eV"] = float(np.std(y[1] - y[0], ddof=1) / np.sqrt(n) * HA_EV)
+    out["gap_err_if_independent_eV"] = float(
+        np.sqrt(np.var(y[0], ddof=1) + np.var(y[1], ddof=1)) / np.sqrt(n) * HA_EV)
+    return {"gpu_s_per_sample_two_states": t, "speedup_vs_two_runs": 2 * t_sample / t,
+            "samples": n, **out}
 
 
 def cv_form(args, ctx, s, phis, ev, phi, p, homo, eg, gam, t_sample, sigma1, Z):
@@ -296,6 +335,9 @@ def main():
                                            sgw.SGW_C64_BF16KB)
         forms["bf16x2kb_graphs"] = bf16_form(args, s, phi, p, sigma1, sig, homo, gam,
                                              sgw.SGW_C64_BF16X2KB)
+    if not args.no_states:
+        phi2 = np.stack([phi, phis[s.n_occ].cpu().numpy()])
+        forms["homo_lumo_shared"] = states_form(args, ctx, phi2, p, homo, lumo, gam, t_sample)
     if args.cv:
         forms["control_variate"] = cv_form(args, ctx, s, phis, ev, phi, p, homo, eg, gam,
                                           t_sample, sigma1, Z)
