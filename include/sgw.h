@@ -251,7 +251,11 @@ typedef struct {
  * time ordering -> zeta^+ forward / occupied part backward (Eq. 4) ->
  * contraction (Eq. 5).  sigma_t: host [n_zeta][2 n_tau + 1][2] (re, im);
  * x: host [n_zeta]; phase_ms: nullable host [6] receiving the device time
- * of the phases (filter, tdh, time order, zeta, contraction, total).
+ * of the phases (filter, TDH, time ordering, zeta propagation and
+ * contraction, the rest, total).  In xi mode the zeta propagation runs on a
+ * second stream of the context beside the TDH steps (its time then falls in
+ * the TDH phase; the results are bitwise those of running it afterwards,
+ * which the environment variable SGW_ZETA_OVERLAP=0 at sgw_create selects).
  * Requires N_g to be a multiple of 32 in xi mode. */
 sgw_status sgw_sigma_estimate(sgw_ctx *ctx, const sgw_sigma_params *params,
                               const double *phi, double *sigma_t, double *x,
@@ -294,8 +298,10 @@ sgw_status sgw_sigma_omega(const double *sigma_t, int32_t n_tau, double dt, doub
 /* Launch timer of the dominant kernel: the inverse xy-plane FFT pass that
  * carries the Chebyshev-recurrence epilogue (Eq. 3 filter and the zeta
  * propagator).  enable != 0: from now on every launch of that pass on the
- * context's stream is bracketed by a pair of HIP events; enable = 0 stops
- * it.  sgw_kernel_timer_read synchronises the stream and returns the summed
+ * context's stream is bracketed by a pair of HIP events (launches that
+ * sgw_sigma_estimate issues on the context's second stream, the zeta
+ * propagation running beside the TDH steps, are not timed: they share the
+ * device with the TDH kernels); enable = 0 stops it.  sgw_kernel_timer_read synchronises the stream and returns the summed
  * event time (ms), the number of timed launches and the number of grid
  * points x vectors they processed, then resets the counters. */
 sgw_status sgw_kernel_timer(sgw_ctx *ctx, int32_t enable);

@@ -274,7 +274,7 @@ const void *kb_exp_matrix(sgw_ctx *ctx, double tau) {
   // cache the device matrix per tau
   char key[64];
   std::snprintf(key, sizeof key, "kbexp_%.17g", tau);
-  auto it = ctx->scratch.find(key);
+  auto it = ctx->scratch.find(key + ctx->ns);
   if (it != ctx->scratch.end()) return it->second->p;
   std::vector<double> K;
   kb_exponential_matrix(ctx, tau, K);
@@ -401,6 +401,21 @@ void apply_h(sgw_ctx *ctx, const void *psi, void *hpsi, int64_t nvec, int64_t ld
   }
 }
 
+// Issue work on another stream of the context, with its own scratch buffers.
+struct OnStream {
+  sgw_ctx *c;
+  hipStream_t s0;
+  std::string n0;
+  OnStream(sgw_ctx *ctx, hipStream_t s, const char *ns) : c(ctx), s0(ctx->stream), n0(ctx->ns) {
+    c->stream = s;
+    c->ns = ns;
+  }
+  ~OnStream() {
+    c->stream = s0;
+    c->ns = n0;
+  }
+};
+
 int next_pow2(int n) {
   int p = 1;
   while (p < n) p *= 2;
@@ -453,6 +468,7 @@ sgw_status sgw_create(const sgw_grid *grid, const double *v_loc, const sgw_proje
       if (colon != std::string::npos) c->arch.resize(colon);
     }
     if (const char *fc = std::getenv("SGW_FILTER_CHUNK")) c->filter_chunk = std::atoi(fc);
+    if (const char *ov = std::getenv("SGW_ZETA_OVERLAP")) c->overlap = std::atoi(ov) != 0;
     if (const char *fv = std::getenv("SGW_FORCE_VARIANT")) {
       // "name=i,name=i": pin autotuned kernel variants (testing)
       std::string spec(fv);
@@ -859,10 +875,10 @@ sgw_status sgw_sigma_estimate_states(sgw_ctx *ctx, const sgw_sigma_params *P, in
     const double amp = xi ? 1.0 / std::sqrt(P->n_xi * (32.0 * nseg / N) * ctx->dV) : 0.0;
     const int64_t n_inner = xi ? P->n_xi : N;
 
-    hipEvent_t ev[7];
+    hipEvent_t ev[9];                    // phases; [7], [8]: zeta stream fork and join
     for (auto &e : ev) SGW_HIP(hipEventCreate(&e));
     double ph[6] = {0, 0, 0, 0, 0, 0};
-    struct EvGuard { hipEvent_t *e; ~EvGuard() { for (int i = 0; i < 7; ++i) (void)hipEventDestroy(e[i]); } } eg{ev};
+    struct EvGuard { hipEvent_t *e; ~EvGuard() { for (int i = 0; i < 9; ++i) (void)hipEventDestroy(e[i]); } } eg{ev};
 
     for (int b0 = 0; b0 < P->n_zeta; b0 += Sb) {
       const int S = std::min(Sb, P->n_zeta - b0);
@@ -960,6 +976,40 @@ sgw_status sgw_sigma_estimate_states(sgw_ctx *ctx, const sgw_sigma_params *P, in
                                  hipMemcpyDeviceToDevice, ctx->stream));
       }
       SGW_HIP(hipEventRecord(ev[3], ctx->stream));
+      // zeta propagation, Eq. (4).  In xi mode it runs on the context's second
+      // stream beside the TDH steps (the two meet only in the contraction),
+      // and its overlaps d_m(t_j) are kept for every output step.
+      const bool ovl = xi && ctx->overlap;
+      if (ovl && !ctx->aux) SGW_HIP(hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
+      hipStream_t zs = ovl ? ctx->aux : ctx->stream;
+      const char *zns = ovl ? "|z" : "";
+      void *zb, *zacc, *zt;
+      {
+        OnStream on(ctx, zs, zns);
+        zb = ctx->buf("z_b", cs * N * 2 * S).p;
+        zacc = ctx->buf("z_acc", cs * N * 2 * S).p;
+        zt = ctx->buf("z_tmp", cs * N * 2 * S).p;
+      }
+      const size_t dstep = cs * (size_t)S * (ovl ? P->n_xi : 0);   // one (step, state) of d
+      char *dpa = ovl ? static_cast<char *>(ctx->buf("xi_dp_all", dstep * nt1 * K).p) : nullptr;
+      char *dta = ovl ? static_cast<char *>(ctx->buf("xi_dt_all", dstep * nt1 * K).p) : nullptr;
+      void *zc = zeta;
+      auto zeta_step = [&](int j) {
+        OnStream on(ctx, zs, zns);
+        if (j > 0) {
+          cheb_series(ctx, zc, zb, zacc, zt, 2 * S, pb, P->emin, P->emax);
+          std::swap(zc, zacc);
+        }
+        for (int k = 0; k < K; ++k)
+          launch_xi_zeta(ctx, zc, phi_of(k), blocks, d_ksign.as<uint64_t>(), S, P->n_xi, nseg,
+                         amp * ctx->dV, dpa + dstep * ((size_t)j * K + k),
+                         dta + dstep * ((size_t)j * K + k));
+      };
+      if (ovl) {
+        SGW_HIP(hipEventRecord(ev[7], ctx->stream));
+        SGW_HIP(hipStreamWaitEvent(zs, ev[7], 0));
+        zeta_step(0);
+      }
       // 4. TDH response, stored at the output steps
       const double tau = P->dt / P->m_sub;
       const bool tdh_graph = ctx->graphs && !ctx->ktimer && xi && nt1 > 2;
@@ -980,7 +1030,10 @@ sgw_status sgw_sigma_estimate_states(sgw_ctx *ctx, const sgw_sigma_params *P, in
           });
           if (ex) {
             launch_counter(ctx, 1, 2, false);
-            for (; j < nt1; ++j) SGW_HIP(hipGraphLaunch(ex, ctx->stream));
+            for (; j < nt1; ++j) {
+              SGW_HIP(hipGraphLaunch(ex, ctx->stream));
+              if (ovl) zeta_step(j);
+            }
             break;
           }
         }
@@ -993,6 +1046,7 @@ sgw_status sgw_sigma_estimate_states(sgw_ctx *ctx, const sgw_sigma_params *P, in
         else
           SGW_HIP(hipMemcpy2DAsync(static_cast<char *>(cR) + rs * N * j, rs * N * nt1, st.u, rs * N,
                                    rs * N, (size_t)S * K, hipMemcpyDeviceToDevice, ctx->stream));
+        if (ovl) zeta_step(j);
       }
       SGW_HIP(hipEventRecord(ev[4], ctx->stream));
       // 5. time ordering
@@ -1002,10 +1056,18 @@ sgw_status sgw_sigma_estimate_states(sgw_ctx *ctx, const sgw_sigma_params *P, in
                                     d_tw.p),
                   SGW_EUNSUPPORTED, "time-ordering length not built");
       SGW_HIP(hipEventRecord(ev[5], ctx->stream));
-      // 6. zeta propagation and contraction, Eq. (4), Eq. (5)
+      // 6. contraction, Eq. (5) (with the zeta propagation here when it did
+      // not run beside the TDH)
       double *d_sig = ctx->buf("sig", sizeof(double) * 4 * S * nt1 * K).as<double>();
-      void *zb = ctx->buf("z_b", cs * N * 2 * S).p, *zacc = ctx->buf("z_acc", cs * N * 2 * S).p;
-      void *zt = ctx->buf("z_tmp", cs * N * 2 * S).p;
+      if (ovl) {
+        SGW_HIP(hipEventRecord(ev[8], zs));
+        SGW_HIP(hipStreamWaitEvent(ctx->stream, ev[8], 0));
+        for (int j = 0; j < nt1; ++j)
+          for (int k = 0; k < K; ++k)
+            launch_contract_xi(ctx, cto + cto_state * k, dpa + dstep * ((size_t)j * K + k),
+                               dta + dstep * ((size_t)j * K + k), S, P->n_xi, nt1, j,
+                               d_sig + (size_t)4 * S * nt1 * k);
+      }
       void *dp = nullptr, *dtl = nullptr;
       double *partial = nullptr;
       if (xi) {
@@ -1014,8 +1076,7 @@ sgw_status sgw_sigma_estimate_states(sgw_ctx *ctx, const sgw_sigma_params *P, in
       } else {
         partial = ctx->buf("c_partial", sizeof(double) * 4 * S * ((N + 4095) / 4096)).as<double>();
       }
-      void *zc = zeta;
-      for (int j = 0; j < nt1; ++j) {
+      for (int j = 0; j < (ovl ? 0 : nt1); ++j) {
         if (j > 0) {
           cheb_series(ctx, zc, zb, zacc, zt, 2 * S, pb, P->emin, P->emax);
           std::swap(zc, zacc);

@@ -143,7 +143,18 @@ struct sgw_ctx {
     }
     return kt_events[i];
   }
+  // second stream of the context (non-blocking, default priority): the zeta
+  // propagation of sgw_sigma_estimate runs on it beside the TDH steps.  While
+  // work is issued there, `ns` suffixes every scratch buffer name so the two
+  // streams never share scratch memory.
+  hipStream_t aux = nullptr;
+  bool overlap = true;
+  std::string ns;
   ~sgw_ctx() {
+    if (aux) {
+      (void)hipStreamSynchronize(aux);
+      (void)hipStreamDestroy(aux);
+    }
     for (auto e : kt_events) (void)hipEventDestroy(e);
     for (auto &g : gexec) (void)hipGraphExecDestroy(g.second);
   }
@@ -201,7 +212,7 @@ struct sgw_ctx {
   // scratch (grown on demand)
   std::map<std::string, std::unique_ptr<sgw::DevBuf>> scratch;
   sgw::DevBuf &buf(const std::string &name, size_t bytes) {
-    auto &p = scratch[name];
+    auto &p = scratch[name + ns];
     if (!p) p.reset(new sgw::DevBuf());
     if (bytes > p->bytes && p->p) clear_graphs();   // captured graphs hold the old address
     p->ensure(bytes);

@@ -489,7 +489,7 @@ void fft3d_apply_t(sgw_ctx *ctx, const void *src, void *tmp, void *dst, int64_t 
     // inverse xy with the epilogue
     PassArgs b = a;
     b.src = tmpv; b.ld_src = N; b.dst = dstv; b.ld_dst = ld; b.mode = inv_mode; b.inverse = 1;
-    const bool timed = ctx->ktimer && inv_mode == PLANE_INV_CHEB;
+    const bool timed = ctx->ktimer && inv_mode == PLANE_INV_CHEB && ctx->ns.empty();
     if (!use_plane) {
       PassArgs py = a;
       py.dst = tmpv; py.ld_dst = N; py.axis = 1; py.tw0 = twy; py.inverse = 1; py.mul = MUL_NONE;

@@ -380,8 +380,10 @@ __global__ __launch_bounds__(NTK) void k_kb_gather_mma(
 
 // dst_v(r) += s1 sum_e beta_e(r) C'[p(e)][v] on the points r of tile t (s1 real).
 // betaT holds each tile's block transposed, [512 points][nek entries], with the
-// entry count nek padded to 32 (zeros).
-template <class Op, int NVB>
+// entry count nek padded to 32 (zeros).  A wave owns MJ M tiles of 16 points, so
+// a workgroup covers 64 MJ points and a tile takes 512 / (64 MJ) workgroups per
+// vector block (fewer registers per wave for MJ = 4, more waves per SIMD).
+template <class Op, int NVB, int MJ>
 __global__ __launch_bounds__(NTK) void k_kb_scatter_mma(
     const float2 *coef, int64_t nvec, const int *tile_base, const int *tile_off,
     const int *tile_offT, const int *entry_proj, const typename Op::T *betaT, float2 *dst,
@@ -390,10 +392,13 @@ __global__ __launch_bounds__(NTK) void k_kb_scatter_mma(
   constexpr int NC = 2 * NVB, NTL = NC / 16;
   constexpr int EL = 16 / (int)sizeof(T);
   constexpr int PE = KB_MAXE + EL;                  // LDS pitch of a coefficient column
+  constexpr int NH = KB_TP / (64 * MJ);             // workgroups per tile and vector block
   __shared__ __align__(16) T sc[(Op::SPLIT ? 2 : 1) * NC * PE];   // C' [column][entry] (hi, lo)
   int t;
-  int64_t vb;
-  if (!tile_block(ntile, nvb, t, vb)) return;
+  int64_t vbh;
+  if (!tile_block(ntile, nvb * NH, t, vbh)) return;
+  const int64_t vb = vbh / NH;
+  const int p0 = (int)(vbh % NH) * 64 * MJ;       // first point of this workgroup
   const int64_t v0 = vb * NVB;
   const int off = tile_off[t], ne = tile_off[t + 1] - off;
   const int offT = tile_offT[t], nek = tile_offT[t + 1] - offT;
@@ -429,23 +434,23 @@ __global__ __launch_bounds__(NTK) void k_kb_scatter_mma(
   // at two neighbouring points (even lane: r = 0, 1; odd lane: r = 2, 3)
   const int odd = col & 1;
   const int vcol = col >> 1;
-  float2 *ptr[8][NTL];
+  float2 *ptr[MJ][NTL];
 #pragma unroll
-  for (int j = 0; j < 8; ++j)
+  for (int j = 0; j < MJ; ++j)
 #pragma unroll
     for (int n = 0; n < NTL; ++n) {
       const int vl = 8 * n + vcol;
-      const int pb = 16 * (8 * w + j) + 4 * q + 2 * odd;
+      const int pb = p0 + 16 * (MJ * w + j) + 4 * q + 2 * odd;
       ptr[j][n] = v0 + vl < nvec ? dst + (v0 + vl) * ld + tile_point(base, pb, nx, ny, lx, ly)
                                  : nullptr;
     }
   // with one N tile the old destination values are loaded before the K loop,
   // so their memory latency overlaps the products
   constexpr bool PREFETCH = NTL == 1;
-  float2 o[8][NTL][2];
+  float2 o[MJ][NTL][2];
   if constexpr (PREFETCH) {
 #pragma unroll
-    for (int j = 0; j < 8; ++j)
+    for (int j = 0; j < MJ; ++j)
 #pragma unroll
       for (int n = 0; n < NTL; ++n)
         if (ptr[j][n]) {
@@ -453,18 +458,19 @@ __global__ __launch_bounds__(NTK) void k_kb_scatter_mma(
           o[j][n][1] = ptr[j][n][1];
         }
   }
-  // wave w owns the M tiles (16 points each) 8 w .. 8 w + 7
-  f32x4 acc[8][NTL];
+  // wave w owns the M tiles (16 points each) MJ w .. MJ w + MJ - 1 from p0
+  f32x4 acc[MJ][NTL];
 #pragma unroll
-  for (int j = 0; j < 8; ++j)
+  for (int j = 0; j < MJ; ++j)
 #pragma unroll
     for (int n = 0; n < NTL; ++n) acc[j][n] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const T *bt = betaT + (int64_t)offT * KB_TP + (int64_t)(128 * w + col) * nek + EL * q;
+  const T *bt =
+      betaT + (int64_t)offT * KB_TP + (int64_t)(p0 + 16 * MJ * w + col) * nek + EL * q;
   constexpr int NS = Op::SPLIT ? 2 : 1;            // B terms (hi, lo)
-  u32x4 a_cur[8], a_nxt[8], b_cur[NS][NTL], b_nxt[NS][NTL];
+  u32x4 a_cur[MJ], a_nxt[MJ], b_cur[NS][NTL], b_nxt[NS][NTL];
   auto load_group = [&](int k0, u32x4 *a, u32x4 (*b)[NTL]) {
 #pragma unroll
-    for (int j = 0; j < 8; ++j) a[j] = ld16(bt + (int64_t)(16 * j) * nek + k0);
+    for (int j = 0; j < MJ; ++j) a[j] = ld16(bt + (int64_t)(16 * j) * nek + k0);
 #pragma unroll
     for (int h = 0; h < NS; ++h)
 #pragma unroll
@@ -475,21 +481,21 @@ __global__ __launch_bounds__(NTK) void k_kb_scatter_mma(
   for (int k0 = 0; k0 < nek; k0 += Op::GK) {
     if (k0 + Op::GK < nek) load_group(k0 + Op::GK, a_nxt, b_nxt);
 #pragma unroll
-    for (int j = 0; j < 8; ++j)
+    for (int j = 0; j < MJ; ++j)
 #pragma unroll
       for (int n = 0; n < NTL; ++n)
 #pragma unroll
         for (int h = 0; h < NS; ++h) Op::mma(acc[j][n], a_cur[j], b_cur[h][n]);
 #pragma unroll
-    for (int j = 0; j < 8; ++j) a_cur[j] = a_nxt[j];
+    for (int j = 0; j < MJ; ++j) a_cur[j] = a_nxt[j];
 #pragma unroll
     for (int h = 0; h < NS; ++h)
 #pragma unroll
       for (int n = 0; n < NTL; ++n) b_cur[h][n] = b_nxt[h][n];
   }
-  float2 c[8][NTL][2];
+  float2 c[MJ][NTL][2];
 #pragma unroll
-  for (int j = 0; j < 8; ++j)
+  for (int j = 0; j < MJ; ++j)
 #pragma unroll
     for (int n = 0; n < NTL; ++n) {
       const f32x4 d = acc[j][n];
@@ -500,7 +506,7 @@ __global__ __launch_bounds__(NTK) void k_kb_scatter_mma(
     }
   if constexpr (!PREFETCH) {
 #pragma unroll
-    for (int j = 0; j < 8; ++j)
+    for (int j = 0; j < MJ; ++j)
 #pragma unroll
       for (int n = 0; n < NTL; ++n)
         if (ptr[j][n]) {
@@ -509,7 +515,7 @@ __global__ __launch_bounds__(NTK) void k_kb_scatter_mma(
         }
   }
 #pragma unroll
-  for (int j = 0; j < 8; ++j)
+  for (int j = 0; j < MJ; ++j)
 #pragma unroll
     for (int n = 0; n < NTL; ++n)
       if (ptr[j][n]) {
@@ -521,8 +527,9 @@ __global__ __launch_bounds__(NTK) void k_kb_scatter_mma(
 // variants (autotuned per context, operand type and batch width)
 struct GatherVariant { int nvb, mt; };
 static const GatherVariant kGather[] = {{8, 2}, {8, 4}, {16, 2}, {16, 4}};
-static const int kScatterNvb[] = {8, 16};
-constexpr int NGATHER = 4, NSCATTER = 2;
+struct ScatterVariant { int nvb, mj; };
+static const ScatterVariant kScatter[] = {{8, 8}, {16, 8}, {8, 4}, {16, 4}, {8, 2}, {16, 2}};
+constexpr int NGATHER = 4, NSCATTER = 6;
 
 template <class Op>
 static void launch_gather_variant(int vi, dim3 g, hipStream_t st, const float2 *psi, int64_t ld,
@@ -546,12 +553,17 @@ static void launch_scatter_variant(int vi, dim3 g, hipStream_t st, const float2 
                                    const int *ep, const typename Op::T *betaT, float2 *dst,
                                    int64_t ld, float s1, int nx, int ny, int lx, int ly,
                                    int ntile, int nvb) {
-  if (vi == 0)
-    hipLaunchKernelGGL((k_kb_scatter_mma<Op, 8>), g, dim3(NTK), 0, st, coef, nvec, tb, to, toT,
-                       ep, betaT, dst, ld, s1, nx, ny, lx, ly, ntile, nvb);
-  else
-    hipLaunchKernelGGL((k_kb_scatter_mma<Op, 16>), g, dim3(NTK), 0, st, coef, nvec, tb, to,
-                       toT, ep, betaT, dst, ld, s1, nx, ny, lx, ly, ntile, nvb);
+  switch (vi) {
+#define SGW_S(I, A, B)                                                                           \
+  case I:                                                                                        \
+    hipLaunchKernelGGL((k_kb_scatter_mma<Op, A, B>), g, dim3(NTK), 0, st, coef, nvec, tb, to,   \
+                       toT, ep, betaT, dst, ld, s1, nx, ny, lx, ly, ntile, nvb);                 \
+    break;
+    SGW_S(0, 8, 8) SGW_S(1, 16, 8) SGW_S(2, 8, 4) SGW_S(3, 16, 4) SGW_S(4, 8, 2)
+    SGW_S(5, 16, 2)
+#undef SGW_S
+
+  }
 }
 
 // Operand arrays of the MFMA kernels: beta per entry [entry][512] in the
@@ -676,8 +688,10 @@ static void scatter_t(sgw_ctx *ctx, const void *coef, int64_t nvec, void *dst, i
     auto go = [&](auto op, const char *name, const auto *betaT) {
       using Op = decltype(op);
       auto launch = [&](int vi, float s) {
-        const int64_t nvb = (nvec + kScatterNvb[vi] - 1) / kScatterNvb[vi];
-        launch_scatter_variant<Op>(vi, tile_grid(ctx->kb_ntile, nvb), ctx->stream,
+        const ScatterVariant &sv = kScatter[vi];
+        const int64_t nvb = (nvec + sv.nvb - 1) / sv.nvb;
+        const int64_t nh = KB_TP / (64 * sv.mj);
+        launch_scatter_variant<Op>(vi, tile_grid(ctx->kb_ntile, nvb * nh), ctx->stream,
                                    static_cast<const float2 *>(coef), nvec,
                                    ctx->d_kb_tile_base.as<int>(), ctx->d_kb_tile_off.as<int>(),
                                    ctx->d_kb_tile_offT.as<int>(), ctx->d_kb_entry_proj.as<int>(),

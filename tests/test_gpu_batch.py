@@ -143,3 +143,29 @@ def test_tune_cache_file(tmp_path):
         assert len(keys) == 2, entries
         assert all(k.startswith("gfx") for k in keys)
     assert np.array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("graphs", [False, True])
+def test_zeta_overlap_bitwise(tiny8, tiny8_eig, monkeypatch, graphs):
+    """The zeta propagation on the context's second stream, beside the TDH
+    steps, gives bitwise the results of running it after them (two states,
+    so the stored overlaps of every state and step are used)."""
+    s, _ = tiny8
+    e, V = tiny8_eig
+    phis = np.stack([V[s.n_occ - 1], V[s.n_occ]])
+    st = torch.cuda.Stream()
+    res = []
+    for ov in ("1", "0"):
+        monkeypatch.setenv("SGW_ZETA_OVERLAP", ov)
+        ctx = ctx_on_stream(s, sgw.SGW_C64, st, max_nvec=16)
+        lo, hi = ctx.bounds()
+        if graphs:
+            ctx.use_graphs(True)
+        p = dict(seed=63, n_eta=4, n_tau=11, dt=0.1, m_sub=2, mu=0.5 * (e[1] + e[2]),
+                 beta=10.0, ncoef=151, emin=lo, emax=hi, n_xi=64, f_g=0.125, mode=0)
+        a = ctx.sigma_estimate_states(phis, n_zeta=3, **p)
+        b = ctx.sigma_estimate_states(phis, n_zeta=3, **p)
+        ctx.close()
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+        res.append(a)
+    assert np.array_equal(res[0][0], res[1][0]) and np.array_equal(res[0][1], res[1][1])
