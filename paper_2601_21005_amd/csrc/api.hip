@@ -283,13 +283,13 @@ const void *kb_exp_matrix(sgw_ctx *ctx, double tau) {
   return b.p;
 }
 
-void kb_exp_apply(sgw_ctx *ctx, void *psi, int64_t nvec, double tau) {
+void kb_exp_apply(sgw_ctx *ctx, void *psi, int64_t ld, int64_t nvec, double tau) {
   const void *K = kb_exp_matrix(ctx, tau);
   void *C = ctx->buf("kbC", ctx->csize() * ctx->kb.nproj * nvec).p;
   void *C2 = ctx->buf("kbC2", ctx->csize() * ctx->kb.nproj * nvec).p;
-  kb_gather(ctx, psi, nvec, ctx->N, C);
+  kb_gather(ctx, psi, nvec, ld, C);
   kb_mix_dense(ctx, K, C, C2, nvec);
-  kb_scatter(ctx, C2, nvec, psi, ctx->N, 1.0, 0.0, nullptr, 0.0, 0.0);
+  kb_scatter(ctx, C2, nvec, psi, ld, 1.0, 0.0, nullptr, 0.0, 0.0);
 }
 
 // Poisson of S complex fields rho (ld = N): POISSON -> v, u; SPLIT -> r0, r1
@@ -319,35 +319,35 @@ void tdh_potentials(sgw_ctx *ctx, const void *rho, int64_t S, int nk, PlaneMode 
   }
 }
 
-// One or more Strang substeps for nk response states;  the local half steps
-// of consecutive substeps are merged (a = tau).  `open`: the state is
-// synchronised at entry (first half step a = tau/2); `close`: apply the
-// closing half step.
-void tdh_substeps(sgw_ctx *ctx, sgw_tdh_state *st, int nk, int nsub, double tau, bool open,
-                  bool close) {
+// One or more Strang substeps for nk response states (psi vectors ldp
+// apart);  the local half steps of consecutive substeps are merged (a = tau).
+// `open`: the state is synchronised at entry (first half step a = tau/2);
+// `close`: apply the closing half step.
+void tdh_substeps(sgw_ctx *ctx, sgw_tdh_state *st, int64_t ldp, int nk, int nsub, double tau,
+                  bool open, bool close) {
   const int64_t S = st->nsample, nv = (1 + nk) * (int64_t)st->nsample * st->neta;
   void *tmp = ctx->buf("tdh_tmp", ctx->csize() * ctx->N * nv).p;
   void *rho = ctx->buf("tdh_rho", ctx->csize() * ctx->N * S * (1 + nk / 2)).p;
   for (int k = 0; k < nsub; ++k) {
-    launch_tdh_local(ctx, st->psi, st->v, st->u, st->nsample, st->neta, nk,
+    launch_tdh_local(ctx, st->psi, ldp, st->v, st->u, st->nsample, st->neta, nk,
                      (k == 0 && open) ? 0.5 * tau : tau);
-    if (ctx->has_kb) kb_exp_apply(ctx, st->psi, nv, 0.5 * tau);
-    fft3d_apply(ctx, st->psi, tmp, st->psi, nv, ctx->N, MUL_PROP, tau, PLANE_INV_STORE,
+    if (ctx->has_kb) kb_exp_apply(ctx, st->psi, ldp, nv, 0.5 * tau);
+    fft3d_apply(ctx, st->psi, tmp, st->psi, nv, ldp, MUL_PROP, tau, PLANE_INV_STORE,
                 EpiArgs());
-    if (ctx->has_kb) kb_exp_apply(ctx, st->psi, nv, 0.5 * tau);
-    launch_tdh_density(ctx, st->psi, rho, st->nsample, st->neta, nk, st->weight);
+    if (ctx->has_kb) kb_exp_apply(ctx, st->psi, ldp, nv, 0.5 * tau);
+    launch_tdh_density(ctx, st->psi, ldp, rho, st->nsample, st->neta, nk, st->weight);
     tdh_potentials(ctx, rho, S, nk, PLANE_INV_POISSON, st->v, st->u, st->vh0);
   }
   if (close)
-    launch_tdh_local(ctx, st->psi, st->v, st->u, st->nsample, st->neta, nk, 0.5 * tau);
+    launch_tdh_local(ctx, st->psi, ldp, st->v, st->u, st->nsample, st->neta, nk, 0.5 * tau);
 }
 
-void tdh_start(sgw_ctx *ctx, sgw_tdh_state *st, int nk, const void *dv) {
+void tdh_start(sgw_ctx *ctx, sgw_tdh_state *st, int64_t ldp, int nk, const void *dv) {
   const int64_t S = st->nsample;
   void *rho = ctx->buf("tdh_rho", ctx->csize() * ctx->N * S * (1 + nk / 2)).p;
-  launch_tdh_tangent(ctx, st->psi, dv, st->nsample, st->neta, nk);
+  launch_tdh_tangent(ctx, st->psi, ldp, dv, st->nsample, st->neta, nk);
   launch_bcast_real(ctx, ctx->d_vloc.p, st->v, st->nsample);
-  launch_tdh_density(ctx, st->psi, rho, st->nsample, st->neta, nk, st->weight);
+  launch_tdh_density(ctx, st->psi, ldp, rho, st->nsample, st->neta, nk, st->weight);
   tdh_potentials(ctx, rho, S, nk, PLANE_INV_SPLIT, st->vh0, st->u, nullptr);
 }
 
@@ -722,7 +722,7 @@ sgw_status sgw_tdh_init(sgw_ctx *ctx, sgw_tdh_state *st, const void *dv) {
   return guarded(ctx, [&] {
     check_state(ctx, st);
     check_ptr(dv, "dv");
-    tdh_start(ctx, st, 1, dv);
+    tdh_start(ctx, st, ctx->N, 1, dv);
   });
 }
 
@@ -732,7 +732,7 @@ sgw_status sgw_tdh_step(sgw_ctx *ctx, sgw_tdh_state *st, int32_t nsub, double dt
     check_state(ctx, st);
     SGW_REQUIRE(nsub >= 0 && std::isfinite(dt_sub), SGW_EINVAL, "bad nsub or dt_sub");
     if (nsub == 0) return;
-    tdh_substeps(ctx, st, 1, nsub, dt_sub, true, true);
+    tdh_substeps(ctx, st, ctx->N, 1, nsub, dt_sub, true, true);
   });
 }
 
@@ -931,7 +931,10 @@ sgw_status sgw_sigma_estimate_states(sgw_ctx *ctx, const sgw_sigma_params *P, in
       }
       // 3. unpack, kick potentials, exchange (per state), TDH start.  psi
       // holds per sample the eta set and one tangent copy per state.
-      void *psi = ctx->buf("tdh_psi", cs * N * (1 + K) * neta * S).p;
+      // a leading dimension off a multiple of 1024 points spreads the same
+      // tile of successive vectors over cache sets (the KB kernels)
+      const int64_t ldp = N % 1024 == 0 ? N + 64 : N;
+      void *psi = ctx->buf("tdh_psi", cs * ldp * (1 + K) * neta * S).p;
       void *zeta = ctx->buf("zeta", cs * N * 2 * S).p;
       char *kick = static_cast<char *>(ctx->buf("kick", cs * N * S * K).p);
       const int64_t nxf = (int64_t)S * neta / 2;
@@ -942,6 +945,7 @@ sgw_status sgw_sigma_estimate_states(sgw_ctx *ctx, const sgw_sigma_params *P, in
         ua.psi = k == 0 ? psi : nullptr; ua.zeta = k == 0 ? zeta : nullptr;
         ua.kick = kick + cs * N * S * k; ua.xsrc = F0; ua.S = S; ua.neta = neta;
         ua.ncopy = 1 + K;
+        ua.ldp = ldp;
         launch_unpack(ctx, ua);
         fft3d_apply(ctx, F0, FT, F1, nxf, N, MUL_COUL, 0.0, PLANE_INV_STORE, EpiArgs());
         launch_redot(ctx, F0, F1, N, nxf, d_xd.as<double>() + nxf * k);
@@ -956,7 +960,7 @@ sgw_status sgw_sigma_estimate_states(sgw_ctx *ctx, const sgw_sigma_params *P, in
       st.v = ctx->buf("tdh_v", rs * N * S).p;
       st.u = ctx->buf("tdh_u", rs * N * S * K).p;
       st.vh0 = ctx->buf("tdh_vh0", rs * N * S).p;
-      tdh_start(ctx, &st, K, dv);
+      tdh_start(ctx, &st, ldp, K, dv);
       // u and the stored rows of state k
       const size_t cr_state = rs * (size_t)S * nt1 * n_inner;
       auto u_of = [&](int k) { return static_cast<const char *>(st.u) + rs * N * S * k; };
@@ -1021,7 +1025,7 @@ sgw_status sgw_sigma_estimate_states(sgw_ctx *ctx, const sgw_sigma_params *P, in
               num_key({(double)S, (double)neta, (double)P->m_sub, tau, (double)P->n_xi,
                        (double)nseg, amp * ctx->dV, (double)nt1, (double)K});
           hipGraphExec_t ex = captured(ctx, key, [&] {
-            tdh_substeps(ctx, &st, K, P->m_sub, tau, false, false);
+            tdh_substeps(ctx, &st, ldp, K, P->m_sub, tau, false, false);
             for (int k = 0; k < K; ++k)
               launch_xi_real(ctx, u_of(k), blocks, d_ksign.as<uint64_t>(), S, P->n_xi, nseg,
                              amp * ctx->dV, static_cast<char *>(cR) + cr_state * k,
@@ -1037,7 +1041,7 @@ sgw_status sgw_sigma_estimate_states(sgw_ctx *ctx, const sgw_sigma_params *P, in
             break;
           }
         }
-        tdh_substeps(ctx, &st, K, P->m_sub, tau, j == 1, false);
+        tdh_substeps(ctx, &st, ldp, K, P->m_sub, tau, j == 1, false);
         if (xi)
           for (int k = 0; k < K; ++k)
             launch_xi_real(ctx, u_of(k), blocks, d_ksign.as<uint64_t>(), S, P->n_xi, nseg,

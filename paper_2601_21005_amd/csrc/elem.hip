@@ -251,14 +251,15 @@ __global__ void k_unpack(UnpackArgs a, int64_t N, R amp) {
     zeta[N + r] = cmake<C>(zocc, 0);
   }
   static_cast<C *>(a.kick)[s * N + r] = cmake<C>(ph * zb, 0);
-  C *psi = a.psi ? static_cast<C *>(a.psi) + s * a.ncopy * a.neta * N : nullptr;
+  const int64_t lp = a.ldp > 0 ? a.ldp : N;
+  C *psi = a.psi ? static_cast<C *>(a.psi) + s * a.ncopy * a.neta * lp : nullptr;
   C *xs = static_cast<C *>(a.xsrc) + s * (a.neta / 2) * N;
   for (int l = 0; l < a.neta; l += 2) {
     const R e0 = real_component<R>(filt, q0 + 1 + l, N, r);
     const R e1 = real_component<R>(filt, q0 + 2 + l, N, r);
     if (psi) {
-      psi[(int64_t)l * N + r] = cmake<C>(e0, 0);
-      psi[(int64_t)(l + 1) * N + r] = cmake<C>(e1, 0);
+      psi[(int64_t)l * lp + r] = cmake<C>(e0, 0);
+      psi[(int64_t)(l + 1) * lp + r] = cmake<C>(e1, 0);
     }
     xs[(int64_t)(l / 2) * N + r] = cmake<C>(ph * e0, ph * e1);
   }
@@ -276,23 +277,25 @@ void launch_unpack(sgw_ctx *ctx, const UnpackArgs &a) {
 }
 
 // ============================================================ TDH
-// A sample's block holds 1 + K copies of its N_eta orbitals, psi[s][c][l]:
-// c = 0 the unperturbed eta, c = 1 + k the tangent delta-eta of state k,
-// whose response field is u[k][s].  K = 1 is the single-state layout.
+// A sample's block holds 1 + K copies of its N_eta orbitals, psi[s][c][l]
+// (vectors ld apart): c = 0 the unperturbed eta, c = 1 + k the tangent
+// delta-eta of state k, whose response field is u[k][s].  K = 1 is the
+// single-state layout.
 
 // psi[s][1 + k][l] = -i dv[k][s] psi[s][0][l]
 template <typename R>
-__global__ void k_tdh_tangent(cplx<R> *psi, const R *dv, int neta, int nk, int64_t N) {
+__global__ void k_tdh_tangent(cplx<R> *psi, const R *dv, int neta, int nk, int64_t N,
+                              int64_t ld) {
   const int64_t r = (int64_t)blockIdx.x * NT + threadIdx.x;
   const int64_t s = blockIdx.y, S = gridDim.y;
   if (r >= N) return;
-  cplx<R> *p0 = psi + s * (1 + nk) * neta * N;
+  cplx<R> *p0 = psi + s * (1 + nk) * neta * ld;
   for (int k = 0; k < nk; ++k) {
     const R d = dv[(k * S + s) * N + r];
-    cplx<R> *p1 = p0 + (int64_t)(1 + k) * neta * N;
+    cplx<R> *p1 = p0 + (int64_t)(1 + k) * neta * ld;
     for (int l = 0; l < neta; ++l) {
-      const cplx<R> e = p0[(int64_t)l * N + r];
-      p1[(int64_t)l * N + r] = cmake<cplx<R>>(d * e.y, -d * e.x);
+      const cplx<R> e = p0[(int64_t)l * ld + r];
+      p1[(int64_t)l * ld + r] = cmake<cplx<R>>(d * e.y, -d * e.x);
     }
   }
 }
@@ -301,7 +304,7 @@ __global__ void k_tdh_tangent(cplx<R> *psi, const R *dv, int neta, int nk, int64
 // delta-eta_k <- e^{-i V a} (delta-eta_k - i a u_k eta)
 template <typename R>
 __global__ void k_tdh_local(cplx<R> *psi, const R *v, const R *u, int neta, int nk, int64_t N,
-                            R a) {
+                            int64_t ld, R a) {
   const int64_t r = (int64_t)blockIdx.x * NT + threadIdx.x;
   const int64_t s = blockIdx.y, S = gridDim.y;
   if (r >= N) return;
@@ -312,21 +315,22 @@ __global__ void k_tdh_local(cplx<R> *psi, const R *v, const R *u, int neta, int 
   R au[SGW_MAX_STATES];
 #pragma unroll
   for (int k = 0; k < SGW_MAX_STATES; ++k) au[k] = k < nk ? a * u[(k * S + s) * N + r] : (R)0;
-  cplx<R> *p0 = psi + s * (1 + nk) * neta * N;
+  cplx<R> *p0 = psi + s * (1 + nk) * neta * ld;
+#pragma unroll 4
   for (int l = 0; l < neta; ++l) {
-    const cplx<R> e = p0[(int64_t)l * N + r];
+    const cplx<R> e = p0[(int64_t)l * ld + r];
 #pragma unroll
     for (int k = 0; k < SGW_MAX_STATES; ++k) {
       if (k < nk) {
-        cplx<R> *p1 = p0 + (int64_t)(1 + k) * neta * N;
-        cplx<R> d = p1[(int64_t)l * N + r];
+        cplx<R> *p1 = p0 + (int64_t)(1 + k) * neta * ld;
+        cplx<R> d = p1[(int64_t)l * ld + r];
         d.x += au[k] * e.y;      // - i a u eta
         d.y -= au[k] * e.x;
         // multiply by (cs - i sn)
-        p1[(int64_t)l * N + r] = cmake<cplx<R>>(cs * d.x + sn * d.y, cs * d.y - sn * d.x);
+        p1[(int64_t)l * ld + r] = cmake<cplx<R>>(cs * d.x + sn * d.y, cs * d.y - sn * d.x);
       }
     }
-    p0[(int64_t)l * N + r] = cmake<cplx<R>>(cs * e.x + sn * e.y, cs * e.y - sn * e.x);
+    p0[(int64_t)l * ld + r] = cmake<cplx<R>>(cs * e.x + sn * e.y, cs * e.y - sn * e.x);
   }
 }
 
@@ -335,21 +339,22 @@ __global__ void k_tdh_local(cplx<R> *psi, const R *v, const R *u, int neta, int 
 // b >= 1, rho[b][s] = dn_{2b-1} + i dn_{2b} (0 past the last state).
 template <typename R>
 __global__ void k_tdh_density(const cplx<R> *psi, cplx<R> *rho, int neta, int nk, int64_t N,
-                              R w) {
+                              int64_t ld, R w) {
   const int64_t r = (int64_t)blockIdx.x * NT + threadIdx.x;
   const int64_t s = blockIdx.y, S = gridDim.y;
   if (r >= N) return;
-  const cplx<R> *p0 = psi + s * (1 + nk) * neta * N;
+  const cplx<R> *p0 = psi + s * (1 + nk) * neta * ld;
   R n = 0, dn[SGW_MAX_STATES];
 #pragma unroll
   for (int k = 0; k < SGW_MAX_STATES; ++k) dn[k] = 0;
+#pragma unroll 4
   for (int l = 0; l < neta; ++l) {
-    const cplx<R> e = p0[(int64_t)l * N + r];
+    const cplx<R> e = p0[(int64_t)l * ld + r];
     n += e.x * e.x + e.y * e.y;
 #pragma unroll
     for (int k = 0; k < SGW_MAX_STATES; ++k) {
       if (k < nk) {
-        const cplx<R> d = p0[(int64_t)((1 + k) * neta + l) * N + r];
+        const cplx<R> d = p0[(int64_t)((1 + k) * neta + l) * ld + r];
         dn[k] += e.x * d.x + e.y * d.y;
       }
     }
@@ -370,41 +375,42 @@ __global__ void k_bcast_real(const R *src, R *dst, int64_t N) {
   if (r < N) dst[(int64_t)blockIdx.y * N + r] = src[r];
 }
 
-void launch_tdh_tangent(sgw_ctx *ctx, void *psi, const void *dv, int S, int neta, int nk) {
+void launch_tdh_tangent(sgw_ctx *ctx, void *psi, int64_t ld, const void *dv, int S, int neta,
+                        int nk) {
   if (ctx->dbl)
     hipLaunchKernelGGL(k_tdh_tangent<double>, grid1(ctx->N, S), dim3(NT), 0, ctx->stream,
                        static_cast<double2 *>(psi), static_cast<const double *>(dv), neta, nk,
-                       ctx->N);
+                       ctx->N, ld);
   else
     hipLaunchKernelGGL(k_tdh_tangent<float>, grid1(ctx->N, S), dim3(NT), 0, ctx->stream,
                        static_cast<float2 *>(psi), static_cast<const float *>(dv), neta, nk,
-                       ctx->N);
+                       ctx->N, ld);
   SGW_HIP(hipGetLastError());
 }
 
-void launch_tdh_local(sgw_ctx *ctx, void *psi, const void *v, const void *u, int S, int neta,
-                      int nk, double a) {
+void launch_tdh_local(sgw_ctx *ctx, void *psi, int64_t ld, const void *v, const void *u, int S,
+                      int neta, int nk, double a) {
   if (ctx->dbl)
     hipLaunchKernelGGL(k_tdh_local<double>, grid1(ctx->N, S), dim3(NT), 0, ctx->stream,
                        static_cast<double2 *>(psi), static_cast<const double *>(v),
-                       static_cast<const double *>(u), neta, nk, ctx->N, a);
+                       static_cast<const double *>(u), neta, nk, ctx->N, ld, a);
   else
     hipLaunchKernelGGL(k_tdh_local<float>, grid1(ctx->N, S), dim3(NT), 0, ctx->stream,
                        static_cast<float2 *>(psi), static_cast<const float *>(v),
-                       static_cast<const float *>(u), neta, nk, ctx->N, (float)a);
+                       static_cast<const float *>(u), neta, nk, ctx->N, ld, (float)a);
   SGW_HIP(hipGetLastError());
 }
 
-void launch_tdh_density(sgw_ctx *ctx, const void *psi, void *rho, int S, int neta, int nk,
-                        double w) {
+void launch_tdh_density(sgw_ctx *ctx, const void *psi, int64_t ld, void *rho, int S, int neta,
+                        int nk, double w) {
   if (ctx->dbl)
     hipLaunchKernelGGL(k_tdh_density<double>, grid1(ctx->N, S), dim3(NT), 0, ctx->stream,
                        static_cast<const double2 *>(psi), static_cast<double2 *>(rho), neta, nk,
-                       ctx->N, w);
+                       ctx->N, ld, w);
   else
     hipLaunchKernelGGL(k_tdh_density<float>, grid1(ctx->N, S), dim3(NT), 0, ctx->stream,
                        static_cast<const float2 *>(psi), static_cast<float2 *>(rho), neta, nk,
-                       ctx->N, (float)w);
+                       ctx->N, ld, (float)w);
   SGW_HIP(hipGetLastError());
 }
 

@@ -89,6 +89,8 @@ __global__ void k_kb_reduce(const cplx<R> *partial, const int *proj_off, const i
   const int p = blockIdx.y;
   if (v >= nvec) return;
   double sr = 0, si = 0;
+  // unrolled so that several loads are in flight; the sum keeps its order
+#pragma unroll 8
   for (int k = proj_off[p]; k < proj_off[p + 1]; ++k) {
     const cplx<R> c = partial[(int64_t)proj_entries[k] * nvec + v];
     sr += c.x;
@@ -106,6 +108,7 @@ __global__ void k_kb_mix(const cplx<R> *K, const cplx<R> *in, cplx<R> *out, int 
   if (v >= nvec) return;
   double sr = 0, si = 0;
   const cplx<R> *k = K + (int64_t)p * np;
+#pragma unroll 8
   for (int q = 0; q < np; ++q) {
     const cplx<R> a = k[q], b = in[(int64_t)q * nvec + v];
     sr += (double)a.x * b.x - (double)a.y * b.y;
@@ -294,6 +297,7 @@ __global__ __launch_bounds__(NTK) void k_kb_gather_mma(
   constexpr int NC = 2 * NVB, NTL = NC / 16;
   constexpr int EL = 16 / (int)sizeof(T);           // operand elements per lane per group
   constexpr int NG = 128 / Op::GK;                  // K groups of one wave (128 points)
+  constexpr int NS = Op::SPLIT ? NG : 1, NSN = Op::SPLIT ? NTL : 1;
   __shared__ __align__(16) float red[4 * MT * NTL * 256];   // cross-wave sums
   int t;
   int64_t vb;
@@ -303,28 +307,31 @@ __global__ __launch_bounds__(NTK) void k_kb_gather_mma(
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, q = lane >> 4, col = lane & 15;
   const int off = tile_off[t], ne = tile_off[t + 1] - off;
   // B operands of this wave's quarter of K, kept in registers for all entries
-  u32x4 b[NG][NTL];
-  u32x4 blo[Op::SPLIT ? NG : 1][Op::SPLIT ? NTL : 1];
+  auto load_b = [&](int64_t v0, u32x4 (*b)[NTL], u32x4 (*blo)[NSN]) {
 #pragma unroll
-  for (int n = 0; n < NTL; ++n) {
-    const int64_t v = v0 + 8 * n + (col >> 1);
-    const bool ok = v < nvec;
-    const float2 *src = psi + (ok ? v : 0) * ld;
+    for (int n = 0; n < NTL; ++n) {
+      const int64_t v = v0 + 8 * n + (col >> 1);
+      const bool ok = v < nvec;
+      const float2 *src = psi + (ok ? v : 0) * ld;
 #pragma unroll
-    for (int g = 0; g < NG; ++g) {
-      const int p = 128 * w + g * Op::GK + EL * q;  // EL consecutive points along x
-      const float4 *s4 = reinterpret_cast<const float4 *>(src + tile_point(base, p, nx, ny, lx, ly));
-      float e[EL];
+      for (int g = 0; g < NG; ++g) {
+        const int p = 128 * w + g * Op::GK + EL * q;  // EL consecutive points along x
+        const float4 *s4 =
+            reinterpret_cast<const float4 *>(src + tile_point(base, p, nx, ny, lx, ly));
+        float e[EL];
 #pragma unroll
-      for (int h = 0; h < EL / 2; ++h) {
-        const float4 z = ok ? s4[h] : make_float4(0.f, 0.f, 0.f, 0.f);
-        e[2 * h] = (col & 1) ? z.y : z.x;
-        e[2 * h + 1] = (col & 1) ? z.w : z.z;
+        for (int h = 0; h < EL / 2; ++h) {
+          const float4 z = ok ? s4[h] : make_float4(0.f, 0.f, 0.f, 0.f);
+          e[2 * h] = (col & 1) ? z.y : z.x;
+          e[2 * h + 1] = (col & 1) ? z.w : z.z;
+        }
+        if constexpr (Op::SPLIT) Op::pack2(e, b[g][n], blo[g][n]);
+        else b[g][n] = Op::pack(e);
       }
-      if constexpr (Op::SPLIT) Op::pack2(e, b[g][n], blo[g][n]);
-      else b[g][n] = Op::pack(e);
     }
-  }
+  };
+  u32x4 b[NG][NTL], blo[NS][NSN];
+  load_b(v0, b, blo);
   for (int mg = 0; mg < ne; mg += 16 * MT) {
     f32x4 acc[MT][NTL];
 #pragma unroll
@@ -536,15 +543,13 @@ static void launch_gather_variant(int vi, dim3 g, hipStream_t st, const float2 *
                                   int64_t nvec, const int *tb, const int *to,
                                   const typename Op::T *beta, float2 *partial, int nx, int ny,
                                   int lx, int ly, float dV, int ntile, int nvb) {
-  switch (vi) {
-#define SGW_G(I, A, B)                                                                           \
-  case I:                                                                                        \
+  const GatherVariant v = kGather[vi];
+#define SGW_G(A, B)                                                                              \
+  if (v.nvb == A && v.mt == B)                                                                   \
     hipLaunchKernelGGL((k_kb_gather_mma<Op, A, B>), g, dim3(NTK), 0, st, psi, ld, nvec, tb, to, \
-                       beta, partial, nx, ny, lx, ly, dV, ntile, nvb);                           \
-    break;
-    SGW_G(0, 8, 2) SGW_G(1, 8, 4) SGW_G(2, 16, 2) SGW_G(3, 16, 4)
+                       beta, partial, nx, ny, lx, ly, dV, ntile, nvb);
+  SGW_G(8, 2) SGW_G(8, 4) SGW_G(16, 2) SGW_G(16, 4)
 #undef SGW_G
-  }
 }
 
 template <class Op>
@@ -553,17 +558,13 @@ static void launch_scatter_variant(int vi, dim3 g, hipStream_t st, const float2 
                                    const int *ep, const typename Op::T *betaT, float2 *dst,
                                    int64_t ld, float s1, int nx, int ny, int lx, int ly,
                                    int ntile, int nvb) {
-  switch (vi) {
-#define SGW_S(I, A, B)                                                                           \
-  case I:                                                                                        \
+  const ScatterVariant v = kScatter[vi];
+#define SGW_S(A, B)                                                                              \
+  if (v.nvb == A && v.mj == B)                                                                   \
     hipLaunchKernelGGL((k_kb_scatter_mma<Op, A, B>), g, dim3(NTK), 0, st, coef, nvec, tb, to,   \
-                       toT, ep, betaT, dst, ld, s1, nx, ny, lx, ly, ntile, nvb);                 \
-    break;
-    SGW_S(0, 8, 8) SGW_S(1, 16, 8) SGW_S(2, 8, 4) SGW_S(3, 16, 4) SGW_S(4, 8, 2)
-    SGW_S(5, 16, 2)
+                       toT, ep, betaT, dst, ld, s1, nx, ny, lx, ly, ntile, nvb);
+  SGW_S(8, 8) SGW_S(16, 8) SGW_S(8, 4) SGW_S(16, 4) SGW_S(8, 2) SGW_S(16, 2)
 #undef SGW_S
-
-  }
 }
 
 // Operand arrays of the MFMA kernels: beta per entry [entry][512] in the

@@ -34,22 +34,25 @@ struct UnpackArgs {
   const void *filt;        // [nc][N] complex, filtered
   const uint64_t *keys;    // [nr] noise keys (zeta-bar of sample s at s (1+neta))
   const void *phi;         // [N] real
-  void *psi;               // [S][ncopy][neta][N] complex: copy 0 <- eta (nullable)
+  void *psi;               // [S][ncopy][neta] vectors ldp apart: copy 0 <- eta (nullable)
   void *zeta;              // [S][2][N] complex: zeta^+ = zb - F zb, zeta~ = F zb
                            // (nullable)
   void *kick;              // [S][N] complex: phi zb
   void *xsrc;              // [S][neta/2][N] complex: phi eta_2k + i phi eta_2k+1
   int S = 0, neta = 0, ncopy = 2;
+  int64_t ldp = 0;         // psi leading dimension (0: N)
 };
 void launch_unpack(sgw_ctx *ctx, const UnpackArgs &a);
 
 // ---- TDH
-// psi [S][1 + nk][neta][N]; dv, u [nk][S][N]; v [S][N]; rho [1 + nk/2][S][N]
-void launch_tdh_tangent(sgw_ctx *ctx, void *psi, const void *dv, int S, int neta, int nk);
-void launch_tdh_local(sgw_ctx *ctx, void *psi, const void *v, const void *u, int S,
+// psi [S][1 + nk][neta] vectors ld apart; dv, u [nk][S][N]; v [S][N];
+// rho [1 + nk/2][S][N]
+void launch_tdh_tangent(sgw_ctx *ctx, void *psi, int64_t ld, const void *dv, int S, int neta,
+                        int nk);
+void launch_tdh_local(sgw_ctx *ctx, void *psi, int64_t ld, const void *v, const void *u, int S,
                       int neta, int nk, double a);
-void launch_tdh_density(sgw_ctx *ctx, const void *psi, void *rho, int S, int neta, int nk,
-                        double w);
+void launch_tdh_density(sgw_ctx *ctx, const void *psi, int64_t ld, void *rho, int S, int neta,
+                        int nk, double w);
 void launch_bcast_real(sgw_ctx *ctx, const void *src, void *dst, int S);
 
 // ---- sROI
