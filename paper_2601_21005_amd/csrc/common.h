@@ -118,7 +118,7 @@ struct sgw_ctx {
   sgw::DevBuf d_kb_tile_base, d_kb_tile_off, d_kb_entry_proj, d_kb_beta,
       d_kb_proj_off, d_kb_proj_entries, d_kb_ekb;
   sgw::DevBuf d_kb_tile_offT;        // [ntile + 1] per-tile offsets of betaT in entry rows
-  sgw::DevBuf d_kb_betaT;            // per tile [512][entries padded to 32], FP32 or BF16
+  sgw::DevBuf d_kb_betaT;            // per tile [512][entries padded to the K group], FP32 or BF16
   sgw::DevBuf d_kb_beta16;           // [entry][512] BF16 (the BF16 precisions)
   int kb_ntile = 0, kb_nentry = 0;
   int kb_lx = 3, kb_ly = 3;          // tile extent log2 along x and y (512 points)

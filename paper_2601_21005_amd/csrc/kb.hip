@@ -175,7 +175,7 @@ __global__ __launch_bounds__(NTK) void k_kb_scatter(const cplx<R> *coef, int64_t
 // Per tile the gather is the GEMM  D[e][c] = sum_p beta[e][p] Psi[p][c]
 // (M = projector entries, K = 512 points, N = 2 NVB real columns = NVB
 // complex vectors) and the scatter  D[p][c] = sum_e beta[e][p] C'[e][c]
-// (M = 512 points, K = entries padded to 32).  The operands are stored in
+// (M = 512 points, K = entries padded to the K group).  The operands are stored in
 // FP32 (SGW_C64) or in BF16 rounded to nearest even (SGW_C64_BF16KB; with
 // SGW_C64_BF16X2KB the psi / coefficient operand as two BF16 terms); the
 // accumulation is FP32 either way.  A lane feeds 16 contiguous bytes of A and
@@ -387,9 +387,10 @@ __global__ __launch_bounds__(NTK) void k_kb_gather_mma(
 
 // dst_v(r) += s1 sum_e beta_e(r) C'[p(e)][v] on the points r of tile t (s1 real).
 // betaT holds each tile's block transposed, [512 points][nek entries], with the
-// entry count nek padded to 32 (zeros).  A wave owns MJ M tiles of 16 points, so
-// a workgroup covers 64 MJ points and a tile takes 512 / (64 MJ) workgroups per
-// vector block (fewer registers per wave for MJ = 4, more waves per SIMD).
+// entry count nek padded to the K group (16 FP32, 32 BF16; zeros).  A wave
+// owns MJ M tiles of 16 points, so a workgroup covers 64 MJ points and a tile
+// takes 512 / (64 MJ) workgroups per vector block (fewer registers per wave
+// for MJ = 4, more waves per SIMD).
 template <class Op, int NVB, int MJ>
 __global__ __launch_bounds__(NTK) void k_kb_scatter_mma(
     const float2 *coef, int64_t nvec, const int *tile_base, const int *tile_off,
@@ -569,7 +570,8 @@ static void launch_scatter_variant(int vi, dim3 g, hipStream_t st, const float2 
 
 // Operand arrays of the MFMA kernels: beta per entry [entry][512] in the
 // operand type (BF16 only; FP32 uses the working-precision copy) and the
-// transposed per-tile blocks [512][nek], nek = entries rounded up to 32.
+// transposed per-tile blocks [512][nek], nek = entries rounded up to the
+// scatter's K group.
 void kb_upload_operands(sgw_ctx *ctx) {
   const KBHost &kb = ctx->kb;
   auto upload = [](DevBuf &b, const auto *src, size_t n) {
@@ -577,14 +579,15 @@ void kb_upload_operands(sgw_ctx *ctx) {
     SGW_HIP(hipMemcpy(b.p, src, n * sizeof(*src), hipMemcpyHostToDevice));
   };
   const int nt = (int)kb.tile_base.size();
+  const bool bf = ctx->prec == SGW_C64_BF16KB || ctx->prec == SGW_C64_BF16X2KB;
+  const int kg = bf ? OpBF16::GK : OpF32::GK;      // the scatter's K group
   std::vector<int> offT(nt + 1, 0);
   for (int t = 0; t < nt; ++t) {
     const int ne = kb.tile_off[t + 1] - kb.tile_off[t];
-    offT[t + 1] = offT[t] + ((ne + 31) & ~31);
+    offT[t + 1] = offT[t] + (ne + kg - 1) / kg * kg;
   }
   upload(ctx->d_kb_tile_offT, offT.data(), offT.size());
   const size_t nT = (size_t)offT[nt] * KB_TP;
-  const bool bf = ctx->prec == SGW_C64_BF16KB || ctx->prec == SGW_C64_BF16X2KB;
   auto fill_T = [&](auto *out, auto conv) {
     for (int t = 0; t < nt; ++t) {
       const int e0 = kb.tile_off[t], ne = kb.tile_off[t + 1] - e0, nek = offT[t + 1] - offT[t];
