@@ -185,6 +185,9 @@ struct sgw_ctx {
       tuned[key] = cached;
       return cached;
     }
+    // trials run alone on the device: work of other streams (the context's
+    // second stream, other contexts) would otherwise skew their times
+    (void)hipDeviceSynchronize();
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
       throw sgw::Error{SGW_EHIP, "hipEventCreate failed"};
