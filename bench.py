@@ -35,6 +35,7 @@ HA_EV = 27.211386245988
 METRIC = ("GPU-s per QP energy at +/-0.03 eV (plain vs chosen); "
           "Hpsi Gpt*vec/s vs HBM roofline")
 HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0      # dense BF16 MFMA of one MI355X
 # algorithmic bytes per (grid point x complex vector) of the dominant kernel,
 # the inverse xy-plane pass carrying the Chebyshev update: the real FP32
 # filter term reads v_n, v_{n-1}, acc and writes v_{n+1}, acc (20 B per real
@@ -192,6 +193,31 @@ def states_form(args, ctx, phi2, p, homo, lumo, gam, t_sample):
             "samples": n, **out}
 
 
+def features_roofline(ctx, phis, s, nsamp=262144, reps=3):
+    """The control variate's feature GEMM on MFMA (BF16 operands, FP32
+    accumulation): 64 states x N_g points x nsamp white-noise vectors whose
+    signs the kernel draws in registers; 2 flop per multiply-add, HIP events on
+    the context's stream (the default stream, torch's current one here)."""
+    import torch
+    from paper_2601_21005_amd import sgw
+    k = 64
+    i0 = max(0, s.n_occ - k // 2)
+    phi = phis[i0:i0 + k].real.float().contiguous()
+    out = torch.empty((nsamp, k), dtype=torch.float32, device="cuda")
+    sgw.cv_features(ctx, phi, 7, 0, nsamp, out)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for r in range(reps):
+        sgw.cv_features(ctx, phi, 7, (r + 1) * nsamp, nsamp, out)
+    e1.record()
+    e1.synchronize()
+    t = e0.elapsed_time(e1) * 1e-3 / reps
+    tflops = 2.0 * k * s.grid.N * nsamp / t / 1e12
+    return {"bound": "mfma", "kernel": "k_features (BF16 16x16x32)", "achieved": tflops,
+            "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": tflops / BF16_PEAK_TFLOPS,
+            "traffic": None, "samples": nsamp, "states": k, "avg_launch_us": t * 1e6}
+
+
 def cv_form(args, ctx, s, phis, ev, phi, p, homo, eg, gam, t_sample, sigma1, Z):
     """Control variate: args.cv new samples split 3/8 train, 1/8 validation
     (early stopping), 1/4 fit of c (A), 1/4 evaluation (B); E[g] over
@@ -328,6 +354,8 @@ def main():
         ctx.apply_H(xh, yh)
     torch.cuda.synchronize()
     hpsi_rate = nv * reps * s.grid.N / (time.perf_counter() - t1)
+    del xh, yh
+    feat = features_roofline(ctx, phis, s)
 
     forms = {"plain": {"gpu_s_per_qp": gpu_s_per_qp, "gpu_s_per_sample": t_sample}}
     if not args.no_bf16:
@@ -382,6 +410,7 @@ def main():
                      "traffic_bytes_per_ptvec": CHEB_MEASURED_BYTES,
                      "launches": k_launch,
                      "avg_launch_us": 1e3 * k_ms / k_launch if k_launch else None},
+        "roofline_features": feat,
     }
     if not args.no_cpu_baseline:
         tcpu, parts, cores, sample = cpu_baseline(s, phi, p, args.cpu_terms, ncoef)
