@@ -62,7 +62,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-terms", type=int, default=6,
                     help="filter terms timed for the CPU baseline sample")
-    ap.add_argument("--no-bf16", action="store_true", help="skip the BF16-KB / graphs form")
+    ap.add_argument("--no-bf16", action="store_true",
+                    help="skip the graph-replay forms (FP32, BF16 and split BF16 KB)")
     ap.add_argument("--no-states", action="store_true",
                     help="skip the HOMO + LUMO shared-pass form")
     ap.add_argument("--cv", type=int, default=0,
@@ -128,10 +129,10 @@ def cpu_baseline(system, phi, p, n_terms, ncoef):
     return total, dict(filter=t_filter, tdh=t_tdh, zeta=t_zeta), workers, sample
 
 
-def bf16_form(args, s, phi, p, sigma1, sig_plain, homo, gam, precision):
-    """The same samples with BF16 projector GEMMs (plain or split) and
-    HIP-graph replay on a stream of its own: time per sample and the largest
-    Sigma_c(t) difference from the plain form."""
+def graph_form(args, s, phi, p, sigma1, sig_plain, homo, gam, precision):
+    """The same samples with HIP-graph replay on a stream of its own, in the
+    given precision (FP32, BF16 or split BF16 projector GEMMs): time per
+    sample and the largest Sigma_c(t) difference from the plain form."""
     import numpy as np
     import torch
     from paper_2601_21005_amd import sgw
@@ -359,9 +360,11 @@ def main():
 
     forms = {"plain": {"gpu_s_per_qp": gpu_s_per_qp, "gpu_s_per_sample": t_sample}}
     if not args.no_bf16:
-        forms["bf16kb_graphs"] = bf16_form(args, s, phi, p, sigma1, sig, homo, gam,
+        forms["c64_graphs"] = graph_form(args, s, phi, p, sigma1, sig, homo, gam,
+                                         sgw.SGW_C64)
+        forms["bf16kb_graphs"] = graph_form(args, s, phi, p, sigma1, sig, homo, gam,
                                            sgw.SGW_C64_BF16KB)
-        forms["bf16x2kb_graphs"] = bf16_form(args, s, phi, p, sigma1, sig, homo, gam,
+        forms["bf16x2kb_graphs"] = graph_form(args, s, phi, p, sigma1, sig, homo, gam,
                                              sgw.SGW_C64_BF16X2KB)
     if not args.no_states:
         phi2 = np.stack([phi, phis[s.n_occ].cpu().numpy()])
