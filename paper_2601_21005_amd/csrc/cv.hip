@@ -108,14 +108,20 @@ __global__ void k_phi_bf16(const float *phi, int64_t ld, int K, int64_t N, uint1
 // x[s][k] = dV (sum_r phi_k(r) sign_s(r))^2 = |<phi_k|zeta_s>|^2 for zeta_s =
 // sign / sqrt(dV).  Workgroup: 4 waves x NS tiles of 16 samples; every wave
 // runs the whole grid (K = N points, groups of 32) for its samples with the
-// 4 x 16 state rows as A (from memory) and the signs of its samples as B,
-// made in registers from the counter-based generator: the 8 signs a lane
-// feeds for points r0..r0+7 are 8 bits of word(r0 / 64), bit 0 -> +1.
+// 4 x 16 state rows as A and the signs of its samples as B, made in
+// registers from the counter-based generator: the 8 signs a lane feeds for
+// points r0..r0+7 are 8 bits of word(r0 / 64), bit 0 -> +1.  The A rows of
+// each 64-point chunk are staged once per workgroup in LDS (two buffers: the
+// next chunk is loaded while the current one is multiplied), so the four
+// waves share one read of phi from the cache.
 template <int NS>
 __global__ __launch_bounds__(NT) void k_features(const uint16_t *phi16, int64_t N, int K,
                                                  uint64_t seed, int64_t s0, int64_t nsamp,
                                                  float dV, float *x) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, q = lane >> 4, col = lane & 15;
+  constexpr int PA = 72;                           // LDS row pitch (BF16): 64 points + 8
+  __shared__ __align__(16) uint16_t sa[2][64 * PA];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6, q = lane >> 4, col = lane & 15;
   const int64_t sbase = s0 + ((int64_t)blockIdx.x * 4 + w) * (16 * NS);
   uint64_t key[NS];
 #pragma unroll
@@ -126,18 +132,35 @@ __global__ __launch_bounds__(NT) void k_features(const uint16_t *phi16, int64_t 
   for (int m = 0; m < 4; ++m)
 #pragma unroll
     for (int t = 0; t < NS; ++t) acc[m][t] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const uint16_t *arow = phi16 + (int64_t)col * N + 8 * q;
+  // chunk staging: 64 rows x 64 points = 512 pieces of 16 B, two per thread
+  const int row0 = tid >> 3, seg = tid & 7;
+  auto fetch = [&](int64_t r64, u32x4 *g) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+      g[i] = *reinterpret_cast<const u32x4 *>(phi16 + (int64_t)(row0 + 32 * i) * N + r64 + 8 * seg);
+  };
+  auto stage = [&](int buf, const u32x4 *g) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+      *reinterpret_cast<u32x4 *>(&sa[buf][(row0 + 32 * i) * PA + 8 * seg]) = g[i];
+  };
+  u32x4 gnext[2];
+  fetch(0, gnext);
+  stage(0, gnext);
+  __syncthreads();
+  int buf = 0;
   for (int64_t r64 = 0; r64 < N; r64 += 64) {
+    const bool more = r64 + 64 < N;
+    if (more) fetch(r64 + 64, gnext);
     uint64_t word[NS];
 #pragma unroll
     for (int t = 0; t < NS; ++t) word[t] = sm64(key[t] + (uint64_t)(r64 >> 6));
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
-      const int64_t k0 = r64 + 32 * half;
       u32x4 a[4];
 #pragma unroll
       for (int m = 0; m < 4; ++m)
-        a[m] = *reinterpret_cast<const u32x4 *>(arow + (int64_t)(16 * m) * N + k0);
+        a[m] = *reinterpret_cast<const u32x4 *>(&sa[buf][(16 * m + col) * PA + 32 * half + 8 * q]);
       const int sh = 32 * half + 8 * q;
 #pragma unroll
       for (int t = 0; t < NS; ++t) {
@@ -150,6 +173,9 @@ __global__ __launch_bounds__(NT) void k_features(const uint16_t *phi16, int64_t 
         for (int m = 0; m < 4; ++m) mma(acc[m][t], a[m], b);
       }
     }
+    if (more) stage(buf ^ 1, gnext);
+    __syncthreads();
+    buf ^= 1;
   }
 #pragma unroll
   for (int t = 0; t < NS; ++t) {
