@@ -1,0 +1,65 @@
+"""The 64^3 cluster at the launch shapes the benchmark times: the filter on
+260 complex vectors (8 samples x 65 real orbitals, two per complex vector)
+and the TDH on 8 samples x 128 orbital copies (1024 vectors).  The oracle
+cannot follow 1338 filter terms or 400 TDH steps on these batches within a
+test, so these tests check properties that hold at any size: a vector's or a
+sample's result does not depend on the batch it was launched in, and the
+filtered vectors keep the norm bound of a filter with values in [0, 1].  The
+oracle parity of the same kernels at small sizes is in test_gpu_sigma.py,
+test_gpu_cheb.py and test_gpu_tdh.py."""
+import numpy as np
+import pytest
+import torch
+
+from conftest import make_ctx, rel_err
+from paper_2601_21005_amd import sgw
+
+pytestmark = pytest.mark.gpu
+
+
+def test_filter_batch_of_260_matches_single_vectors(si35):
+    """Each complex vector is filtered on its own (the KB and FFT kernels see
+    a vector block of the batch only): the first and the last (ragged) vector
+    of a 260-vector launch are bitwise those of 1-vector launches."""
+    s, _ = si35
+    ctx = make_ctx(s, sgw.SGW_C64, max_nvec=512)
+    lo, hi = ctx.bounds()
+    coef = sgw.sgw_fermi_coefficients(-4.65, 2.0, lo, hi, 40)
+    g = torch.Generator(device="cuda").manual_seed(5)
+    x = (torch.randn((260, s.grid.N), generator=g, device="cuda", dtype=torch.float32)
+         + 1j * torch.randn((260, s.grid.N), generator=g, device="cuda", dtype=torch.float32))
+    x = x.to(torch.complex64) / np.sqrt(s.grid.h ** 3)
+    singles = [x[i:i + 1].clone() for i in (0, 259)]
+    n_in = torch.linalg.vector_norm(x, dim=1)
+    ctx.fermi_filter(x, coef, lo, hi)
+    for xi in singles:
+        ctx.fermi_filter(xi, coef, lo, hi)
+    torch.cuda.synchronize()
+    assert torch.equal(x[0:1], singles[0]) and torch.equal(x[259:260], singles[1])
+    # the filter's values lie in [0, 1] up to the expansion's tail: no vector grows
+    n_out = torch.linalg.vector_norm(x, dim=1)
+    assert bool(torch.all(n_out <= 1.01 * n_in)) and bool(torch.all(n_out > 0))
+    ctx.close()
+
+
+def test_sigma_batch_of_8_matches_single_samples(si35):
+    """sgw_sigma_estimate with the bench's batch (8 samples, N_eta = 64: a
+    260-vector filter and a 1024-vector TDH) against one sample per call:
+    samples 0 and 7 agree to FP32 rounding (a sample's noise vectors share
+    complex filter vectors with its neighbours in the batch, so the bits of
+    the filter differ, not the arithmetic)."""
+    s, H = si35
+    ctx = make_ctx(s, sgw.SGW_C64, max_nvec=512)
+    lo, hi = ctx.bounds()
+    rs = np.random.default_rng(8)
+    phi = rs.standard_normal(s.grid.N)
+    phi /= np.sqrt(s.grid.h ** 3 * np.sum(phi * phi))
+    kw = dict(seed=1002, n_eta=64, n_tau=4, dt=0.05, m_sub=1, mu=-4.65, beta=2.0, ncoef=60,
+              emin=lo, emax=hi, n_xi=10000, f_g=0.003, mode=0)
+    sig8, x8, _ = ctx.sigma_estimate(phi, n_zeta=8, first_sample=0, **kw)
+    for i in (0, 7):
+        sig1, x1, _ = ctx.sigma_estimate(phi, n_zeta=1, first_sample=i, **kw)
+        assert rel_err(sig8[i], sig1[0]) < 1e-4, i
+        assert rel_err(x8[i:i + 1], x1) < 1e-5, i
+    assert np.all(np.isfinite(sig8)) and np.all(np.isfinite(x8))
+    ctx.close()
