@@ -28,6 +28,14 @@ __device__ __forceinline__ int64_t tile_point(int base, int p, int nx, int ny, i
   return (int64_t)base + x + (int64_t)nx * (y + (int64_t)ny * z);
 }
 
+// the same with the x extent 2^LX known at compile time (y extent 8), in
+// 32-bit arithmetic (grids below 2^31 points)
+template <int LX>
+__device__ __forceinline__ int tile_point_c(int base, int p, int nx, int ny) {
+  const int x = p & ((1 << LX) - 1), y = (p >> LX) & 7, z = p >> (LX + 3);
+  return base + x + nx * (y + ny * z);
+}
+
 template <typename T> __device__ __forceinline__ T wsum(T v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
   return v;
@@ -287,12 +295,15 @@ template <class T> __device__ __forceinline__ u32x4 ld16(const T *p) {
 // (consecutive x, so EL consecutive complex values in memory) of the real
 // (col even) or imaginary (col odd) part of vector v0 + 8 n + col / 2: the
 // lane reads them straight from memory (lanes col and col ^ 1 read the same
-// bytes in the same instruction) -- no staging in LDS.
-template <class Op, int NVB, int MT>
+// bytes in the same instruction) -- no staging in LDS.  The tile's x extent
+// is 2^LX (y 8).  Lanes of vectors past nvec read the last vector and entry
+// rows past ne the last row: both only feed outputs that are never written,
+// so the loads need no branch.
+template <class Op, int NVB, int MT, int LX>
 __global__ __launch_bounds__(NTK) void k_kb_gather_mma(
     const float2 *psi, int64_t ld, int64_t nvec, const int *tile_base, const int *tile_off,
-    const typename Op::T *beta, float2 *partial, int nx, int ny, int lx, int ly, float dV,
-    int ntile, int nvb) {
+    const typename Op::T *beta, float2 *partial, int nx, int ny, float dV, int ntile,
+    int nvb) {
   using T = typename Op::T;
   constexpr int NC = 2 * NVB, NTL = NC / 16;
   constexpr int EL = 16 / (int)sizeof(T);           // operand elements per lane per group
@@ -310,18 +321,16 @@ __global__ __launch_bounds__(NTK) void k_kb_gather_mma(
   auto load_b = [&](int64_t v0, u32x4 (*b)[NTL], u32x4 (*blo)[NSN]) {
 #pragma unroll
     for (int n = 0; n < NTL; ++n) {
-      const int64_t v = v0 + 8 * n + (col >> 1);
-      const bool ok = v < nvec;
-      const float2 *src = psi + (ok ? v : 0) * ld;
+      const int64_t v = min(v0 + 8 * n + (col >> 1), nvec - 1);
+      const float2 *src = psi + v * ld;
 #pragma unroll
       for (int g = 0; g < NG; ++g) {
         const int p = 128 * w + g * Op::GK + EL * q;  // EL consecutive points along x
-        const float4 *s4 =
-            reinterpret_cast<const float4 *>(src + tile_point(base, p, nx, ny, lx, ly));
+        const float4 *s4 = reinterpret_cast<const float4 *>(src + tile_point_c<LX>(base, p, nx, ny));
         float e[EL];
 #pragma unroll
         for (int h = 0; h < EL / 2; ++h) {
-          const float4 z = ok ? s4[h] : make_float4(0.f, 0.f, 0.f, 0.f);
+          const float4 z = s4[h];
           e[2 * h] = (col & 1) ? z.y : z.x;
           e[2 * h + 1] = (col & 1) ? z.w : z.z;
         }
@@ -343,9 +352,8 @@ __global__ __launch_bounds__(NTK) void k_kb_gather_mma(
       u32x4 a[MT];
 #pragma unroll
       for (int j = 0; j < MT; ++j) {
-        const int e = mg + 16 * j + col;            // A row = lane % 16
-        a[j] = u32x4{0u, 0u, 0u, 0u};
-        if (e < ne) a[j] = ld16(beta + (int64_t)(off + e) * KB_TP + 128 * w + g * Op::GK + EL * q);
+        const int e = min(mg + 16 * j + col, ne - 1);   // A row = lane % 16
+        a[j] = ld16(beta + (int64_t)(off + e) * KB_TP + 128 * w + g * Op::GK + EL * q);
       }
 #pragma unroll
       for (int j = 0; j < MT; ++j)
@@ -391,11 +399,11 @@ __global__ __launch_bounds__(NTK) void k_kb_gather_mma(
 // owns MJ M tiles of 16 points, so a workgroup covers 64 MJ points and a tile
 // takes 512 / (64 MJ) workgroups per vector block (fewer registers per wave
 // for MJ = 4, more waves per SIMD).
-template <class Op, int NVB, int MJ>
+template <class Op, int NVB, int MJ, int LX>
 __global__ __launch_bounds__(NTK) void k_kb_scatter_mma(
     const float2 *coef, int64_t nvec, const int *tile_base, const int *tile_off,
     const int *tile_offT, const int *entry_proj, const typename Op::T *betaT, float2 *dst,
-    int64_t ld, float s1, int nx, int ny, int lx, int ly, int ntile, int nvb) {
+    int64_t ld, float s1, int nx, int ny, int ntile, int nvb) {
   using T = typename Op::T;
   constexpr int NC = 2 * NVB, NTL = NC / 16;
   constexpr int EL = 16 / (int)sizeof(T);
@@ -440,18 +448,21 @@ __global__ __launch_bounds__(NTK) void k_kb_scatter_mma(
   // imaginary columns of vector 8 n + col / 2 at the points 4 q + r of each
   // M tile; they will swap halves so that each lane owns two complete values
   // at two neighbouring points (even lane: r = 0, 1; odd lane: r = 2, 3)
+  // (lanes of vectors past nvec read the last vector and store nothing)
   const int odd = col & 1;
   const int vcol = col >> 1;
-  float2 *ptr[MJ][NTL];
+  int rp[MJ];
 #pragma unroll
   for (int j = 0; j < MJ; ++j)
+    rp[j] = tile_point_c<LX>(base, p0 + 16 * (MJ * w + j) + 4 * q + 2 * odd, nx, ny);
+  float2 *vrow[NTL];
+  bool vok[NTL];
 #pragma unroll
-    for (int n = 0; n < NTL; ++n) {
-      const int vl = 8 * n + vcol;
-      const int pb = p0 + 16 * (MJ * w + j) + 4 * q + 2 * odd;
-      ptr[j][n] = v0 + vl < nvec ? dst + (v0 + vl) * ld + tile_point(base, pb, nx, ny, lx, ly)
-                                 : nullptr;
-    }
+  for (int n = 0; n < NTL; ++n) {
+    const int64_t v = v0 + 8 * n + vcol;
+    vok[n] = v < nvec;
+    vrow[n] = dst + min(v, nvec - 1) * ld;
+  }
   // with one N tile the old destination values are loaded before the K loop,
   // so their memory latency overlaps the products
   constexpr bool PREFETCH = NTL == 1;
@@ -460,11 +471,10 @@ __global__ __launch_bounds__(NTK) void k_kb_scatter_mma(
 #pragma unroll
     for (int j = 0; j < MJ; ++j)
 #pragma unroll
-      for (int n = 0; n < NTL; ++n)
-        if (ptr[j][n]) {
-          o[j][n][0] = ptr[j][n][0];
-          o[j][n][1] = ptr[j][n][1];
-        }
+      for (int n = 0; n < NTL; ++n) {
+        o[j][n][0] = vrow[n][rp[j]];
+        o[j][n][1] = vrow[n][rp[j] + 1];
+      }
   }
   // wave w owns the M tiles (16 points each) MJ w .. MJ w + MJ - 1 from p0
   f32x4 acc[MJ][NTL];
@@ -516,19 +526,19 @@ __global__ __launch_bounds__(NTK) void k_kb_scatter_mma(
 #pragma unroll
     for (int j = 0; j < MJ; ++j)
 #pragma unroll
-      for (int n = 0; n < NTL; ++n)
-        if (ptr[j][n]) {
-          o[j][n][0] = ptr[j][n][0];
-          o[j][n][1] = ptr[j][n][1];
-        }
+      for (int n = 0; n < NTL; ++n) {
+        o[j][n][0] = vrow[n][rp[j]];
+        o[j][n][1] = vrow[n][rp[j] + 1];
+      }
   }
 #pragma unroll
   for (int j = 0; j < MJ; ++j)
 #pragma unroll
     for (int n = 0; n < NTL; ++n)
-      if (ptr[j][n]) {
-        ptr[j][n][0] = make_float2(o[j][n][0].x + s1 * c[j][n][0].x, o[j][n][0].y + s1 * c[j][n][0].y);
-        ptr[j][n][1] = make_float2(o[j][n][1].x + s1 * c[j][n][1].x, o[j][n][1].y + s1 * c[j][n][1].y);
+      if (vok[n]) {
+        float2 *d = vrow[n] + rp[j];
+        d[0] = make_float2(o[j][n][0].x + s1 * c[j][n][0].x, o[j][n][0].y + s1 * c[j][n][0].y);
+        d[1] = make_float2(o[j][n][1].x + s1 * c[j][n][1].x, o[j][n][1].y + s1 * c[j][n][1].y);
       }
 }
 
@@ -543,13 +553,14 @@ template <class Op>
 static void launch_gather_variant(int vi, dim3 g, hipStream_t st, const float2 *psi, int64_t ld,
                                   int64_t nvec, const int *tb, const int *to,
                                   const typename Op::T *beta, float2 *partial, int nx, int ny,
-                                  int lx, int ly, float dV, int ntile, int nvb) {
+                                  int lx, float dV, int ntile, int nvb) {
   const GatherVariant v = kGather[vi];
-#define SGW_G(A, B)                                                                              \
-  if (v.nvb == A && v.mt == B)                                                                   \
-    hipLaunchKernelGGL((k_kb_gather_mma<Op, A, B>), g, dim3(NTK), 0, st, psi, ld, nvec, tb, to, \
-                       beta, partial, nx, ny, lx, ly, dV, ntile, nvb);
-  SGW_G(8, 2) SGW_G(8, 4) SGW_G(16, 2) SGW_G(16, 4)
+#define SGW_G(A, B, X)                                                                           \
+  if (v.nvb == A && v.mt == B && lx == X)                                                        \
+    hipLaunchKernelGGL((k_kb_gather_mma<Op, A, B, X>), g, dim3(NTK), 0, st, psi, ld, nvec, tb,  \
+                       to, beta, partial, nx, ny, dV, ntile, nvb);
+  SGW_G(8, 2, 4) SGW_G(8, 4, 4) SGW_G(16, 2, 4) SGW_G(16, 4, 4)
+  SGW_G(8, 2, 3) SGW_G(8, 4, 3) SGW_G(16, 2, 3) SGW_G(16, 4, 3)
 #undef SGW_G
 }
 
@@ -557,14 +568,15 @@ template <class Op>
 static void launch_scatter_variant(int vi, dim3 g, hipStream_t st, const float2 *coef,
                                    int64_t nvec, const int *tb, const int *to, const int *toT,
                                    const int *ep, const typename Op::T *betaT, float2 *dst,
-                                   int64_t ld, float s1, int nx, int ny, int lx, int ly,
-                                   int ntile, int nvb) {
+                                   int64_t ld, float s1, int nx, int ny, int lx, int ntile,
+                                   int nvb) {
   const ScatterVariant v = kScatter[vi];
-#define SGW_S(A, B)                                                                              \
-  if (v.nvb == A && v.mj == B)                                                                   \
-    hipLaunchKernelGGL((k_kb_scatter_mma<Op, A, B>), g, dim3(NTK), 0, st, coef, nvec, tb, to,   \
-                       toT, ep, betaT, dst, ld, s1, nx, ny, lx, ly, ntile, nvb);
-  SGW_S(8, 8) SGW_S(16, 8) SGW_S(8, 4) SGW_S(16, 4) SGW_S(8, 2) SGW_S(16, 2)
+#define SGW_S(A, B, X)                                                                           \
+  if (v.nvb == A && v.mj == B && lx == X)                                                        \
+    hipLaunchKernelGGL((k_kb_scatter_mma<Op, A, B, X>), g, dim3(NTK), 0, st, coef, nvec, tb,    \
+                       to, toT, ep, betaT, dst, ld, s1, nx, ny, ntile, nvb);
+  SGW_S(8, 8, 4) SGW_S(16, 8, 4) SGW_S(8, 4, 4) SGW_S(16, 4, 4) SGW_S(8, 2, 4) SGW_S(16, 2, 4)
+  SGW_S(8, 8, 3) SGW_S(16, 8, 3) SGW_S(8, 4, 3) SGW_S(16, 4, 3) SGW_S(8, 2, 3) SGW_S(16, 2, 3)
 #undef SGW_S
 }
 
@@ -622,6 +634,8 @@ static void gather_t(sgw_ctx *ctx, const void *psi, int64_t nvec, int64_t ld, vo
   if constexpr (sizeof(R) == 4) {
     SGW_REQUIRE(ld % 2 == 0, SGW_EUNSUPPORTED,
                 "projectors in complex FP32 need an even leading dimension");
+    SGW_REQUIRE(ctx->kb_ly == 3 && (ctx->kb_lx == 3 || ctx->kb_lx == 4), SGW_EUNSUPPORTED,
+                "KB tile shape not built");
     auto go = [&](auto op, const char *name, const auto *beta) {
       using Op = decltype(op);
       auto run = [&](int vi) {
@@ -630,7 +644,7 @@ static void gather_t(sgw_ctx *ctx, const void *psi, int64_t nvec, int64_t ld, vo
                                   static_cast<const float2 *>(psi), ld, nvec,
                                   ctx->d_kb_tile_base.as<int>(), ctx->d_kb_tile_off.as<int>(),
                                   beta, reinterpret_cast<float2 *>(partial), ctx->nx, ctx->ny,
-                                  ctx->kb_lx, ctx->kb_ly, (float)ctx->dV, ctx->kb_ntile,
+                                  ctx->kb_lx, (float)ctx->dV, ctx->kb_ntile,
                                   (int)nvb);
       };
       run(ctx->tune(name, nvec, NGATHER, run));   // the gather overwrites: trials are harmless
@@ -689,6 +703,8 @@ static void scatter_t(sgw_ctx *ctx, const void *coef, int64_t nvec, void *dst, i
   if constexpr (sizeof(R) == 4) {
     SGW_REQUIRE(dst2 == nullptr && s1im == 0.0, SGW_EUNSUPPORTED,
                 "KB scatter (FP32): complex scale or second output not built");
+    SGW_REQUIRE(ctx->kb_ly == 3 && (ctx->kb_lx == 3 || ctx->kb_lx == 4), SGW_EUNSUPPORTED,
+                "KB tile shape not built");
     auto go = [&](auto op, const char *name, const auto *betaT) {
       using Op = decltype(op);
       auto launch = [&](int vi, float s) {
@@ -700,7 +716,7 @@ static void scatter_t(sgw_ctx *ctx, const void *coef, int64_t nvec, void *dst, i
                                    ctx->d_kb_tile_base.as<int>(), ctx->d_kb_tile_off.as<int>(),
                                    ctx->d_kb_tile_offT.as<int>(), ctx->d_kb_entry_proj.as<int>(),
                                    betaT, static_cast<float2 *>(dst), ld, s, ctx->nx, ctx->ny,
-                                   ctx->kb_lx, ctx->kb_ly, ctx->kb_ntile, (int)nvb);
+                                   ctx->kb_lx, ctx->kb_ntile, (int)nvb);
       };
       // trials add 0 * (B C) to dst, which leaves it unchanged
       const int vi = ctx->tune(name, nvec, NSCATTER, [&](int i) { launch(i, 0.0f); });
