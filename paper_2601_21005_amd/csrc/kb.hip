@@ -444,25 +444,27 @@ __global__ __launch_bounds__(NTK) void k_kb_scatter_mma(
     }
   }
   __syncthreads();
-  // destinations of this lane: lanes col and col ^ 1 hold the real and
-  // imaginary columns of vector 8 n + col / 2 at the points 4 q + r of each
-  // M tile; they will swap halves so that each lane owns two complete values
-  // at two neighbouring points (even lane: r = 0, 1; odd lane: r = 2, 3)
-  // (lanes of vectors past nvec read the last vector and store nothing)
-  const int odd = col & 1;
-  const int vcol = col >> 1;
+  // The products are taken transposed, D'[column][point] = sum_e C'[e][column]
+  // beta_e(point) (C' from LDS as the A operand, betaT as B): lane l then
+  // holds D'[4 (l / 16) + r][l % 16], i.e. the real and imaginary parts of
+  // vectors 8 n + 2 (l / 16) (r = 0, 1) and + 1 (r = 2, 3) at point l % 16 of
+  // the M tile: two complete complex values, stored without a lane exchange.
+  // Lanes of vectors past nvec read the last vector and store nothing.
+  const int cg = q;                                 // column group: vectors 2 cg, 2 cg + 1
   int rp[MJ];
 #pragma unroll
   for (int j = 0; j < MJ; ++j)
-    rp[j] = tile_point_c<LX>(base, p0 + 16 * (MJ * w + j) + 4 * q + 2 * odd, nx, ny);
-  float2 *vrow[NTL];
-  bool vok[NTL];
+    rp[j] = tile_point_c<LX>(base, p0 + 16 * (MJ * w + j) + col, nx, ny);
+  float2 *vrow[NTL][2];
+  bool vok[NTL][2];
 #pragma unroll
-  for (int n = 0; n < NTL; ++n) {
-    const int64_t v = v0 + 8 * n + vcol;
-    vok[n] = v < nvec;
-    vrow[n] = dst + min(v, nvec - 1) * ld;
-  }
+  for (int n = 0; n < NTL; ++n)
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int64_t v = v0 + 8 * n + 2 * cg + u;
+      vok[n][u] = v < nvec;
+      vrow[n][u] = dst + min(v, nvec - 1) * ld;
+    }
   // with one N tile the old destination values are loaded before the K loop,
   // so their memory latency overlaps the products
   constexpr bool PREFETCH = NTL == 1;
@@ -472,8 +474,8 @@ __global__ __launch_bounds__(NTK) void k_kb_scatter_mma(
     for (int j = 0; j < MJ; ++j)
 #pragma unroll
       for (int n = 0; n < NTL; ++n) {
-        o[j][n][0] = vrow[n][rp[j]];
-        o[j][n][1] = vrow[n][rp[j] + 1];
+        o[j][n][0] = vrow[n][0][rp[j]];
+        o[j][n][1] = vrow[n][1][rp[j]];
       }
   }
   // wave w owns the M tiles (16 points each) MJ w .. MJ w + MJ - 1 from p0
@@ -484,7 +486,7 @@ __global__ __launch_bounds__(NTK) void k_kb_scatter_mma(
     for (int n = 0; n < NTL; ++n) acc[j][n] = f32x4{0.f, 0.f, 0.f, 0.f};
   const T *bt =
       betaT + (int64_t)offT * KB_TP + (int64_t)(p0 + 16 * MJ * w + col) * nek + EL * q;
-  constexpr int NS = Op::SPLIT ? 2 : 1;            // B terms (hi, lo)
+  constexpr int NS = Op::SPLIT ? 2 : 1;            // C' terms (hi, lo)
   u32x4 a_cur[MJ], a_nxt[MJ], b_cur[NS][NTL], b_nxt[NS][NTL];
   auto load_group = [&](int k0, u32x4 *a, u32x4 (*b)[NTL]) {
 #pragma unroll
@@ -503,7 +505,7 @@ __global__ __launch_bounds__(NTK) void k_kb_scatter_mma(
 #pragma unroll
       for (int n = 0; n < NTL; ++n)
 #pragma unroll
-        for (int h = 0; h < NS; ++h) Op::mma(acc[j][n], a_cur[j], b_cur[h][n]);
+        for (int h = 0; h < NS; ++h) Op::mma(acc[j][n], b_cur[h][n], a_cur[j]);
 #pragma unroll
     for (int j = 0; j < MJ; ++j) a_cur[j] = a_nxt[j];
 #pragma unroll
@@ -511,35 +513,25 @@ __global__ __launch_bounds__(NTK) void k_kb_scatter_mma(
 #pragma unroll
       for (int n = 0; n < NTL; ++n) b_cur[h][n] = b_nxt[h][n];
   }
-  float2 c[MJ][NTL][2];
-#pragma unroll
-  for (int j = 0; j < MJ; ++j)
-#pragma unroll
-    for (int n = 0; n < NTL; ++n) {
-      const f32x4 d = acc[j][n];
-      const float x0 = __shfl_xor(odd ? d[0] : d[2], 1, 64);
-      const float x1 = __shfl_xor(odd ? d[1] : d[3], 1, 64);
-      c[j][n][0] = odd ? make_float2(x0, d[2]) : make_float2(d[0], x0);
-      c[j][n][1] = odd ? make_float2(x1, d[3]) : make_float2(d[1], x1);
-    }
   if constexpr (!PREFETCH) {
 #pragma unroll
     for (int j = 0; j < MJ; ++j)
 #pragma unroll
       for (int n = 0; n < NTL; ++n) {
-        o[j][n][0] = vrow[n][rp[j]];
-        o[j][n][1] = vrow[n][rp[j] + 1];
+        o[j][n][0] = vrow[n][0][rp[j]];
+        o[j][n][1] = vrow[n][1][rp[j]];
       }
   }
 #pragma unroll
   for (int j = 0; j < MJ; ++j)
 #pragma unroll
-    for (int n = 0; n < NTL; ++n)
-      if (vok[n]) {
-        float2 *d = vrow[n] + rp[j];
-        d[0] = make_float2(o[j][n][0].x + s1 * c[j][n][0].x, o[j][n][0].y + s1 * c[j][n][0].y);
-        d[1] = make_float2(o[j][n][1].x + s1 * c[j][n][1].x, o[j][n][1].y + s1 * c[j][n][1].y);
-      }
+    for (int n = 0; n < NTL; ++n) {
+      const f32x4 d = acc[j][n];
+      if (vok[n][0])
+        vrow[n][0][rp[j]] = make_float2(o[j][n][0].x + s1 * d[0], o[j][n][0].y + s1 * d[1]);
+      if (vok[n][1])
+        vrow[n][1][rp[j]] = make_float2(o[j][n][1].x + s1 * d[2], o[j][n][1].y + s1 * d[3]);
+    }
 }
 
 // variants (autotuned per context, operand type and batch width)
