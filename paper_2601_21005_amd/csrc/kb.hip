@@ -328,11 +328,20 @@ __global__ __launch_bounds__(NTK) void k_kb_gather_mma(
         const int p = 128 * w + g * Op::GK + EL * q;  // EL consecutive points along x
         const float4 *s4 = reinterpret_cast<const float4 *>(src + tile_point_c<LX>(base, p, nx, ny));
         float e[EL];
+        // the lane pair (col, col ^ 1) reads each group of 4 complex values
+        // once: the even lane points 0, 1 and the odd lane points 2, 3; then
+        // they swap the parts the other needs (real parts to the even lane,
+        // imaginary parts to the odd lane)
+        const int od = col & 1;
 #pragma unroll
-        for (int h = 0; h < EL / 2; ++h) {
-          const float4 z = s4[h];
-          e[2 * h] = (col & 1) ? z.y : z.x;
-          e[2 * h + 1] = (col & 1) ? z.w : z.z;
+        for (int i = 0; i < EL / 4; ++i) {
+          const float4 z = s4[2 * i + od];
+          const float g0 = __shfl_xor(od ? z.x : z.y, 1, 64);
+          const float g1 = __shfl_xor(od ? z.z : z.w, 1, 64);
+          e[4 * i] = od ? g0 : z.x;
+          e[4 * i + 1] = od ? g1 : z.z;
+          e[4 * i + 2] = od ? z.y : g0;
+          e[4 * i + 3] = od ? z.w : g1;
         }
         if constexpr (Op::SPLIT) Op::pack2(e, b[g][n], blo[g][n]);
         else b[g][n] = Op::pack(e);
