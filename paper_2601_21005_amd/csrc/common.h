@@ -151,6 +151,7 @@ struct sgw_ctx {
   bool overlap = true;
   std::string ns;
   ~sgw_ctx() {
+    (void)hipStreamSynchronize(stream);   // no graph or buffer in use is released
     if (aux) {
       (void)hipStreamSynchronize(aux);
       (void)hipStreamDestroy(aux);
@@ -222,6 +223,8 @@ struct sgw_ctx {
     return *p;
   }
   void clear_graphs() {
+    // a replay of one of them may still run on either stream
+    if (!gexec.empty()) (void)hipDeviceSynchronize();
     for (auto &g : gexec) (void)hipGraphExecDestroy(g.second);
     gexec.clear();
   }
