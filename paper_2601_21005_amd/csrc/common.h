@@ -151,7 +151,7 @@ struct sgw_ctx {
   bool overlap = true;
   std::string ns;
   ~sgw_ctx() {
-    (void)hipStreamSynchronize(stream);   // no graph or buffer in use is released
+    (void)hipDeviceSynchronize();   // no graph or buffer is released while in use
     if (aux) {
       (void)hipStreamSynchronize(aux);
       (void)hipStreamDestroy(aux);
