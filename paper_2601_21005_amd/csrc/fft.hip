@@ -126,7 +126,7 @@ __global__ __launch_bounds__(NT_FFT) void k_plane(PassArgs a) {
     }
   }
   __syncthreads();
-  lds_fft<C, NX, NY, P, 1, false, NT_FFT>(s, twx, tid);
+  lds_fft<C, NX, NY, P, 1, true, NT_FFT>(s, twx, tid);
   lds_fft<C, NY, NX, 1, P, true, NT_FFT>(s, twy, tid);
   constexpr int Q = (E + NT_FFT - 1) / NT_FFT;
   if constexpr (MODE == PLANE_INV_CHEB && E % NT_FFT == 0) {
@@ -242,7 +242,7 @@ __global__ __launch_bounds__(NT_FFT) void k_xlines(PassArgs a) {
     }
   }
   __syncthreads();
-  lds_fft<C, NX, NL, P, 1, false, NT_FFT>(s, twx, tid);
+  lds_fft<C, NX, NL, P, 1, true, NT_FFT>(s, twx, tid);
 #pragma unroll
   for (int q = 0; q < (E + NT_FFT - 1) / NT_FFT; ++q) {
     const int e = tid + q * NT_FFT;
