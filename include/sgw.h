@@ -256,6 +256,10 @@ typedef struct {
  * second stream of the context beside the TDH steps (its time then falls in
  * the TDH phase; the results are bitwise those of running it afterwards,
  * which the environment variable SGW_ZETA_OVERLAP=0 at sgw_create selects).
+ * The zeta states of G consecutive output steps come from one Chebyshev
+ * sweep with the Jacobi-Anger coefficients of the times dt, 2 dt, ..., G dt
+ * (each truncated at prop_tol), so the propagation is exact to prop_tol at
+ * every step; G is 8, or SGW_ZETA_SWEEP at sgw_create (clamped to 1 .. 8).
  * Requires N_g to be a multiple of 32 in xi mode. */
 sgw_status sgw_sigma_estimate(sgw_ctx *ctx, const sgw_sigma_params *params,
                               const double *phi, double *sigma_t, double *x,

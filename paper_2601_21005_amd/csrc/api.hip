@@ -240,6 +240,71 @@ void *cheb_series(sgw_ctx *ctx, void *v0, void *w1, void *acc, void *tmp, int64_
   return last();
 }
 
+// G sums of one recurrence on v0: acc_g = sum_n coef_g,n T_n(H~) v0 for
+// g < G (accumulators G-major, acc + g nvec N; ld = N), each series padded
+// with zeros to the longest.  The zeta propagation takes the states of G
+// consecutive output steps from one sweep (the Jacobi-Anger coefficients of
+// the times dt, 2 dt, ..., G dt, Eq. 4), instead of G series of one step
+// each.  The pairs b_{k-1} v_{k-1} + b_k v_k go into the accumulators before
+// term k (odd k) overwrites v_{k-1}.  v0 and w1 are overwritten; with graphs
+// on, the sweep is replayed whole (one graph per buffers and coefficients).
+void cheb_sweep(sgw_ctx *ctx, void *v0, void *w1, void *acc, void *tmp, int64_t nvec,
+                const std::vector<std::vector<double>> &coefs, double emin, double emax) {
+  const int G = (int)coefs.size();
+  SGW_REQUIRE(G >= 1 && G <= kMaxSweep, SGW_EINVAL, "sweep: bad number of outputs");
+  int nc = 0;
+  for (const auto &cg : coefs) nc = std::max(nc, (int)cg.size() / 2);
+  const double c = 0.5 * (emax + emin), R = 0.5 * (emax - emin), invR = 1.0 / R;
+  void *kbC = nullptr;
+  if (ctx->has_kb) kbC = ctx->buf("kbC", ctx->csize() * ctx->kb.nproj * nvec).p;
+  auto cur_of = [&](int k) { return (k % 2 == 0) ? v0 : w1; };
+  auto old_of = [&](int k) { return (k % 2 == 0) ? w1 : v0; };
+  auto b_of = [&](int g, int n, int part) {
+    return 2 * n + 1 < (int)coefs[g].size() ? coefs[g][2 * n + part] : 0.0;
+  };
+  // acc_g (=/+=) b_g,n0 v_n0 (+ b_g,n1 v_n1)
+  auto accs = [&](const void *a, int n0, const void *b, int n1, bool assign) {
+    ChebAccCoefs cf{};
+    for (int g = 0; g < G; ++g) {
+      cf.c[g][0] = b_of(g, n0, 0);
+      cf.c[g][1] = b_of(g, n0, 1);
+      cf.c[g][2] = b ? b_of(g, n1, 0) : 0.0;
+      cf.c[g][3] = b ? b_of(g, n1, 1) : 0.0;
+    }
+    launch_cheb_accs(ctx, a, b, acc, nvec, G, cf, assign);
+  };
+  auto run = [&]() {
+    for (int k = 0; k + 1 < nc; ++k) {
+      if (k % 2 == 1) accs(old_of(k), k - 1, cur_of(k), k, k == 1);
+      cheb_term(ctx, cur_of(k), old_of(k), nullptr, tmp, kbC, nvec, k == 0, 0, nullptr, nullptr,
+                c, invR, nullptr);
+    }
+    // the loop ran terms 0 .. nc - 2 and took the pairs up to the last odd one
+    const int k = nc - 1;
+    if (k % 2 == 1)
+      accs(old_of(k), k - 1, cur_of(k), k, k == 1);
+    else
+      accs(cur_of(k), k, nullptr, 0, k == 0);
+  };
+  if (!(ctx->graphs && !ctx->ktimer) || nc > 2 * SHORT_SERIES) {
+    run();
+    return;
+  }
+  std::string key = "sweep|" + ptr_key({v0, w1, acc, tmp, kbC}) +
+                    num_key({(double)nvec, c, invR, (double)G});
+  for (const auto &cg : coefs) {
+    key += "/";
+    for (double x : cg) key += num_key({x});
+  }
+  auto it = ctx->gexec.find(key);
+  if (it == ctx->gexec.end()) {
+    run();                              // this call runs eagerly, later ones replay
+    if (!g_no_capture) captured(ctx, key, run);
+  } else {
+    SGW_HIP(hipGraphLaunch(it->second, ctx->stream));
+  }
+}
+
 // ||v_last|| <= ||v_0|| when spec(H~) lies in [-1, 1]; growth means the
 // interval did not enclose the spectrum.
 void check_growth(sgw_ctx *ctx, const std::vector<double> &n0, const void *vlast, int64_t nvec) {
@@ -469,6 +534,7 @@ sgw_status sgw_create(const sgw_grid *grid, const double *v_loc, const sgw_proje
     }
     if (const char *fc = std::getenv("SGW_FILTER_CHUNK")) c->filter_chunk = std::atoi(fc);
     if (const char *ov = std::getenv("SGW_ZETA_OVERLAP")) c->overlap = std::atoi(ov) != 0;
+    if (const char *zw = std::getenv("SGW_ZETA_SWEEP")) c->zeta_sweep = std::atoi(zw);
     if (const char *fv = std::getenv("SGW_FORCE_VARIANT")) {
       // "name=i,name=i": pin autotuned kernel variants (testing)
       std::string spec(fv);
@@ -851,14 +917,19 @@ sgw_status sgw_sigma_estimate_states(sgw_ctx *ctx, const sgw_sigma_params *P, in
     const size_t cs = ctx->csize(), rs = ctx->rsize();
 
     // coefficients
-    std::vector<double> a(P->ncoef), fc(2 * P->ncoef, 0.0), pb;
+    std::vector<double> a(P->ncoef), fc(2 * P->ncoef, 0.0);
     if (P->filter == 1)
       gapped_coefficients(P->e_homo, P->e_lumo, P->filter_eps, P->emin, P->emax, P->ncoef,
                           a.data());
     else
       fermi_coefficients(P->mu, P->beta, P->emin, P->emax, P->ncoef, a.data());
     for (int i = 0; i < P->ncoef; ++i) fc[2 * i] = a[i];
-    propagator_coefficients(P->emin, P->emax, P->dt, P->prop_tol, pb);
+    // zeta propagator: the output steps come G at a time from one sweep
+    // (coefficients of the times dt .. G dt)
+    const int G = std::max(1, std::min(ctx->zeta_sweep, std::min(kMaxSweep, P->n_tau)));
+    std::vector<std::vector<double>> pbs(G);
+    for (int g = 0; g < G; ++g)
+      propagator_coefficients(P->emin, P->emax, (g + 1) * P->dt, P->prop_tol, pbs[g]);
     // time-ordering twiddles
     std::vector<double> tw(2 * nft);
     for (int j = 0; j < nft; ++j) {
@@ -991,19 +1062,31 @@ sgw_status sgw_sigma_estimate_states(sgw_ctx *ctx, const sgw_sigma_params *P, in
       {
         OnStream on(ctx, zs, zns);
         zb = ctx->buf("z_b", cs * N * 2 * S).p;
-        zacc = ctx->buf("z_acc", cs * N * 2 * S).p;
+        zacc = ctx->buf("z_acc", cs * N * 2 * S * G).p;
         zt = ctx->buf("z_tmp", cs * N * 2 * S).p;
       }
       const size_t dstep = cs * (size_t)S * (ovl ? P->n_xi : 0);   // one (step, state) of d
       char *dpa = ovl ? static_cast<char *>(ctx->buf("xi_dp_all", dstep * nt1 * K).p) : nullptr;
       char *dta = ovl ? static_cast<char *>(ctx->buf("xi_dt_all", dstep * nt1 * K).p) : nullptr;
-      void *zc = zeta;
+      // zeta(t_j) for j = 0, 1, 2, ... in turn: a sweep from zeta(t_{j-1})
+      // gives the steps j .. j + G - 1 (fewer at the end); the last of them
+      // is copied back to be the next sweep's start
+      auto zeta_at = [&](int j) -> void * {
+        if (j == 0) return zeta;
+        const int g = (j - 1) % G;
+        if (g == 0) {
+          const int64_t nz = 2 * S;
+          if (j > 1)
+            launch_copy(ctx, static_cast<char *>(zacc) + cs * N * nz * (G - 1), N, zeta, N, nz);
+          const int gn = std::min(G, nt1 - j);
+          const std::vector<std::vector<double>> sub(pbs.begin(), pbs.begin() + gn);
+          cheb_sweep(ctx, zeta, zb, zacc, zt, nz, sub, P->emin, P->emax);
+        }
+        return static_cast<char *>(zacc) + cs * N * 2 * S * g;
+      };
       auto zeta_step = [&](int j) {
         OnStream on(ctx, zs, zns);
-        if (j > 0) {
-          cheb_series(ctx, zc, zb, zacc, zt, 2 * S, pb, P->emin, P->emax);
-          std::swap(zc, zacc);
-        }
+        void *zc = zeta_at(j);
         for (int k = 0; k < K; ++k)
           launch_xi_zeta(ctx, zc, phi_of(k), blocks, d_ksign.as<uint64_t>(), S, P->n_xi, nseg,
                          amp * ctx->dV, dpa + dstep * ((size_t)j * K + k),
@@ -1081,10 +1164,7 @@ sgw_status sgw_sigma_estimate_states(sgw_ctx *ctx, const sgw_sigma_params *P, in
         partial = ctx->buf("c_partial", sizeof(double) * 4 * S * ((N + 4095) / 4096)).as<double>();
       }
       for (int j = 0; j < (ovl ? 0 : nt1); ++j) {
-        if (j > 0) {
-          cheb_series(ctx, zc, zb, zacc, zt, 2 * S, pb, P->emin, P->emax);
-          std::swap(zc, zacc);
-        }
+        void *zc = zeta_at(j);
         for (int k = 0; k < K; ++k) {
           double *sig_k = d_sig + (size_t)4 * S * nt1 * k;
           if (xi) {

@@ -149,6 +149,7 @@ struct sgw_ctx {
   // streams never share scratch memory.
   hipStream_t aux = nullptr;
   bool overlap = true;
+  int zeta_sweep = 8;   // zeta output steps per Chebyshev sweep (1 .. 8)
   std::string ns;
   ~sgw_ctx() {
     (void)hipDeviceSynchronize();   // no graph or buffer is released while in use

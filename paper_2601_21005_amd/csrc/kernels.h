@@ -17,6 +17,13 @@ void launch_axpy(sgw_ctx *ctx, const void *x, int64_t ldx, void *acc, int64_t ld
 // acc[v] (= when assign, else +=) c0 a[v] + c1 b[v]  (common leading dimension ld)
 void launch_axpy2(sgw_ctx *ctx, const void *a, const void *b, int64_t ld, void *acc,
                   int64_t nvec, double c0r, double c0i, double c1r, double c1i, bool assign);
+// Several sums over one Chebyshev recurrence (the zeta sweep): for g < G,
+// acc_g[v] (= when assign, else +=) c0_g a[v] + c1_g b[v] (b nullable); all
+// vectors N apart, the accumulators G-major (acc + (g nvec + v) N).
+constexpr int kMaxSweep = 8;
+struct ChebAccCoefs { double c[kMaxSweep][4]; };   // (c0 re, c0 im, c1 re, c1 im)
+void launch_cheb_accs(sgw_ctx *ctx, const void *a, const void *b, void *acc, int64_t nvec,
+                      int G, const ChebAccCoefs &cf, bool assign);
 // dst[v] = src[v]
 void launch_copy(sgw_ctx *ctx, const void *src, int64_t lds, void *dst, int64_t ldd,
                  int64_t nvec);

@@ -107,3 +107,25 @@ def test_sigma_tiny8_gapped_filter(tiny8, tiny_states, prec, tol):
                                     mu=0.0, beta=0.0)
     assert rel_err(sig, sig_o) < tol
     assert rel_err(x, x_o) < tol
+
+
+@pytest.mark.parametrize("sweep", ["1", "3", "8"])
+@pytest.mark.parametrize("mode", ["xi", "exact"])
+def test_sigma_zeta_sweeps(tiny8, tiny_states, monkeypatch, sweep, mode):
+    """The zeta states of G consecutive output steps come from one Chebyshev
+    sweep with the Jacobi-Anger coefficients of the times dt .. G dt (Eq. 4
+    for each time).  Over 19 steps (sweeps of 8, 8 and 3 steps for G = 8; six
+    of 3 and one of 1 for G = 3) the estimate matches the oracle's
+    step-by-step propagation in FP64."""
+    monkeypatch.setenv("SGW_ZETA_SWEEP", sweep)
+    s, H = tiny8
+    e, V = tiny_states
+    phi = V[s.n_occ - 1]
+    lo, hi = H.bounds()
+    mu = 0.5 * (e[1] + e[2])
+    n = cheb.suggested_ncoef(mu, 10.0, lo, hi, tol=1e-12, nmax=8192)
+    sig, x, sig_o, x_o, p = compare(s, H, phi, sgw.SGW_C128, seed=13, n_zeta=2, n_eta=4,
+                                    n_tau=19, dt=0.2, m_sub=1, mu=mu, beta=10.0, ncoef=n,
+                                    n_xi=64, f_g=0.125, mode=mode)
+    assert rel_err(sig, sig_o) < 1e-9
+    assert rel_err(x, x_o) < 1e-9
