@@ -48,6 +48,15 @@ HPSI_ALGO_BYTES = 16.0
 # scaled by the counters' reading for a plain 256 MiB device copy.  Valid only
 # for the kernel source it was measured on; None once that kernel changes.
 CHEB_MEASURED_BYTES = 36.68
+# The dominant kernel by time, the projector scatter psi += s B C' (the TDH's
+# KB exponential twice per substep at 1024 vectors, every filter term at 260):
+# algorithmic bytes per (point of a tile that projectors touch x complex
+# vector) = read and write of psi there, 16 B (the reads of B and C', under
+# 2 % of that at these batch widths, are left out).
+KB_SCATTER_ALGO_BYTES = 16.0
+# its counter bytes per touched point x vector (FETCH_SIZE + WRITE_SIZE,
+# scaled as above): 16.5 at 1024 vectors, 16.8 at 260
+KB_SCATTER_MEASURED_BYTES = 16.6
 
 
 def parse():
@@ -320,7 +329,7 @@ def main():
     for w in range(args.warmup):
         ctx.sigma_estimate(phi, n_zeta=B, first_sample=w * B, **p)
     torch.cuda.synchronize()
-    ctx.kernel_timer(True)
+    ctx.kernel_timer(sgw.SGW_TIMER_CHEB_PLANE | sgw.SGW_TIMER_KB_SCATTER)
     sigs, xs, phases = [], [], np.zeros(6)
     t0 = time.perf_counter()
     for k in range(args.steps):
@@ -330,8 +339,9 @@ def main():
         phases += ms
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t0
-    ctx.kernel_timer(False)
-    k_ms, k_launch, k_pts = ctx.kernel_timer_read()
+    ctx.kernel_timer(0)
+    k_ms, k_launch, k_pts = ctx.kernel_timer_read(sgw.SGW_TIMER_CHEB_PLANE)
+    s_ms, s_launch, s_pts = ctx.kernel_timer_read(sgw.SGW_TIMER_KB_SCATTER)
 
     sig = np.concatenate(sigs)
     x = np.concatenate(xs)
@@ -374,6 +384,7 @@ def main():
                                           t_sample, sigma1, Z)
 
     achieved = CHEB_ALGO_BYTES * k_pts / (k_ms * 1e-3) / 1e9 if k_ms > 0 else None
+    s_achieved = KB_SCATTER_ALGO_BYTES * s_pts / (s_ms * 1e-3) / 1e9 if s_ms > 0 else None
     line = {
         "metric": METRIC,
         "value": gpu_s_per_qp,
@@ -403,7 +414,17 @@ def main():
         "hpsi_algo_roofline_frac": hpsi_rate * HPSI_ALGO_BYTES / (HBM_PEAK_GBS * 1e9),
         "phase_ms": {"filter": phases[0], "tdh": phases[1], "time_order": phases[2],
                      "zeta_contract": phases[3], "other": phases[4], "total": phases[5]},
-        "roofline": {"bound": "hbm", "kernel": "k_plane<float,64,64,PLANE_INV_CHEB>",
+        "roofline": {"bound": "hbm", "kernel": "k_kb_scatter_mma<OpF32,NVB,MJ,LX> (autotuned)",
+                     "achieved": s_achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": s_achieved / HBM_PEAK_GBS if s_achieved else None,
+                     "traffic": (KB_SCATTER_MEASURED_BYTES * s_pts / s_launch
+                                 if s_launch and KB_SCATTER_MEASURED_BYTES else None),
+                     "traffic_unit": "B per launch",
+                     "algo_bytes_per_touched_ptvec": KB_SCATTER_ALGO_BYTES,
+                     "traffic_bytes_per_touched_ptvec": KB_SCATTER_MEASURED_BYTES,
+                     "launches": s_launch,
+                     "avg_launch_us": 1e3 * s_ms / s_launch if s_launch else None},
+        "roofline_cheb": {"bound": "hbm", "kernel": "k_plane<float,64,64,PLANE_INV_CHEB>",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS if achieved else None,
                      "traffic": (CHEB_MEASURED_BYTES * k_pts / k_launch

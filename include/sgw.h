@@ -299,16 +299,27 @@ sgw_status sgw_qp_solve(const double *sigma_t, int32_t n_tau, double dt,
 sgw_status sgw_sigma_omega(const double *sigma_t, int32_t n_tau, double dt, double gamma,
                            const double *omega, int32_t n_omega, double *out);
 
-/* Launch timer of the dominant kernel: the inverse xy-plane FFT pass that
- * carries the Chebyshev-recurrence epilogue (Eq. 3 filter and the zeta
- * propagator).  enable != 0: from now on every launch of that pass on the
- * context's stream is bracketed by a pair of HIP events (launches that
+/* Launch timers of the two largest kernels (bits of `which`):
+ *   SGW_TIMER_CHEB_PLANE  the inverse xy-plane FFT pass that carries the
+ *                         Chebyshev-recurrence epilogue (Eq. 3 filter and the
+ *                         zeta propagator); points = grid points x vectors;
+ *   SGW_TIMER_KB_SCATTER  the projector scatter GEMM psi += s B C' (complex
+ *                         FP32 precisions; filter terms, H applications and
+ *                         the KB exponential of the TDH steps); points =
+ *                         points of the tiles that projectors touch x vectors.
+ * From sgw_kernel_timer(ctx, bits) on, every launch of the selected kernels
+ * on the context's stream is bracketed by a pair of HIP events (launches that
  * sgw_sigma_estimate issues on the context's second stream, the zeta
  * propagation running beside the TDH steps, are not timed: they share the
- * device with the TDH kernels); enable = 0 stops it.  sgw_kernel_timer_read synchronises the stream and returns the summed
- * event time (ms), the number of timed launches and the number of grid
- * points x vectors they processed, then resets the counters. */
-sgw_status sgw_kernel_timer(sgw_ctx *ctx, int32_t enable);
+ * device with the TDH kernels); bits = 0 stops timing, other bits are
+ * SGW_EINVAL.  sgw_kernel_timer_read(ctx, which, ...) takes one timer,
+ * synchronises the stream and returns its summed event time (ms), the number
+ * of timed launches and the points they processed, then resets that timer. */
+#define SGW_TIMER_CHEB_PLANE 1
+#define SGW_TIMER_KB_SCATTER 2
+sgw_status sgw_kernel_timer(sgw_ctx *ctx, int32_t which);
+sgw_status sgw_kernel_timer_read(sgw_ctx *ctx, int32_t which, double *total_ms,
+                                 int64_t *launches, int64_t *points);
 
 /* HIP graphs for repeated launch sequences.  enable != 0: a Chebyshev series
  * of at most 64 terms (the zeta propagator, Eq. 4) runs as one captured graph
@@ -321,8 +332,6 @@ sgw_status sgw_kernel_timer(sgw_ctx *ctx, int32_t enable);
  * context created on a non-default stream (SGW_EINVAL otherwise); graphs are
  * not used while the kernel timer is on.  Synchronises the stream. */
 sgw_status sgw_use_graphs(sgw_ctx *ctx, int32_t enable);
-sgw_status sgw_kernel_timer_read(sgw_ctx *ctx, double *total_ms, int64_t *launches,
-                                 int64_t *points);
 
 
 /* Many clusters of uneven size in one call.  Each item is one

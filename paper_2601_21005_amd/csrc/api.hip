@@ -834,9 +834,13 @@ sgw_status sgw_sigma_omega(const double *sigma_t, int32_t n_tau, double dt, doub
   return SGW_OK;
 }
 
-sgw_status sgw_kernel_timer(sgw_ctx *ctx, int32_t enable) {
+sgw_status sgw_kernel_timer(sgw_ctx *ctx, int32_t which) {
   if (!ctx) return SGW_EINVAL;
-  return guarded(ctx, [&] { ctx->ktimer = enable != 0; });
+  return guarded(ctx, [&] {
+    SGW_REQUIRE((which & ~(SGW_TIMER_CHEB_PLANE | SGW_TIMER_KB_SCATTER)) == 0, SGW_EINVAL,
+                "unknown timer bits");
+    ctx->ktimer = which;
+  });
 }
 
 sgw_status sgw_use_graphs(sgw_ctx *ctx, int32_t enable) {
@@ -850,23 +854,26 @@ sgw_status sgw_use_graphs(sgw_ctx *ctx, int32_t enable) {
   });
 }
 
-sgw_status sgw_kernel_timer_read(sgw_ctx *ctx, double *total_ms, int64_t *launches,
-                                 int64_t *points) {
+sgw_status sgw_kernel_timer_read(sgw_ctx *ctx, int32_t which, double *total_ms,
+                                 int64_t *launches, int64_t *points) {
   if (!ctx) return SGW_EINVAL;
   return guarded(ctx, [&] {
     SGW_REQUIRE(total_ms && launches && points, SGW_EINVAL, "NULL output");
+    SGW_REQUIRE(which == SGW_TIMER_CHEB_PLANE || which == SGW_TIMER_KB_SCATTER, SGW_EINVAL,
+                "which must name one timer");
+    sgw_ctx::KTimer &t = ctx->kt[which == SGW_TIMER_CHEB_PLANE ? 0 : 1];
     SGW_HIP(hipStreamSynchronize(ctx->stream));
     double ms = 0;
-    for (int64_t i = 0; i < ctx->kt_used; ++i) {
-      float t = 0;
-      SGW_HIP(hipEventElapsedTime(&t, ctx->kt_events[2 * i], ctx->kt_events[2 * i + 1]));
-      ms += t;
+    for (int64_t i = 0; i < t.used; ++i) {
+      float e = 0;
+      SGW_HIP(hipEventElapsedTime(&e, t.events[2 * i], t.events[2 * i + 1]));
+      ms += e;
     }
     *total_ms = ms;
-    *launches = ctx->kt_used;
-    *points = ctx->kt_points;
-    ctx->kt_used = 0;
-    ctx->kt_points = 0;
+    *launches = t.used;
+    *points = t.points;
+    t.used = 0;
+    t.points = 0;
   });
 }
 

@@ -130,19 +130,23 @@ struct sgw_ctx {
   std::map<std::string, hipGraphExec_t> gexec;
   sgw::DevBuf d_counter;
 
-  // launch timer of the inverse plane pass with the Chebyshev epilogue
-  bool ktimer = false;
-  std::vector<hipEvent_t> kt_events;   // pairs (start, stop)
-  int64_t kt_used = 0, kt_points = 0;
-  hipEvent_t timer_event(int which) {
-    const size_t i = 2 * (size_t)kt_used + which;
-    while (kt_events.size() <= i) {
-      hipEvent_t e;
-      if (hipEventCreate(&e) != hipSuccess) throw sgw::Error{SGW_EHIP, "hipEventCreate failed"};
-      kt_events.push_back(e);
+  // launch timers: ktimer bit 0 the inverse plane pass with the Chebyshev
+  // epilogue, bit 1 the KB scatter (launches on the context's stream)
+  struct KTimer {
+    std::vector<hipEvent_t> events;   // pairs (start, stop)
+    int64_t used = 0, points = 0;
+    hipEvent_t event(int which) {
+      const size_t i = 2 * (size_t)used + which;
+      while (events.size() <= i) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) throw sgw::Error{SGW_EHIP, "hipEventCreate failed"};
+        events.push_back(e);
+      }
+      return events[i];
     }
-    return kt_events[i];
-  }
+  };
+  int ktimer = 0;
+  KTimer kt[2];
   // second stream of the context (non-blocking, default priority): the zeta
   // propagation of sgw_sigma_estimate runs on it beside the TDH steps.  While
   // work is issued there, `ns` suffixes every scratch buffer name so the two
@@ -157,7 +161,8 @@ struct sgw_ctx {
       (void)hipStreamSynchronize(aux);
       (void)hipStreamDestroy(aux);
     }
-    for (auto e : kt_events) (void)hipEventDestroy(e);
+    for (auto &t : kt)
+      for (auto e : t.events) (void)hipEventDestroy(e);
     for (auto &g : gexec) (void)hipGraphExecDestroy(g.second);
   }
 

@@ -489,13 +489,13 @@ void fft3d_apply_t(sgw_ctx *ctx, const void *src, void *tmp, void *dst, int64_t 
     // inverse xy with the epilogue
     PassArgs b = a;
     b.src = tmpv; b.ld_src = N; b.dst = dstv; b.ld_dst = ld; b.mode = inv_mode; b.inverse = 1;
-    const bool timed = ctx->ktimer && inv_mode == PLANE_INV_CHEB && ctx->ns.empty();
+    const bool timed = (ctx->ktimer & 1) && inv_mode == PLANE_INV_CHEB && ctx->ns.empty();
     if (!use_plane) {
       PassArgs py = a;
       py.dst = tmpv; py.ld_dst = N; py.axis = 1; py.tw0 = twy; py.inverse = 1; py.mul = MUL_NONE;
       oy.pencil(dim3((ctx->nx / oy.tx) * ctx->nz, nv), st, py);
     }
-    if (timed) SGW_HIP(hipEventRecord(ctx->timer_event(0), st));
+    if (timed) SGW_HIP(hipEventRecord(ctx->kt[0].event(0), st));
     if (use_plane) {
       b.tw0 = twx; b.tw1 = twy;
       ox.plane(dim3(ctx->nz, nv), st, b);
@@ -504,9 +504,9 @@ void fft3d_apply_t(sgw_ctx *ctx, const void *src, void *tmp, void *dst, int64_t 
       ox.xlines(dim3((ctx->ny * ctx->nz + ox.nl - 1) / ox.nl, nv), st, b);
     }
     if (timed) {
-      SGW_HIP(hipEventRecord(ctx->timer_event(1), st));
-      ctx->kt_used++;
-      ctx->kt_points += nv * N;
+      SGW_HIP(hipEventRecord(ctx->kt[0].event(1), st));
+      ctx->kt[0].used++;
+      ctx->kt[0].points += nv * N;
     }
     SGW_HIP(hipGetLastError());
   }

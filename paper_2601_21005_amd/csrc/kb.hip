@@ -721,7 +721,14 @@ static void scatter_t(sgw_ctx *ctx, const void *coef, int64_t nvec, void *dst, i
       };
       // trials add 0 * (B C) to dst, which leaves it unchanged
       const int vi = ctx->tune(name, nvec, NSCATTER, [&](int i) { launch(i, 0.0f); });
+      const bool timed = (ctx->ktimer & 2) && ctx->ns.empty();
+      if (timed) SGW_HIP(hipEventRecord(ctx->kt[1].event(0), ctx->stream));
       launch(vi, (float)s1re);
+      if (timed) {
+        SGW_HIP(hipEventRecord(ctx->kt[1].event(1), ctx->stream));
+        ctx->kt[1].used++;
+        ctx->kt[1].points += (int64_t)ctx->kb_ntile * KB_TP * nvec;
+      }
     };
     if (ctx->prec == SGW_C64_BF16KB)
       go(OpBF16{}, "kb_scatter_bf16", ctx->d_kb_betaT.as<uint16_t>());

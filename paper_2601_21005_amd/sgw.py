@@ -17,6 +17,7 @@ SGW_OK, SGW_EINVAL, SGW_ENOMEM, SGW_EHIP, SGW_EDIVERGED, SGW_ENOROOT, SGW_EUNSUP
     0, -1, -2, -3, -4, -5, -6
 SGW_C128, SGW_C64, SGW_C64_BF16KB, SGW_C64_BF16X2KB = 0, 1, 2, 3
 SGW_MAX_STATES = 8
+SGW_TIMER_CHEB_PLANE, SGW_TIMER_KB_SCATTER = 1, 2
 
 STATUS_NAMES = {0: "SGW_OK", -1: "SGW_EINVAL", -2: "SGW_ENOMEM", -3: "SGW_EHIP",
                 -4: "SGW_EDIVERGED", -5: "SGW_ENOROOT", -6: "SGW_EUNSUPPORTED"}
@@ -120,7 +121,7 @@ def load():
     lib.sgw_kernel_timer.argtypes = [vp, i32]
     lib.sgw_use_graphs.argtypes = [vp, i32]
     lib.sgw_batch_sigma_estimate.argtypes = [C.POINTER(SgwBatchItem), i32, i32]
-    lib.sgw_kernel_timer_read.argtypes = [vp, dp, C.POINTER(i64), C.POINTER(i64)]
+    lib.sgw_kernel_timer_read.argtypes = [vp, i32, dp, C.POINTER(i64), C.POINTER(i64)]
     u64, fp = C.c_uint64, C.c_void_p
     lib.sgw_cv_features.argtypes = [vp, fp, i32, i64, u64, i64, i64, fp]
     lib.sgw_mlp_create.argtypes = [i32, i32, i32, dp, vp, C.POINTER(vp)]
@@ -318,13 +319,18 @@ class Context:
     def use_graphs(self, enable=True):
         _check(load().sgw_use_graphs(self.ctx, 1 if enable else 0), self.ctx)
 
-    def kernel_timer(self, enable):
-        _check(load().sgw_kernel_timer(self.ctx, 1 if enable else 0), self.ctx)
+    def kernel_timer(self, which):
+        """which: SGW_TIMER_CHEB_PLANE | SGW_TIMER_KB_SCATTER bits (True: the
+        Chebyshev plane pass), 0 / False stops timing."""
+        which = SGW_TIMER_CHEB_PLANE if which is True else int(which)
+        _check(load().sgw_kernel_timer(self.ctx, which), self.ctx)
 
-    def kernel_timer_read(self):
+    def kernel_timer_read(self, which=None):
+        """(summed ms, launches, points) of one timer, which resets."""
+        which = SGW_TIMER_CHEB_PLANE if which is None else which
         ms, n, pts = C.c_double(), C.c_int64(), C.c_int64()
-        _check(load().sgw_kernel_timer_read(self.ctx, C.byref(ms), C.byref(n), C.byref(pts)),
-               self.ctx)
+        _check(load().sgw_kernel_timer_read(self.ctx, which, C.byref(ms), C.byref(n),
+                                            C.byref(pts)), self.ctx)
         return ms.value, n.value, pts.value
 
     def sigma_estimate(self, phi, seed, n_zeta, n_eta, n_tau, dt, m_sub, ncoef, emin, emax,

@@ -76,3 +76,12 @@ def test_max_states_matches_header():
     from paper_2601_21005_amd import sgw
     m = re.search(r"#define\s+SGW_MAX_STATES\s+(\d+)", open(HEADER).read())
     assert m and int(m.group(1)) == sgw.SGW_MAX_STATES
+
+
+def test_timer_bits_match_header():
+    import re
+    from paper_2601_21005_amd import sgw
+    text = open(HEADER).read()
+    for name in ("SGW_TIMER_CHEB_PLANE", "SGW_TIMER_KB_SCATTER"):
+        m = re.search(r"#define\s+%s\s+(\d+)" % name, text)
+        assert m and int(m.group(1)) == getattr(sgw, name), name

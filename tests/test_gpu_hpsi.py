@@ -155,3 +155,32 @@ def test_lanczos_bounds_si35h36_fp32(si35):
     assert lo <= -8.0305409 and hi >= 27.99999
     assert lw <= lo and hi <= hw
     assert hi - lo < 0.9 * (hw - lw)
+
+
+def test_kernel_timers(tiny8):
+    """The launch timers of the Chebyshev plane pass and the KB scatter count
+    one launch of each per filter term and the points they cover (the 8^3
+    grid is one 512-point tile, which the projectors touch)."""
+    s, _ = tiny8
+    ctx = make_ctx(s, sgw.SGW_C64, max_nvec=32)
+    N, nvec = s.grid.N, 5
+    g = torch.Generator(device="cuda").manual_seed(3)
+    x = torch.randn((nvec, N), generator=g, device="cuda", dtype=torch.complex64)
+    lo, hi = ctx.bounds()
+    coef = sgw.sgw_fermi_coefficients(-0.5, 6.0, lo, hi, 40)
+    ctx.kernel_timer(sgw.SGW_TIMER_CHEB_PLANE | sgw.SGW_TIMER_KB_SCATTER)
+    ctx.fermi_filter(x, coef, lo, hi)
+    ctx.kernel_timer(0)
+    ms, n, pts = ctx.kernel_timer_read(sgw.SGW_TIMER_CHEB_PLANE)
+    assert n == 39 and pts == 39 * nvec * N and ms > 0
+    ms, n, pts = ctx.kernel_timer_read(sgw.SGW_TIMER_KB_SCATTER)
+    assert n == 39 and pts == 39 * nvec * 512 and ms > 0
+    assert ctx.kernel_timer_read(sgw.SGW_TIMER_KB_SCATTER)[:2] == (0.0, 0)   # read resets
+    for bad in (4, -1):
+        with pytest.raises(sgw.SgwError) as e:
+            ctx.kernel_timer(bad)
+        assert e.value.code == sgw.SGW_EINVAL
+    with pytest.raises(sgw.SgwError) as e:
+        ctx.kernel_timer_read(3)
+    assert e.value.code == sgw.SGW_EINVAL
+    ctx.close()
