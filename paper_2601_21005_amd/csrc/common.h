@@ -121,6 +121,7 @@ struct sgw_ctx {
   sgw::DevBuf d_kb_betaT;            // per tile [512][entries padded to the K group], FP32 or BF16
   sgw::DevBuf d_kb_beta16;           // [entry][512] BF16 (the BF16 precisions)
   int kb_ntile = 0, kb_nentry = 0;
+  int kb_nek_max = 0;                // largest padded entry count of a tile (scatter LDS)
   int kb_lx = 3, kb_ly = 3;          // tile extent log2 along x and y (512 points)
 
   // HIP graphs: repeated launch sequences (Chebyshev terms, TDH output

@@ -404,7 +404,10 @@ __global__ __launch_bounds__(NTK) void k_kb_gather_mma(
 
 // dst_v(r) += s1 sum_e beta_e(r) C'[p(e)][v] on the points r of tile t (s1 real).
 // betaT holds each tile's block transposed, [512 points][nek entries], with the
-// entry count nek padded to the K group (16 FP32, 32 BF16; zeros).  A wave
+// entry count nek padded to the K group (16 FP32, 32 BF16; zeros).  The
+// coefficient columns sit in dynamic LDS with pitch pe = (largest nek of the
+// context) + one 16-byte group, so the LDS a workgroup holds follows the
+// projector density of the system, not the 256-entry limit.  A wave
 // owns MJ M tiles of 16 points, so a workgroup covers 64 MJ points and a tile
 // takes 512 / (64 MJ) workgroups per vector block (fewer registers per wave
 // for MJ = 4, more waves per SIMD).
@@ -412,13 +415,13 @@ template <class Op, int NVB, int MJ, int LX>
 __global__ __launch_bounds__(NTK) void k_kb_scatter_mma(
     const float2 *coef, int64_t nvec, const int *tile_base, const int *tile_off,
     const int *tile_offT, const int *entry_proj, const typename Op::T *betaT, float2 *dst,
-    int64_t ld, float s1, int nx, int ny, int ntile, int nvb) {
+    int64_t ld, float s1, int nx, int ny, int ntile, int nvb, int pe) {
   using T = typename Op::T;
   constexpr int NC = 2 * NVB, NTL = NC / 16;
   constexpr int EL = 16 / (int)sizeof(T);
-  constexpr int PE = KB_MAXE + EL;                  // LDS pitch of a coefficient column
   constexpr int NH = KB_TP / (64 * MJ);             // workgroups per tile and vector block
-  __shared__ __align__(16) T sc[(Op::SPLIT ? 2 : 1) * NC * PE];   // C' [column][entry] (hi, lo)
+  extern __shared__ __align__(16) unsigned char kb_lds[];
+  T *sc = reinterpret_cast<T *>(kb_lds);            // C' [column][entry] (hi, lo), pitch pe
   int t;
   int64_t vbh;
   if (!tile_block(ntile, nvb * NH, t, vbh)) return;
@@ -443,11 +446,11 @@ __global__ __launch_bounds__(NTK) void k_kb_scatter_mma(
       const int idx = i0 + u * NTK + tid, el = idx / NVB, vl = idx % NVB;
       if (el < nek) {
         if constexpr (Op::SPLIT) {
-          Op::put1x2(sc + (2 * vl) * PE + el, sc + NC * PE + (2 * vl) * PE + el, val[u].x);
-          Op::put1x2(sc + (2 * vl + 1) * PE + el, sc + NC * PE + (2 * vl + 1) * PE + el, val[u].y);
+          Op::put1x2(sc + (2 * vl) * pe + el, sc + NC * pe + (2 * vl) * pe + el, val[u].x);
+          Op::put1x2(sc + (2 * vl + 1) * pe + el, sc + NC * pe + (2 * vl + 1) * pe + el, val[u].y);
         } else {
-          Op::put1(sc + (2 * vl) * PE + el, val[u].x);
-          Op::put1(sc + (2 * vl + 1) * PE + el, val[u].y);
+          Op::put1(sc + (2 * vl) * pe + el, val[u].x);
+          Op::put1(sc + (2 * vl + 1) * pe + el, val[u].y);
         }
       }
     }
@@ -504,7 +507,7 @@ __global__ __launch_bounds__(NTK) void k_kb_scatter_mma(
     for (int h = 0; h < NS; ++h)
 #pragma unroll
       for (int n = 0; n < NTL; ++n)
-        b[h][n] = ld16(sc + h * NC * PE + (16 * n + col) * PE + k0 + EL * q);
+        b[h][n] = ld16(sc + h * NC * pe + (16 * n + col) * pe + k0 + EL * q);
   };
   if (nek > 0) load_group(0, a_cur, b_cur);
   for (int k0 = 0; k0 < nek; k0 += Op::GK) {
@@ -570,12 +573,15 @@ static void launch_scatter_variant(int vi, dim3 g, hipStream_t st, const float2 
                                    int64_t nvec, const int *tb, const int *to, const int *toT,
                                    const int *ep, const typename Op::T *betaT, float2 *dst,
                                    int64_t ld, float s1, int nx, int ny, int lx, int ntile,
-                                   int nvb) {
+                                   int nvb, int nek_max) {
   const ScatterVariant v = kScatter[vi];
+  constexpr int EL = 16 / (int)sizeof(typename Op::T);
+  const int pe = nek_max + EL;
+  const size_t lds = (Op::SPLIT ? 2 : 1) * 2 * (size_t)v.nvb * pe * sizeof(typename Op::T);
 #define SGW_S(A, B, X)                                                                           \
   if (v.nvb == A && v.mj == B && lx == X)                                                        \
-    hipLaunchKernelGGL((k_kb_scatter_mma<Op, A, B, X>), g, dim3(NTK), 0, st, coef, nvec, tb,    \
-                       to, toT, ep, betaT, dst, ld, s1, nx, ny, ntile, nvb);
+    hipLaunchKernelGGL((k_kb_scatter_mma<Op, A, B, X>), g, dim3(NTK), lds, st, coef, nvec, tb,  \
+                       to, toT, ep, betaT, dst, ld, s1, nx, ny, ntile, nvb, pe);
   SGW_S(8, 8, 4) SGW_S(16, 8, 4) SGW_S(8, 4, 4) SGW_S(16, 4, 4) SGW_S(8, 2, 4) SGW_S(16, 2, 4)
   SGW_S(8, 8, 3) SGW_S(16, 8, 3) SGW_S(8, 4, 3) SGW_S(16, 4, 3) SGW_S(8, 2, 3) SGW_S(16, 2, 3)
 #undef SGW_S
@@ -595,9 +601,11 @@ void kb_upload_operands(sgw_ctx *ctx) {
   const bool bf = ctx->prec == SGW_C64_BF16KB || ctx->prec == SGW_C64_BF16X2KB;
   const int kg = bf ? OpBF16::GK : OpF32::GK;      // the scatter's K group
   std::vector<int> offT(nt + 1, 0);
+  ctx->kb_nek_max = 0;
   for (int t = 0; t < nt; ++t) {
     const int ne = kb.tile_off[t + 1] - kb.tile_off[t];
     offT[t + 1] = offT[t] + (ne + kg - 1) / kg * kg;
+    ctx->kb_nek_max = std::max(ctx->kb_nek_max, offT[t + 1] - offT[t]);
   }
   upload(ctx->d_kb_tile_offT, offT.data(), offT.size());
   const size_t nT = (size_t)offT[nt] * KB_TP;
@@ -717,7 +725,7 @@ static void scatter_t(sgw_ctx *ctx, const void *coef, int64_t nvec, void *dst, i
                                    ctx->d_kb_tile_base.as<int>(), ctx->d_kb_tile_off.as<int>(),
                                    ctx->d_kb_tile_offT.as<int>(), ctx->d_kb_entry_proj.as<int>(),
                                    betaT, static_cast<float2 *>(dst), ld, s, ctx->nx, ctx->ny,
-                                   ctx->kb_lx, ctx->kb_ntile, (int)nvb);
+                                   ctx->kb_lx, ctx->kb_ntile, (int)nvb, ctx->kb_nek_max);
       };
       // trials add 0 * (B C) to dst, which leaves it unchanged
       const int vi = ctx->tune(name, nvec, NSCATTER, [&](int i) { launch(i, 0.0f); });
