@@ -412,7 +412,7 @@ template <typename R> bool get_ops(int n, SizeOps &o) {
 #define SGW_SIZE(N) case N: o = make_ops<R, N>(); return true;
     SGW_SIZE(8) SGW_SIZE(12) SGW_SIZE(16) SGW_SIZE(24) SGW_SIZE(32) SGW_SIZE(40)
     SGW_SIZE(48) SGW_SIZE(56) SGW_SIZE(64) SGW_SIZE(80) SGW_SIZE(96) SGW_SIZE(112)
-    SGW_SIZE(128)
+    SGW_SIZE(128) SGW_SIZE(160)
 #undef SGW_SIZE
     default: return false;
   }

@@ -79,6 +79,40 @@ def test_features_match_oracle(which, K, first, nsamp, request):
     assert np.max(np.abs(got - model)) < 1e-4 * np.max(model)
 
 
+def test_features_160_grid_sampled():
+    """The control-variate configuration's grid (160^3 points, h = 0.6 bohr)
+    with its 64 states and a ragged last block of samples (600 = 2 x 256 + 88):
+    sampled rows (block edges and the tail) against the oracle computed one
+    sample at a time.  The states are random normalised stand-ins for the
+    near-gap KS states (the kernel sees only their values).  Bounds: the
+    rigorous one of test_features_match_oracle, and against the BF16 rounding
+    model the FP32 accumulation over N = 4.1e6 points, whose rounding errors
+    add like a random walk: 2^-24 sqrt(N) sum|phi| sqrt(dV) per amplitude, with
+    a factor 16 of margin."""
+    n, h, K, nsamp, first = 160, 0.6, 64, 600, 3000
+    g = Grid(n, h=h)
+    rs = np.random.default_rng(35)
+    phi = rs.standard_normal((K, g.N)).astype(np.float32).astype(np.float64)
+    phi /= np.sqrt(g.dV * np.sum(phi * phi, axis=1))[:, None]
+    phi = phi.astype(np.float32).astype(np.float64)
+    ctx = sgw.Context(n, h, np.zeros(g.N), None, precision=sgw.SGW_C64, max_nvec=2)
+    x = sgw.cv_features(ctx, f32(phi), seed=91, first_sample=first, nsamp=nsamp)
+    got = x.cpu().numpy().astype(np.float64)
+    ctx.close()
+    rows = [0, 1, 255, 256, 511, 512, 599]
+    ref = cv.features(g, phi, 91, [first + i for i in rows])
+    a = np.sqrt(ref)
+    l1 = np.sqrt(g.dV) * np.sum(np.abs(phi), axis=1)
+    da = l1 * (U_BF16 + g.N * 2.0 ** -24)
+    assert np.all(np.abs(got[rows] - ref) <= 2 * a * da[None] + da[None] ** 2)
+    signs = np.stack([cv.rng.white_noise_signs(91, cv.rng.stream_id(cv.rng.ZETA, first + i, 0),
+                                               g.N) for i in rows])
+    am = np.sqrt(g.dV) * (bf16(phi) @ signs.T).T
+    e = 16 * 2.0 ** -24 * np.sqrt(g.N) * l1
+    assert np.all(np.abs(got[rows] - am ** 2) <= 2 * np.abs(am) * e[None] + e[None] ** 2)
+    assert np.all(np.isfinite(got)) and np.all(got >= 0)
+
+
 def test_features_reject_bad_sizes(tiny8):
     s, _ = tiny8
     ctx = sgw.Context(s.grid.n, s.grid.h, s.v_loc, None, precision=sgw.SGW_C64, max_nvec=4)

@@ -56,6 +56,19 @@ def test_hpsi_gaussian_wells_32(cfg1, prec):
     assert norm_err(got, ref) < TOL[prec]
 
 
+def test_hpsi_gaussian_wells_160():
+    """The control-variate configuration's grid, 160^3 at h = 0.6 bohr (x
+    lines and pencils with radix 8, 5 and 4 stages; the planes do not fit in
+    LDS): local H psi on two vectors against the oracle."""
+    from conftest import build_oracle_h
+    from paper_2601_21005_amd import systems
+    s = systems.gaussian_wells(seed=1011, n=160, h=0.6, nwell=24)
+    H = build_oracle_h(s, workers=8)
+    for prec in (sgw.SGW_C128, sgw.SGW_C64):
+        got, ref = run_hpsi(s, H, prec, nvec=2)
+        assert norm_err(got, ref) < TOL[prec], prec
+
+
 @pytest.mark.parametrize("prec", [sgw.SGW_C128, sgw.SGW_C64])
 def test_hpsi_si35h36_64(si35, prec):
     # C128 at 64^3 runs the x-line / y-pencil fallback (plane too big for LDS)
