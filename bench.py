@@ -245,6 +245,8 @@ def cv_form(args, ctx, s, phis, ev, phi, p, homo, eg, gam, t_sample, sigma1, Z):
         a, x, _ = ctx.sigma_estimate(phi, n_zeta=nb, first_sample=first + b0, **p)
         sig.append(a)
         xs.append(x)
+        if (b0 + nb) % 64 == 0 or b0 + nb == n:
+            print(f"control variate: {b0 + nb} / {n} samples", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t_samples = time.perf_counter() - t0
     sig, xs = np.concatenate(sig), np.concatenate(xs)
@@ -282,7 +284,9 @@ def cv_form(args, ctx, s, phis, ev, phi, p, homo, eg, gam, t_sample, sigma1, Z):
     sd_cv = float(r["sigma_cv"] * np.sqrt(nB))       # per-sample spread of the CV form
     sigma1_cv = Z * sd_cv * 27.211386245988
     plain_sd = float(np.std(y[B], ddof=1))
+    sigma1_plain_b = Z * plain_sd * 27.211386245988   # plain spread on the same set B
     return {"gpu_s_per_qp": t_sample * (sigma1_cv / 0.03) ** 2 + t_cv, "samples": n,
+            "plain_gpu_s_per_qp_same_set": t_sample * (sigma1_plain_b / 0.03) ** 2,
             "rho2_A": r["rho2"], "variance_ratio_B": (sd_cv / plain_sd) ** 2,
             "fallback": r["fallback"], "sigma1_eV": sigma1_cv, "plain_sigma1_eV": sigma1,
             "feature_and_training_s": t_cv, "cheap_samples": args.cv_cheap,
