@@ -63,3 +63,29 @@ def test_sigma_batch_of_8_matches_single_samples(si35):
         assert rel_err(x8[i:i + 1], x1) < 1e-5, i
     assert np.all(np.isfinite(sig8)) and np.all(np.isfinite(x8))
     ctx.close()
+
+
+def test_zeta_sweep_full_time_axis(si35, monkeypatch):
+    """The bench's time axis (400 output steps of 0.05 au) with the zeta states
+    taken 8 per Chebyshev sweep (50 sweeps) against one series per step: both
+    are the exact propagator to the 1e-14 truncation, so the estimates agree to
+    the FP32 rounding of 400 steps (about 2.4e-7 per step, added over the
+    steps: at most 1e-4), and X, which involves no propagation, is bitwise the
+    same."""
+    s, _ = si35
+    rs = np.random.default_rng(9)
+    phi = rs.standard_normal(s.grid.N)
+    phi /= np.sqrt(s.grid.h ** 3 * np.sum(phi * phi))
+    res = []
+    for sweep in ("1", "8"):
+        monkeypatch.setenv("SGW_ZETA_SWEEP", sweep)
+        ctx = make_ctx(s, sgw.SGW_C64, max_nvec=512)
+        lo, hi = ctx.bounds()
+        kw = dict(seed=1003, n_eta=8, n_tau=400, dt=0.05, m_sub=1, mu=-4.65, beta=2.0,
+                  ncoef=60, emin=lo, emax=hi, n_xi=10000, f_g=0.003, mode=0)
+        sig, x, _ = ctx.sigma_estimate(phi, n_zeta=2, first_sample=0, **kw)
+        ctx.close()
+        assert np.all(np.isfinite(sig))
+        res.append((sig, x))
+    assert rel_err(res[1][0], res[0][0]) < 1e-4
+    assert np.array_equal(res[1][1], res[0][1])
