@@ -432,6 +432,16 @@ __global__ __launch_bounds__(NTK) void k_kb_scatter_mma(
   const int offT = tile_offT[t], nek = tile_offT[t + 1] - offT;
   const int base = tile_base[t];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, q = lane >> 4, col = lane & 15;
+  // betaT rows of this wave's points: the first K group is loaded before the
+  // coefficient staging, so its latency overlaps that of the staging loads
+  const T *bt =
+      betaT + (int64_t)offT * KB_TP + (int64_t)(p0 + 16 * MJ * w + col) * nek + EL * q;
+  constexpr int NS = Op::SPLIT ? 2 : 1;            // C' terms (hi, lo)
+  u32x4 a_cur[MJ], a_nxt[MJ], b_cur[NS][NTL], b_nxt[NS][NTL];
+  if (nek > 0) {
+#pragma unroll
+    for (int j = 0; j < MJ; ++j) a_cur[j] = ld16(bt + (int64_t)(16 * j) * nek);
+  }
   // C' rows of this tile's entries (zero from ne up to nek), four loads in flight
   for (int i0 = 0; i0 < nek * NVB; i0 += 4 * NTK) {
     float2 val[4];
@@ -496,20 +506,19 @@ __global__ __launch_bounds__(NTK) void k_kb_scatter_mma(
   for (int j = 0; j < MJ; ++j)
 #pragma unroll
     for (int n = 0; n < NTL; ++n) acc[j][n] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const T *bt =
-      betaT + (int64_t)offT * KB_TP + (int64_t)(p0 + 16 * MJ * w + col) * nek + EL * q;
-  constexpr int NS = Op::SPLIT ? 2 : 1;            // C' terms (hi, lo)
-  u32x4 a_cur[MJ], a_nxt[MJ], b_cur[NS][NTL], b_nxt[NS][NTL];
-  auto load_group = [&](int k0, u32x4 *a, u32x4 (*b)[NTL]) {
-#pragma unroll
-    for (int j = 0; j < MJ; ++j) a[j] = ld16(bt + (int64_t)(16 * j) * nek + k0);
+  auto load_b = [&](int k0, u32x4 (*b)[NTL]) {
 #pragma unroll
     for (int h = 0; h < NS; ++h)
 #pragma unroll
       for (int n = 0; n < NTL; ++n)
         b[h][n] = ld16(sc + h * NC * pe + (16 * n + col) * pe + k0 + EL * q);
   };
-  if (nek > 0) load_group(0, a_cur, b_cur);
+  auto load_group = [&](int k0, u32x4 *a, u32x4 (*b)[NTL]) {
+#pragma unroll
+    for (int j = 0; j < MJ; ++j) a[j] = ld16(bt + (int64_t)(16 * j) * nek + k0);
+    load_b(k0, b);
+  };
+  if (nek > 0) load_b(0, b_cur);                  // a_cur holds group 0 already
   for (int k0 = 0; k0 < nek; k0 += Op::GK) {
     if (k0 + Op::GK < nek) load_group(k0 + Op::GK, a_nxt, b_nxt);
 #pragma unroll
