@@ -410,8 +410,10 @@ __global__ __launch_bounds__(NTK) void k_kb_gather_mma(
 // projector density of the system, not the 256-entry limit.  A wave
 // owns MJ M tiles of 16 points, so a workgroup covers 64 MJ points and a tile
 // takes 512 / (64 MJ) workgroups per vector block (fewer registers per wave
-// for MJ = 4, more waves per SIMD).
-template <class Op, int NVB, int MJ, int LX>
+// for MJ = 4, more waves per SIMD).  PF (always with one N tile): the old
+// destination values are loaded first, so their latency overlaps the
+// staging and the products (more registers, fewer waves per SIMD).
+template <class Op, int NVB, int MJ, int LX, bool PF>
 __global__ __launch_bounds__(NTK) void k_kb_scatter_mma(
     const float2 *coef, int64_t nvec, const int *tile_base, const int *tile_off,
     const int *tile_offT, const int *entry_proj, const typename Op::T *betaT, float2 *dst,
@@ -432,6 +434,40 @@ __global__ __launch_bounds__(NTK) void k_kb_scatter_mma(
   const int offT = tile_offT[t], nek = tile_offT[t + 1] - offT;
   const int base = tile_base[t];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, q = lane >> 4, col = lane & 15;
+  // The products are taken transposed, D'[column][point] = sum_e C'[e][column]
+  // beta_e(point) (C' from LDS as the A operand, betaT as B): lane l then
+  // holds D'[4 (l / 16) + r][l % 16], i.e. the real and imaginary parts of
+  // vectors 8 n + 2 (l / 16) (r = 0, 1) and + 1 (r = 2, 3) at point l % 16 of
+  // the M tile: two complete complex values, stored without a lane exchange.
+  // Lanes of vectors past nvec read the last vector and store nothing.
+  const int cg = q;                                 // column group: vectors 2 cg, 2 cg + 1
+  int rp[MJ];
+#pragma unroll
+  for (int j = 0; j < MJ; ++j)
+    rp[j] = tile_point_c<LX>(base, p0 + 16 * (MJ * w + j) + col, nx, ny);
+  float2 *vrow[NTL][2];
+  bool vok[NTL][2];
+#pragma unroll
+  for (int n = 0; n < NTL; ++n)
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int64_t v = v0 + 8 * n + 2 * cg + u;
+      vok[n][u] = v < nvec;
+      vrow[n][u] = dst + min(v, nvec - 1) * ld;
+    }
+  // with one N tile, or PF, the old destination values are loaded here, before
+  // the staging, so their memory latency overlaps it and the products
+  constexpr bool PREFETCH = NTL == 1 || PF;
+  float2 o[MJ][NTL][2];
+  if constexpr (PREFETCH) {
+#pragma unroll
+    for (int j = 0; j < MJ; ++j)
+#pragma unroll
+      for (int n = 0; n < NTL; ++n) {
+        o[j][n][0] = vrow[n][0][rp[j]];
+        o[j][n][1] = vrow[n][1][rp[j]];
+      }
+  }
   // betaT rows of this wave's points: the first K group is loaded before the
   // coefficient staging, so its latency overlaps that of the staging loads
   const T *bt =
@@ -466,40 +502,6 @@ __global__ __launch_bounds__(NTK) void k_kb_scatter_mma(
     }
   }
   __syncthreads();
-  // The products are taken transposed, D'[column][point] = sum_e C'[e][column]
-  // beta_e(point) (C' from LDS as the A operand, betaT as B): lane l then
-  // holds D'[4 (l / 16) + r][l % 16], i.e. the real and imaginary parts of
-  // vectors 8 n + 2 (l / 16) (r = 0, 1) and + 1 (r = 2, 3) at point l % 16 of
-  // the M tile: two complete complex values, stored without a lane exchange.
-  // Lanes of vectors past nvec read the last vector and store nothing.
-  const int cg = q;                                 // column group: vectors 2 cg, 2 cg + 1
-  int rp[MJ];
-#pragma unroll
-  for (int j = 0; j < MJ; ++j)
-    rp[j] = tile_point_c<LX>(base, p0 + 16 * (MJ * w + j) + col, nx, ny);
-  float2 *vrow[NTL][2];
-  bool vok[NTL][2];
-#pragma unroll
-  for (int n = 0; n < NTL; ++n)
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int64_t v = v0 + 8 * n + 2 * cg + u;
-      vok[n][u] = v < nvec;
-      vrow[n][u] = dst + min(v, nvec - 1) * ld;
-    }
-  // with one N tile the old destination values are loaded before the K loop,
-  // so their memory latency overlaps the products
-  constexpr bool PREFETCH = NTL == 1;
-  float2 o[MJ][NTL][2];
-  if constexpr (PREFETCH) {
-#pragma unroll
-    for (int j = 0; j < MJ; ++j)
-#pragma unroll
-      for (int n = 0; n < NTL; ++n) {
-        o[j][n][0] = vrow[n][0][rp[j]];
-        o[j][n][1] = vrow[n][1][rp[j]];
-      }
-  }
   // wave w owns the M tiles (16 points each) MJ w .. MJ w + MJ - 1 from p0
   f32x4 acc[MJ][NTL];
 #pragma unroll
@@ -558,9 +560,10 @@ __global__ __launch_bounds__(NTK) void k_kb_scatter_mma(
 // variants (autotuned per context, operand type and batch width)
 struct GatherVariant { int nvb, mt; };
 static const GatherVariant kGather[] = {{8, 2}, {8, 4}, {16, 2}, {16, 4}};
-struct ScatterVariant { int nvb, mj; };
-static const ScatterVariant kScatter[] = {{8, 8}, {16, 8}, {8, 4}, {16, 4}, {8, 2}, {16, 2}};
-constexpr int NGATHER = 4, NSCATTER = 6;
+struct ScatterVariant { int nvb, mj, pf; };
+static const ScatterVariant kScatter[] = {{8, 8, 0}, {16, 8, 0}, {8, 4, 0}, {16, 4, 0},
+                                          {8, 2, 0}, {16, 2, 0}, {16, 2, 1}};
+constexpr int NGATHER = 4, NSCATTER = 7;
 
 template <class Op>
 static void launch_gather_variant(int vi, dim3 g, hipStream_t st, const float2 *psi, int64_t ld,
@@ -587,12 +590,14 @@ static void launch_scatter_variant(int vi, dim3 g, hipStream_t st, const float2 
   constexpr int EL = 16 / (int)sizeof(typename Op::T);
   const int pe = nek_max + EL;
   const size_t lds = (Op::SPLIT ? 2 : 1) * 2 * (size_t)v.nvb * pe * sizeof(typename Op::T);
-#define SGW_S(A, B, X)                                                                           \
-  if (v.nvb == A && v.mj == B && lx == X)                                                        \
-    hipLaunchKernelGGL((k_kb_scatter_mma<Op, A, B, X>), g, dim3(NTK), lds, st, coef, nvec, tb,  \
-                       to, toT, ep, betaT, dst, ld, s1, nx, ny, ntile, nvb, pe);
-  SGW_S(8, 8, 4) SGW_S(16, 8, 4) SGW_S(8, 4, 4) SGW_S(16, 4, 4) SGW_S(8, 2, 4) SGW_S(16, 2, 4)
-  SGW_S(8, 8, 3) SGW_S(16, 8, 3) SGW_S(8, 4, 3) SGW_S(16, 4, 3) SGW_S(8, 2, 3) SGW_S(16, 2, 3)
+#define SGW_S(A, B, X, F)                                                                        \
+  if (v.nvb == A && v.mj == B && v.pf == F && lx == X)                                           \
+    hipLaunchKernelGGL((k_kb_scatter_mma<Op, A, B, X, F>), g, dim3(NTK), lds, st, coef, nvec,   \
+                       tb, to, toT, ep, betaT, dst, ld, s1, nx, ny, ntile, nvb, pe);
+  SGW_S(8, 8, 4, 0) SGW_S(16, 8, 4, 0) SGW_S(8, 4, 4, 0) SGW_S(16, 4, 4, 0) SGW_S(8, 2, 4, 0)
+  SGW_S(16, 2, 4, 0) SGW_S(16, 2, 4, 1)
+  SGW_S(8, 8, 3, 0) SGW_S(16, 8, 3, 0) SGW_S(8, 4, 3, 0) SGW_S(16, 4, 3, 0) SGW_S(8, 2, 3, 0)
+  SGW_S(16, 2, 3, 0) SGW_S(16, 2, 3, 1)
 #undef SGW_S
 }
 

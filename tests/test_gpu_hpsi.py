@@ -127,7 +127,7 @@ def test_kb_variants_bit_identical(si35, monkeypatch, prec, names):
     rs = np.random.default_rng(9)
     x = rs.standard_normal((20, s.grid.N)) + 1j * rs.standard_normal((20, s.grid.N))
     ref = None
-    for g, sc in [(g, 0) for g in range(4)] + [(0, sc) for sc in range(1, 6)]:
+    for g, sc in [(g, 0) for g in range(4)] + [(0, sc) for sc in range(1, 7)]:
         monkeypatch.setenv("SGW_FORCE_VARIANT", f"{names[0]}={g},{names[1]}={sc}")
         ctx = make_ctx(s, prec, max_nvec=32)
         xd = torch.from_numpy(x).to(torch.complex64).cuda()
