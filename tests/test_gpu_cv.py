@@ -245,9 +245,9 @@ def test_control_variate_gain_on_sgw_samples(tiny8, tiny8_eig):
     (early-stopped on 512 more), c is fitted on 1024 others (A) and the
     estimate taken on the last 1024 (B) with 50000 cheap samples for E[g].
     Every step is deterministic (seeded draws, fixed-order sums), so the
-    measured variance ratio is a fixed number of this build; it must show a
-    gain (< 0.95; measured about 0.86, nearly all from the HOMO's own
-    projection) and agree with the plain mean (no fallback)."""
+    measured variance ratio is a fixed number for this code and these seeds;
+    it must show a gain (< 0.95; measured about 0.86, nearly all from the
+    HOMO's own projection) and agree with the plain mean (no fallback)."""
     s, H = tiny8
     e, V = tiny8_eig
     ho = s.n_occ - 1
