@@ -60,11 +60,14 @@ typedef enum {
 } sgw_precision;
 
 /* Grid (Eq. 1 on a Fourier grid, Sec. 2.2).  ecut > 0 clips the kinetic
- * energy T(k) = |k|^2/2 at ecut (Sec. 3: "energy cutoff ... to the kinetic
- * energy operator"); ecut <= 0 leaves it unclipped.  Each of nx, ny, nz must
- * be one of the built FFT lengths (8, 12, 16, 24, 32, 40, 48, 56, 64, 80,
- * 96, 112, 128) with nx == ny, and nx*ny*sizeof(complex) small enough for one
- * xy plane to fit in LDS; otherwise SGW_EUNSUPPORTED. */
+ * energy T(k) = |k|^2/2 at ecut (Sec. 3 applies such a cutoff to the kinetic
+ * operator); ecut <= 0 leaves it unclipped.  Each of nx, ny, nz must be one
+ * of the built FFT lengths (8, 12, 16, 24, 32, 40, 48, 56, 64, 80, 96, 112,
+ * 128, 160), with nx == ny and nx a multiple of the z pencils' width (16 when
+ * nz % 16 == 0, else 8 when nz % 8 == 0, else 4); otherwise SGW_EUNSUPPORTED.
+ * The x and y transforms run on whole xy planes in LDS when a plane fits
+ * (n <= 80 in complex FP32, n <= 56 in complex FP64), else on x lines and y
+ * pencils (one more pass over the batch, same results). */
 typedef struct {
   int32_t nx, ny, nz;
   double h;               /* grid spacing, bohr */

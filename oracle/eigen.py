@@ -79,3 +79,19 @@ def lanczos_bounds(H, k, seed=0, pad=0.01):
     lo = max(lo_w, theta[0] - r[0] - pad * width)
     hi = min(hi_w, theta[-1] + r[-1] + pad * width)
     return lo, hi
+
+
+def highest_eigenvalue(H, tol=1e-10, v0_seed=11):
+    """The largest eigenvalue of H by Lanczos (ARPACK, largest algebraic)
+    on the unshifted operator; the upper end of the interval that every
+    Chebyshev map of Sec. 2.1 needs."""
+    N = H.grid.N
+
+    def mv(x):
+        return H.apply(np.asarray(x, dtype=np.float64).ravel())
+
+    op = spla.LinearOperator((N, N), matvec=mv, dtype=np.float64)
+    v0 = np.random.default_rng(v0_seed).standard_normal(N)
+    e = spla.eigsh(op, k=1, which="LA", tol=tol, v0=v0, ncv=min(N, 40),
+                   return_eigenvectors=False)
+    return float(e[0])

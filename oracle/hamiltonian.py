@@ -13,8 +13,8 @@ Readings (the paper gives no pseudopotential tables):
   with d the minimum-image displacement r - R_p, cut to zero where
   |d| > rcut_over_rc * rc, and N_p chosen so that dV sum beta_p^2 = 1 on the
   grid.  V_NL = sum_p |beta_p> E_p <beta_p|.
-* Kinetic cutoff (Sec. 3, "energy cutoff of 28 Hartrees to the kinetic
-  energy operator"): T(k) = min(|k|^2/2, E_cut) when E_cut > 0.
+* Kinetic cutoff (Sec. 3 clips the kinetic operator at 28 Ha to bound the
+  spectral width): T(k) = min(|k|^2/2, E_cut) when E_cut > 0.
 """
 import numpy as np
 import scipy.sparse as sp

@@ -11,7 +11,8 @@ Readings (the paper defers the equations to its references):
 * H^c(t) = H_0 + v_H[n^c(t)] - v_H[n(0)] for either copy c, with
   n^c(t) = w sum_l |eta^c_l(r, t)|^2, w = 2 / N_eta (closed shell).
 * The perturbation is an impulsive kick eta^lambda(0) = exp(-i lambda dv) eta
-  with dv = v_H[phi * zeta-bar] (the "vector related to zeta-bar", Sec. 2.1).
+  with dv = v_H[phi * zeta-bar] (Sec. 2.1 perturbs with a potential built
+  from the random vector zeta-bar).
 * u^R(t) = (v_H[n^lambda(t)] - v_H[n(t)]) / lambda.  The canonical form used
   by the library is its lambda -> 0 limit: the exact tangent map of the
   Strang step, carried by delta-eta with delta-eta(0) = -i dv eta(0) and

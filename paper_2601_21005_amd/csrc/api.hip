@@ -515,6 +515,9 @@ sgw_status sgw_create(const sgw_grid *grid, const double *v_loc, const sgw_proje
                     fft_size_supported(grid->nz, dbl),
                 SGW_EUNSUPPORTED, "grid size not built into this library");
     SGW_REQUIRE(grid->nx == grid->ny, SGW_EUNSUPPORTED, "nx must equal ny");
+    SGW_REQUIRE(fft_pencils_cover(grid->nx, grid->ny, grid->nz, dbl), SGW_EUNSUPPORTED,
+                "nx must be a multiple of the z pencils' width (16 when nz % 16 == 0, "
+                "else 8 when nz % 8 == 0, else 4)");
     std::unique_ptr<sgw_ctx> c(new sgw_ctx());
     c->nx = grid->nx; c->ny = grid->ny; c->nz = grid->nz;
     c->N = (int64_t)c->nx * c->ny * c->nz;

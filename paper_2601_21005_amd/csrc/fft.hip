@@ -423,6 +423,17 @@ bool fft_size_supported(int n, bool dbl) {
   return dbl ? get_ops<double>(n, o) : get_ops<float>(n, o);
 }
 
+// The pencil passes launch (nx / width) workgroups per row of columns, the
+// width being that of the pencil length: every column is covered only when
+// nx is a multiple of the z pencils' width (and of the y pencils', which
+// holds whenever nx == ny).
+bool fft_pencils_cover(int nx, int ny, int nz, bool dbl) {
+  SizeOps oy, oz;
+  const bool ok = dbl ? (get_ops<double>(ny, oy) && get_ops<double>(nz, oz))
+                      : (get_ops<float>(ny, oy) && get_ops<float>(nz, oz));
+  return ok && nx % oz.tx == 0 && nx % oy.tx == 0;
+}
+
 template <typename R>
 void fft3d_apply_t(sgw_ctx *ctx, const void *src, void *tmp, void *dst, int64_t nvec,
                    int64_t ld, MulMode mul, double tau, PlaneMode inv_mode,

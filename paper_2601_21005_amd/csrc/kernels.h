@@ -6,6 +6,7 @@
 namespace sgw {
 
 bool fft_size_supported(int n, bool dbl);
+bool fft_pencils_cover(int nx, int ny, int nz, bool dbl);
 
 // ---- vectors
 // acc[v] = (cre + i cim) x[v]

@@ -197,21 +197,45 @@ def test_adam_steps_match_oracle(net_case):
     assert np.max(np.abs(got - th)) < 1e-6 * (1 + np.max(np.abs(th)))
 
 
+def model_train(theta, xh, y, steps, din, h1, h2, lr=1e-3):
+    """Full-batch Adam driven by the rounding model's gradient (BF16 GEMM
+    operands, FP64 otherwise), parameters kept as FP32 masters like the
+    device's; returns the loss before each step."""
+    opt = cv.Adam(theta.size, lr=lr)
+    hist = []
+    W1, b1, W2, b2, w3, b3 = cv.unpack(theta, din, h1, h2)
+    for _ in range(steps):
+        g, _, _ = model_forward(theta, xh, din, h1, h2)
+        hist.append(float(np.mean((g - y) ** 2)))
+        theta = opt.step(theta, model_gradient(theta, xh, y, din, h1, h2))
+        theta = theta.astype(np.float32).astype(np.float64)
+    return np.array(hist)
+
+
 def test_training_follows_oracle(net_case):
-    """200 full-batch Adam steps on the device (BF16 products) and in the
-    oracle (FP64) from the same start.  The first 20 losses agree to 5%
-    (the gradients differ by BF16 rounding, which Adam's per-parameter
-    normalisation passes on); later the two descents separate, so the end
-    is held only to a factor 2 and to a > 3x drop for both."""
+    """200 full-batch Adam steps on the device (BF16 products) against two
+    host trajectories from the same start: the FP64 oracle, and the same
+    Adam driven by the rounding model of the device's arithmetic (BF16 GEMM
+    operands, FP32 parameters).  The first 20 losses agree with the oracle to
+    5%.  Late in training the loss falls to the floor that BF16 operands
+    leave, where the FP64 oracle keeps descending: the rounding model's own
+    final loss differs from the oracle's by about x1.5, so the device is held
+    to the rounding model (5% over the first 100 steps, x1.3 at the end) and
+    to the oracle only within that model-to-oracle gap times 1.3.  Neither
+    host trajectory descends monotonically (full-batch Adam overshoots near
+    the floor), so no monotonicity is asserted; both must drop > 3x."""
     c = net_case
     m = make_net(c)
     hist = m.train(f32(c["x"]), f32(c["y"]), 200, lr=1e-3)
     m.close()
     _, ho = cv.train(c["theta"], c["xh"], c["y"], 200, lr=1e-3)
+    hm = model_train(c["theta"], c["xh"], c["y"], 200, c["din"], c["h1"], c["h2"])
     assert abs(hist[0] - ho[0]) < 4 * U_BF16 * ho[0]
     assert np.max(np.abs(hist[:20] / ho[:20] - 1)) < 0.05
+    assert np.max(np.abs(hist[:100] / hm[:100] - 1)) < 0.05
+    assert abs(np.log(hist[-1] / hm[-1])) < np.log(1.3)
+    assert abs(np.log(hist[-1] / ho[-1])) < abs(np.log(hm[-1] / ho[-1])) + np.log(1.3)
     assert hist[-1] < hist[0] / 3 and ho[-1] < ho[0] / 3
-    assert abs(np.log(hist[-1] / ho[-1])) < np.log(2.0)
 
 
 def test_cheap_moments_match_model(tiny8, net_case):
@@ -244,10 +268,10 @@ def test_control_variate_gain_on_sgw_samples(tiny8, tiny8_eig):
     |<phi_k|zeta_i>|^2 over the 64 lowest states is trained on 1536 of them
     (early-stopped on 512 more), c is fitted on 1024 others (A) and the
     estimate taken on the last 1024 (B) with 50000 cheap samples for E[g].
-    Every step is deterministic (seeded draws, fixed-order sums), so the
-    measured variance ratio is a fixed number for this code and these seeds;
-    it must show a gain (< 0.95; measured about 0.86, nearly all from the
-    HOMO's own projection) and agree with the plain mean (no fallback)."""
+    The gain must be significant: the variance ratio on B (measured about
+    0.86, nearly all from the HOMO's own projection) plus three of its
+    jackknife standard errors over the B samples stays below 1, and the
+    estimate agrees with the plain mean (no fallback)."""
     s, H = tiny8
     e, V = tiny8_eig
     ho = s.n_occ - 1
@@ -294,8 +318,24 @@ def test_control_variate_gain_on_sgw_samples(tiny8, tiny8_eig):
     r = sgw.sgw_cv_estimate(y[A], g[A], y[B], g[B], gm, gvar, 50000)
     plain_B = y[B].std(ddof=1) / np.sqrt(1024)
     ratio = (r["sigma_cv"] / plain_B) ** 2
-    print(f"\ncontrol variate: rho2(A) {r['rho2']:.3f}  variance ratio {ratio:.3f}  "
-          f"cv {r['estimate']:.5f} +- {r['sigma_cv']:.5f}  plain {r['plain']:.5f}  "
-          f"fallback {r['fallback']}", flush=True)
+    se = variance_ratio_jackknife_se(y[B], g[B], r["c"], r["c"] ** 2 * gvar / 50000)
+    print(f"\ncontrol variate: rho2(A) {r['rho2']:.3f}  variance ratio {ratio:.3f} "
+          f"+- {se:.3f}  cv {r['estimate']:.5f} +- {r['sigma_cv']:.5f}  "
+          f"plain {r['plain']:.5f}  fallback {r['fallback']}", flush=True)
     assert not r["fallback"]
-    assert ratio < 0.95
+    assert ratio + 3.0 * se < 1.0
+
+
+def variance_ratio_jackknife_se(y, g, c, var_mean_term):
+    """Jackknife standard error, over the evaluation samples, of the variance
+    ratio (Var(y - c g)/n + var_mean_term) / (Var(y)/n) with c fixed (it is
+    fitted on another set)."""
+    n = y.size
+    r = y - c * g
+
+    def ratio(yy, rr):
+        m = yy.size
+        return (np.var(rr, ddof=1) / m + var_mean_term) / (np.var(yy, ddof=1) / m)
+
+    loo = np.array([ratio(np.delete(y, i), np.delete(r, i)) for i in range(n)])
+    return float(np.sqrt((n - 1) / n * np.sum((loo - loo.mean()) ** 2)))

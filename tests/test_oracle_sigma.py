@@ -143,3 +143,52 @@ def test_xi_mode_assembly_and_unbiasedness(tiny8, tiny8_eig):
     ref = sig_e[p.n_tau + 1:]
     assert np.all(np.abs(m.real - ref.real) < 4.5 * se_r)
     assert np.all(np.abs(m.imag - ref.imag) < 4.5 * se_i)
+
+
+def test_stochastic_eta_weight_matches_occupied_density(tiny8, tiny8_eig):
+    """The density weight of the stochastic eta set (Sec. 2.1, Eq. 5 with
+    closed-shell occupation): with eta_l = F(H) eta-bar_l and +-1/sqrt(dV)
+    noise, E[eta eta^T] = sum_j f_j^2 phi_j phi_j^T, so w sum_l eta_l eta_l^T
+    has the mean of the deterministic set {f_j phi_j} taken with weight 2
+    exactly when w = 2 / N_eta.
+
+    After one Strang substep (m_sub = 1) the response density is bilinear in
+    the eta set: u^R(0) = 0, V(0) = V_loc, so eta(tau) = U eta and
+    delta-eta(tau) = U (-i dv eta) with one linear U for every l, and
+    u^R(tau) = v_H[w sum_l 2 Re(conj(U eta_l) U(-i dv eta_l))].  Its mean over
+    eta-bar draws (zeta-bar held fixed, so dv is the same) therefore equals
+    the deterministic u^R(tau) with no O(1/N_eta) bias.  The same draws pin
+    the exchange: E[X_i] = -sum_j f_j^2 (phi phi_j | v | phi phi_j)."""
+    s, H = tiny8
+    e, V = tiny8_eig
+    g = H.grid
+    n_occ = s.n_occ
+    p = _params(H, e, n_occ, n_eta=16, n_tau=1, m_sub=1, dt=0.3, beta=4.0,
+                ncoef=cheb.suggested_ncoef(0.5 * (e[n_occ - 1] + e[n_occ]), 4.0,
+                                           *H.bounds(), tol=1e-13, nmax=8192))
+    phi = V[n_occ - 1]
+    zb = rng.white_noise(5, rng.ZETA, 0, 0, g.N, g.dV)
+    # the filter the recurrence applies, evaluated at the eigenvalues
+    a = cheb.fermi_coefficients(p.mu, p.beta, p.emin, p.emax, p.ncoef)
+    c0, r0 = 0.5 * (p.emax + p.emin), 0.5 * (p.emax - p.emin)
+    f = np.polynomial.chebyshev.chebval((e - c0) / r0, a)
+    _, _, det = sample_sigma(H, phi, p, 0, return_parts=True, zb=zb,
+                             eta_det=f[:, None] * V, eta_weight=2.0)
+    u_det = det["uR"][1]
+    S = 120
+    us, xs = [], []
+    for i in range(S):
+        _, X, parts = sample_sigma(H, phi, p, i, return_parts=True, zb=zb)
+        us.append(parts["uR"][1])
+        xs.append(X)
+    us, xs = np.array(us), np.array(xs)
+    m = us.mean(axis=0)
+    se2 = np.sum(us.var(axis=0, ddof=1)) / S            # E||m - u_det||^2
+    nd = np.linalg.norm(u_det)
+    # the test resolves a factor-2 error in w: 3 standard errors < nd / 4
+    assert 3.0 * np.sqrt(se2) < 0.25 * nd
+    assert np.linalg.norm(m - u_det) ** 2 < 9.0 * se2
+    pp = phi[None, :] * V
+    x_ref = -np.sum(f ** 2 * g.dV * np.sum(pp * hartree(g, pp), axis=1))
+    assert abs(xs.mean() - x_ref) < 4.0 * xs.std(ddof=1) / np.sqrt(S)
+    assert 4.0 * xs.std(ddof=1) / np.sqrt(S) < 0.25 * abs(x_ref)
