@@ -42,12 +42,25 @@ class Projectors:
         self.rc = np.asarray(rc, dtype=np.float64)
         self.ekb = np.asarray(ekb, dtype=np.float64)
         self.np_ = len(self.l)
-        r = grid.coords()
+        nx, ny, nz = grid.n
+        L = np.asarray(grid.L)
         rows, cols, vals = [], [], []
         for p in range(self.np_):
-            d = grid.min_image(r - pos[self.atom_of[p]])
-            d2 = np.sum(d * d, axis=1)
             rcut = rcut_over_rc * self.rc[p]
+            # candidate points: the box of grid lines whose per-axis
+            # minimum-image offset is within rcut (it holds the whole sphere);
+            # flat indices ascending, as over the full grid
+            ax = []
+            for a, m in enumerate((nx, ny, nz)):
+                da = np.mod(grid.h * np.arange(m) - pos[self.atom_of[p], a] + 0.5 * L[a],
+                            L[a]) - 0.5 * L[a]
+                ax.append(np.nonzero(np.abs(da) <= rcut)[0])
+            ix, iy, iz = ax
+            cand = (ix[None, None, :] + nx * (iy[None, :, None] + ny * iz[:, None, None])).ravel()
+            cand.sort()
+            rr = grid.h * np.stack([cand % nx, (cand // nx) % ny, cand // (nx * ny)], axis=1)
+            d = grid.min_image(rr - pos[self.atom_of[p]])
+            d2 = np.sum(d * d, axis=1)
             inside = d2 <= rcut * rcut
             g = np.exp(-d2[inside] / (2.0 * self.rc[p] ** 2))
             if self.l[p] == 1:
@@ -55,7 +68,7 @@ class Projectors:
             elif self.l[p] != 0:
                 raise ValueError("only s and p projectors are modelled")
             nrm = np.sqrt(grid.dV * np.sum(g * g))
-            idx = np.nonzero(inside)[0]
+            idx = cand[inside]
             rows.append(idx)
             cols.append(np.full(idx.size, p))
             vals.append(g / nrm)
