@@ -143,6 +143,26 @@ sgw_status sgw_lanczos_bounds(sgw_ctx *ctx, int32_t k, uint64_t seed, double pad
 sgw_status sgw_apply_H(sgw_ctx *ctx, const void *psi, void *hpsi,
                        int64_t nvec, int64_t ld);
 
+/* sgw_apply_H for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same operation and result, with no hipMalloc, hipFree or other
+ * allocating call.  The projector partial sums and coefficients live in one
+ * static 64 MiB device array per GPU, reserved when the library is loaded
+ * (its address is looked up by the first sgw_create on each device); the
+ * FFT intermediate lives in hpsi.  Vectors are processed in chunks of as
+ * many as that array holds (per vector: 8 or 16 bytes times the projector
+ * entries of all grid tiles plus the projectors); SGW_EUNSUPPORTED when not
+ * even one vector fits.  Kernel variants are not timed: the choice already
+ * made for this batch width, the tuning cache's, or the first (all variants
+ * give identical results).  The context's device must be current
+ * (SGW_EINVAL otherwise), psi and hpsi must not overlap, and the launch
+ * timers are off during the call.  Every call on one GPU shares its array:
+ * calls that overlap in time on one GPU (other streams, other contexts,
+ * other threads) race and must be serialised by the caller.  Nothing in the
+ * array has to start at zero (each call overwrites what it reads). */
+sgw_status sgw_apply_H_noalloc(sgw_ctx *ctx, const void *psi, void *hpsi,
+                               int64_t nvec, int64_t ld);
+
 /* Chebyshev coefficients of the Fermi filter F(E) = 1/(1 + e^{beta(E-mu)})
  * on [emin, emax] (Eq. 3 with the step smoothed), by Chebyshev-Gauss
  * quadrature on M = 4 ncoef nodes:

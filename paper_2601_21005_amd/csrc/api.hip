@@ -5,6 +5,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <chrono>
+#include <mutex>
 #include <numeric>
 #include <thread>
 
@@ -13,6 +14,11 @@
 #include "rng.h"
 
 using namespace sgw;
+
+// Scratch of sgw_apply_H_noalloc (see below): 64 MiB per GPU, reserved when
+// the library is loaded.
+constexpr size_t kNoAllocBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
 
 namespace {
 
@@ -466,6 +472,75 @@ void apply_h(sgw_ctx *ctx, const void *psi, void *hpsi, int64_t nvec, int64_t ld
   }
 }
 
+// ---------------------------------------------------------------- no-alloc H
+// Scratch of sgw_apply_H_noalloc: one statically sized device array per GPU
+// (module-scope, so loading the library reserves it; nothing is allocated
+// per call).  Host code uses only the address that hipGetSymbolAddress gives
+// for the current device, kept per device from the first sgw_create there.
+constexpr int kNoAllocMaxDev = 64;
+std::mutex g_noalloc_mu;
+void *g_noalloc_ptr[kNoAllocMaxDev] = {};
+
+// with `dev` current: look up this device's copy of the array once
+void noalloc_setup(int dev) {
+  SGW_REQUIRE(dev >= 0 && dev < kNoAllocMaxDev, SGW_EUNSUPPORTED, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (g_noalloc_ptr[dev]) return;
+  void *p = nullptr;
+  SGW_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  SGW_REQUIRE(p != nullptr, SGW_EHIP, "no device address for the no-alloc scratch");
+  g_noalloc_ptr[dev] = p;
+}
+
+void *noalloc_ptr(int dev) {
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  return (dev >= 0 && dev < kNoAllocMaxDev) ? g_noalloc_ptr[dev] : nullptr;
+}
+
+size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+// apply_h with the projector partials and coefficients in `scr` (kNoAllocBytes)
+// and the FFT intermediate in hpsi itself; chunks of as many vectors as the
+// scratch holds.  Kernel variants are not timed here (all give identical
+// results): the remembered, cached or forced choice, else the first.
+void apply_h_noalloc(sgw_ctx *ctx, const void *psi, void *hpsi, int64_t nvec, int64_t ld,
+                     void *scr) {
+  int64_t chunk = nvec;
+  size_t part_per = 0, coef_per = 0;
+  if (ctx->has_kb) {
+    part_per = kb_partial_bytes_per_vec(ctx);
+    coef_per = ctx->csize() * (size_t)ctx->kb.nproj;
+    // both blocks 256-byte aligned: at most 512 bytes of padding per chunk
+    chunk = std::min<int64_t>(nvec, (int64_t)((kNoAllocBytes - 512) / (part_per + coef_per)));
+    SGW_REQUIRE(chunk >= 1, SGW_EUNSUPPORTED,
+                "sgw_apply_H_noalloc: one vector's projector scratch exceeds the 64 MiB "
+                "static buffer");
+  }
+  struct Restore {
+    sgw_ctx *c;
+    int kt;
+    ~Restore() { c->no_tune = false; c->ktimer = kt; }
+  } restore{ctx, ctx->ktimer};
+  ctx->no_tune = true;
+  ctx->ktimer = 0;                       // the launch timers create events
+  for (int64_t v0 = 0; v0 < nvec; v0 += chunk) {
+    const int64_t nv = std::min(chunk, nvec - v0);
+    const char *x = static_cast<const char *>(psi) + v0 * ld * ctx->csize();
+    char *y = static_cast<char *>(hpsi) + v0 * ld * ctx->csize();
+    void *kbC = nullptr;
+    if (ctx->has_kb) {
+      void *partial = scr;
+      kbC = static_cast<char *>(scr) + align256(part_per * nv);
+      kb_gather_e(ctx, x, nv, ld, kbC, partial);
+    }
+    EpiArgs e;
+    e.x = x;
+    e.vloc = ctx->d_vloc.p;
+    fft3d_apply(ctx, x, y, y, nv, ld, MUL_KIN, 0.0, PLANE_INV_HPSI, e, ld);
+    if (ctx->has_kb) kb_scatter(ctx, kbC, nv, y, ld, 1.0, 0.0, nullptr, 0.0, 0.0);
+  }
+}
+
 // Issue work on another stream of the context, with its own scratch buffers.
 struct OnStream {
   sgw_ctx *c;
@@ -534,6 +609,8 @@ sgw_status sgw_create(const sgw_grid *grid, const double *v_loc, const sgw_proje
       c->arch = prop.gcnArchName;
       const size_t colon = c->arch.find(':');           // drop feature suffixes
       if (colon != std::string::npos) c->arch.resize(colon);
+      c->dev = dev;
+      noalloc_setup(dev);
     }
     if (const char *fc = std::getenv("SGW_FILTER_CHUNK")) c->filter_chunk = std::atoi(fc);
     if (const char *ov = std::getenv("SGW_ZETA_OVERLAP")) c->overlap = std::atoi(ov) != 0;
@@ -615,6 +692,27 @@ sgw_status sgw_apply_H(sgw_ctx *ctx, const void *psi, void *hpsi, int64_t nvec, 
     check_ptr(hpsi, "hpsi");
     SGW_REQUIRE(psi != hpsi, SGW_EINVAL, "psi and hpsi must not overlap");
     apply_h(ctx, psi, hpsi, nvec, ld);
+  });
+}
+
+sgw_status sgw_apply_H_noalloc(sgw_ctx *ctx, const void *psi, void *hpsi, int64_t nvec,
+                               int64_t ld) {
+  if (!ctx) return SGW_EINVAL;
+  return guarded(ctx, [&] {
+    SGW_REQUIRE(nvec >= 0 && ld >= ctx->N, SGW_EINVAL, "nvec < 0 or ld < N");
+    if (nvec == 0) return;
+    check_ptr(psi, "psi");
+    check_ptr(hpsi, "hpsi");
+    const size_t bytes = ctx->csize() * (size_t)((nvec - 1) * ld + ctx->N);
+    const char *a = static_cast<const char *>(psi), *b = static_cast<const char *>(hpsi);
+    SGW_REQUIRE(a + bytes <= b || b + bytes <= a, SGW_EINVAL, "psi and hpsi must not overlap");
+    int cur = -1;
+    SGW_HIP(hipGetDevice(&cur));
+    SGW_REQUIRE(cur == ctx->dev, SGW_EINVAL,
+                "sgw_apply_H_noalloc: the context's device must be current");
+    void *scr = noalloc_ptr(cur);
+    SGW_REQUIRE(scr != nullptr, SGW_EHIP, "no-alloc scratch not set up on this device");
+    apply_h_noalloc(ctx, psi, hpsi, nvec, ld, scr);
   });
 }
 

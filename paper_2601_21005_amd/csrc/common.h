@@ -148,6 +148,10 @@ struct sgw_ctx {
   };
   int ktimer = 0;
   KTimer kt[2];
+  int dev = 0;                 // HIP device the context was created on
+  // set while a call must not time kernel variants (sgw_apply_H_noalloc):
+  // tune() then returns the forced, remembered or cached choice, else 0
+  bool no_tune = false;
   // second stream of the context (non-blocking, default priority): the zeta
   // propagation of sgw_sigma_estimate runs on it beside the TDH steps.  While
   // work is issued there, `ns` suffixes every scratch buffer name so the two
@@ -190,9 +194,10 @@ struct sgw_ctx {
     if (it != tuned.end()) return it->second;
     int cached = -1;
     if (sgw::tune_cache_lookup(key, cached) && cached >= 0 && cached < nvar) {
-      tuned[key] = cached;
+      if (!no_tune) tuned[key] = cached;
       return cached;
     }
+    if (no_tune) return 0;
     // trials run alone on the device: work of other streams (the context's
     // second stream, other contexts) would otherwise skew their times
     (void)hipDeviceSynchronize();
@@ -278,14 +283,20 @@ struct EpiArgs {
 
 // Full forward+multiply+inverse 3D transform of nvec vectors of `src` (ld),
 // result written through the inverse pass mode into dst / epilogue outputs.
+// tmp holds nvec vectors ld_tmp apart (0: N); it may be dst itself when
+// ld_tmp equals ld (every pass after the first works in place per plane,
+// pencil or line).
 void fft3d_apply(sgw_ctx *ctx, const void *src, void *tmp, void *dst, int64_t nvec,
                  int64_t ld, MulMode mul, double tau, PlaneMode inv_mode,
-                 const EpiArgs &epi);
+                 const EpiArgs &epi, int64_t ld_tmp = 0);
 
 // KB (kb.hip)
 // C[p][v] = <beta_p|psi_v>  (kb_gather_e: times E_p)
 void kb_gather(sgw_ctx *ctx, const void *psi, int64_t nvec, int64_t ld, void *coef_out);
-void kb_gather_e(sgw_ctx *ctx, const void *psi, int64_t nvec, int64_t ld, void *coef_out);
+void kb_gather_e(sgw_ctx *ctx, const void *psi, int64_t nvec, int64_t ld, void *coef_out,
+                 void *partial = nullptr);
+// bytes of per-(tile, projector) partial sums the gather needs per vector
+size_t kb_partial_bytes_per_vec(const sgw_ctx *ctx);
 // C' = K C  (K complex [nproj][nproj] in the working precision)
 void kb_mix_dense(sgw_ctx *ctx, const void *K, const void *coef_in, void *coef_out,
                   int64_t nvec);

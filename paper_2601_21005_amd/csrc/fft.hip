@@ -437,7 +437,7 @@ bool fft_pencils_cover(int nx, int ny, int nz, bool dbl) {
 template <typename R>
 void fft3d_apply_t(sgw_ctx *ctx, const void *src, void *tmp, void *dst, int64_t nvec,
                    int64_t ld, MulMode mul, double tau, PlaneMode inv_mode,
-                   const EpiArgs &epi) {
+                   const EpiArgs &epi, int64_t ldt) {
   using C = cplx<R>;
   SizeOps ox, oy, oz;
   SGW_REQUIRE(get_ops<R>(ctx->nx, ox) && get_ops<R>(ctx->ny, oy) && get_ops<R>(ctx->nz, oz),
@@ -459,7 +459,7 @@ void fft3d_apply_t(sgw_ctx *ctx, const void *src, void *tmp, void *dst, int64_t 
   for (int64_t v0 = 0; v0 < nvec; v0 += 65535) {
     const int64_t nv = std::min<int64_t>(65535, nvec - v0);
     const C *srcv = static_cast<const C *>(src) + v0 * ld;
-    C *tmpv = static_cast<C *>(tmp) + v0 * N;
+    C *tmpv = static_cast<C *>(tmp) + v0 * ldt;
     C *dstv = dst ? static_cast<C *>(dst) + v0 * ld : nullptr;
     PassArgs a = base;
     // shift epilogue vector pointers to this chunk
@@ -472,7 +472,7 @@ void fft3d_apply_t(sgw_ctx *ctx, const void *src, void *tmp, void *dst, int64_t 
     a.ld_x = ld;
     // forward xy
     PassArgs f = a;
-    f.src = srcv; f.dst = tmpv; f.ld_src = ld; f.ld_dst = N; f.mode = PLANE_FWD; f.inverse = 0;
+    f.src = srcv; f.dst = tmpv; f.ld_src = ld; f.ld_dst = ldt; f.mode = PLANE_FWD; f.inverse = 0;
     if (use_plane) {
       f.tw0 = twx; f.tw1 = twy;
       ox.plane(dim3(ctx->nz, nv), st, f);
@@ -480,13 +480,13 @@ void fft3d_apply_t(sgw_ctx *ctx, const void *src, void *tmp, void *dst, int64_t 
       f.tw0 = twx;
       ox.xlines(dim3((ctx->ny * ctx->nz + ox.nl - 1) / ox.nl, nv), st, f);
       PassArgs py = a;
-      py.dst = tmpv; py.ld_dst = N; py.axis = 1; py.tw0 = twy; py.inverse = 0; py.mul = MUL_NONE;
+      py.dst = tmpv; py.ld_dst = ldt; py.axis = 1; py.tw0 = twy; py.inverse = 0; py.mul = MUL_NONE;
       oy.pencil(dim3((ctx->nx / oy.tx) * ctx->nz, nv), st, py);
     }
     SGW_HIP(hipGetLastError());
     // z: forward, multiply, inverse
     PassArgs pz = a;
-    pz.dst = tmpv; pz.ld_dst = N; pz.axis = 2; pz.tw0 = twz; pz.inverse = 0; pz.mul = mul;
+    pz.dst = tmpv; pz.ld_dst = ldt; pz.axis = 2; pz.tw0 = twz; pz.inverse = 0; pz.mul = mul;
     // z pencils: rows of 32 complex when the lengths allow it (SGW_FORCE_VARIANT
     // pencil=0 keeps rows of 16); every column is the same 1D transform either way
     const auto fp = ctx->forced.find("pencil");
@@ -499,11 +499,11 @@ void fft3d_apply_t(sgw_ctx *ctx, const void *src, void *tmp, void *dst, int64_t 
     SGW_HIP(hipGetLastError());
     // inverse xy with the epilogue
     PassArgs b = a;
-    b.src = tmpv; b.ld_src = N; b.dst = dstv; b.ld_dst = ld; b.mode = inv_mode; b.inverse = 1;
+    b.src = tmpv; b.ld_src = ldt; b.dst = dstv; b.ld_dst = ld; b.mode = inv_mode; b.inverse = 1;
     const bool timed = (ctx->ktimer & 1) && inv_mode == PLANE_INV_CHEB && ctx->ns.empty();
     if (!use_plane) {
       PassArgs py = a;
-      py.dst = tmpv; py.ld_dst = N; py.axis = 1; py.tw0 = twy; py.inverse = 1; py.mul = MUL_NONE;
+      py.dst = tmpv; py.ld_dst = ldt; py.axis = 1; py.tw0 = twy; py.inverse = 1; py.mul = MUL_NONE;
       oy.pencil(dim3((ctx->nx / oy.tx) * ctx->nz, nv), st, py);
     }
     if (timed) SGW_HIP(hipEventRecord(ctx->kt[0].event(0), st));
@@ -525,12 +525,13 @@ void fft3d_apply_t(sgw_ctx *ctx, const void *src, void *tmp, void *dst, int64_t 
 
 void fft3d_apply(sgw_ctx *ctx, const void *src, void *tmp, void *dst, int64_t nvec,
                  int64_t ld, MulMode mul, double tau, PlaneMode inv_mode,
-                 const EpiArgs &epi) {
+                 const EpiArgs &epi, int64_t ld_tmp) {
   if (nvec <= 0) return;
+  const int64_t ldt = ld_tmp > 0 ? ld_tmp : ctx->N;
   if (ctx->dbl)
-    fft3d_apply_t<double>(ctx, src, tmp, dst, nvec, ld, mul, tau, inv_mode, epi);
+    fft3d_apply_t<double>(ctx, src, tmp, dst, nvec, ld, mul, tau, inv_mode, epi, ldt);
   else
-    fft3d_apply_t<float>(ctx, src, tmp, dst, nvec, ld, mul, tau, inv_mode, epi);
+    fft3d_apply_t<float>(ctx, src, tmp, dst, nvec, ld, mul, tau, inv_mode, epi, ldt);
 }
 
 }  // namespace sgw

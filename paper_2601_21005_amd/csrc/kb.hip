@@ -649,10 +649,11 @@ void kb_upload_operands(sgw_ctx *ctx) {
 // ---------------------------------------------------------------- launchers
 template <typename R>
 static void gather_t(sgw_ctx *ctx, const void *psi, int64_t nvec, int64_t ld, void *out,
-                     bool use_e) {
+                     bool use_e, void *partial_ext) {
   constexpr int NV = KBV<R>::NV;
   using C = cplx<R>;
-  C *partial = ctx->buf("kb_partial", sizeof(C) * (size_t)ctx->kb_nentry * nvec).as<C>();
+  C *partial = partial_ext ? static_cast<C *>(partial_ext)
+                           : ctx->buf("kb_partial", sizeof(C) * (size_t)ctx->kb_nentry * nvec).as<C>();
   SGW_REQUIRE(ctx->kb_ntile <= 65535, SGW_EUNSUPPORTED, "KB gather: too many tiles");
   if constexpr (sizeof(R) == 4) {
     SGW_REQUIRE(ld % 2 == 0, SGW_EUNSUPPORTED,
@@ -694,13 +695,18 @@ static void gather_t(sgw_ctx *ctx, const void *psi, int64_t nvec, int64_t ld, vo
 }
 
 void kb_gather(sgw_ctx *ctx, const void *psi, int64_t nvec, int64_t ld, void *coef_out) {
-  if (ctx->dbl) gather_t<double>(ctx, psi, nvec, ld, coef_out, false);
-  else gather_t<float>(ctx, psi, nvec, ld, coef_out, false);
+  if (ctx->dbl) gather_t<double>(ctx, psi, nvec, ld, coef_out, false, nullptr);
+  else gather_t<float>(ctx, psi, nvec, ld, coef_out, false, nullptr);
 }
 
-void kb_gather_e(sgw_ctx *ctx, const void *psi, int64_t nvec, int64_t ld, void *coef_out) {
-  if (ctx->dbl) gather_t<double>(ctx, psi, nvec, ld, coef_out, true);
-  else gather_t<float>(ctx, psi, nvec, ld, coef_out, true);
+void kb_gather_e(sgw_ctx *ctx, const void *psi, int64_t nvec, int64_t ld, void *coef_out,
+                 void *partial) {
+  if (ctx->dbl) gather_t<double>(ctx, psi, nvec, ld, coef_out, true, partial);
+  else gather_t<float>(ctx, psi, nvec, ld, coef_out, true, partial);
+}
+
+size_t kb_partial_bytes_per_vec(const sgw_ctx *ctx) {
+  return ctx->csize() * (size_t)ctx->kb_nentry;
 }
 
 void kb_mix_dense(sgw_ctx *ctx, const void *K, const void *coef_in, void *coef_out,

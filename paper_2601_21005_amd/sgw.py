@@ -24,7 +24,7 @@ STATUS_NAMES = {0: "SGW_OK", -1: "SGW_EINVAL", -2: "SGW_ENOMEM", -3: "SGW_EHIP",
 
 # every entry point declared in include/sgw.h
 EXPORTS = ["sgw_create", "sgw_destroy", "sgw_last_error", "sgw_bounds", "sgw_lanczos_bounds",
-           "sgw_apply_H",
+           "sgw_apply_H", "sgw_apply_H_noalloc",
            "sgw_fermi_coefficients", "sgw_gapped_coefficients", "sgw_fermi_filter", "sgw_propagator_coefficients",
            "sgw_cheb_propagate", "sgw_tdh_init", "sgw_tdh_step", "sgw_sigma_estimate",
            "sgw_sigma_estimate_states",
@@ -108,6 +108,7 @@ def load():
     lib.sgw_bounds.argtypes = [vp, d, dp, dp]
     lib.sgw_lanczos_bounds.argtypes = [vp, i32, C.c_uint64, d, dp, dp]
     lib.sgw_apply_H.argtypes = [vp, vp, vp, i64, i64]
+    lib.sgw_apply_H_noalloc.argtypes = [vp, vp, vp, i64, i64]
     lib.sgw_fermi_coefficients.argtypes = [d, d, d, d, i32, dp]
     lib.sgw_gapped_coefficients.argtypes = [d, d, d, d, d, i32, dp]
     lib.sgw_fermi_filter.argtypes = [vp, vp, i64, i64, dp, i32, d, d]
@@ -293,6 +294,10 @@ class Context:
     def apply_H(self, psi, hpsi):
         _check(load().sgw_apply_H(self.ctx, _dev(psi, "psi"), _dev(hpsi, "hpsi"),
                                   psi.shape[0], psi.shape[-1]), self.ctx)
+
+    def apply_H_noalloc(self, psi, hpsi):
+        _check(load().sgw_apply_H_noalloc(self.ctx, _dev(psi, "psi"), _dev(hpsi, "hpsi"),
+                                          psi.shape[0], psi.shape[-1]), self.ctx)
 
     def fermi_filter(self, v, coef, emin, emax):
         c = np.ascontiguousarray(np.asarray(coef, dtype=np.float64))
