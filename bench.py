@@ -14,13 +14,18 @@ time ordering, zeta propagation, contraction) for a batch of samples, through
 sgw_sigma_estimate.  The QP energy of the HOMO and its per-sample spread give
 GPU-seconds per QP energy at +-0.03 eV.  Printed as one JSON line.
 
-Forms: "plain" (complex FP32, the value), "bf16kb_graphs" and
-"bf16x2kb_graphs" (projector GEMMs with BF16 operands, plain or with the
-state operand split into two BF16 terms; launch sequences replayed from HIP
-graphs; same samples, so the same spread) and, with --cv N, "control_variate": N more samples are
-split into a fit set and an evaluation set, a network on |<phi_k|zeta>|^2
-over the 64 near-gap states is trained on the fit set and its mean taken over
---cv-cheap cheap samples.
+Forms: "plain" (complex FP32, the value; --steps timed steps), and, over
+--form-steps steps each: "c64_graphs" (the same with launch sequences
+replayed from HIP graphs), "bf16x2kb_graphs" (projector GEMMs on BF16 MFMA
+with the state operand split into two BF16 terms, graphs), "homo_lumo_shared"
+(both states from one pass); "cfg1_32_c128_plain" (the 32^3 Gaussian-well
+system in complex FP64); "cfg3_128_bf16" (the 128^3 cluster shape with 512
+TDH orbitals per launch, complex FP64 against split and plain BF16 projector
+GEMMs on the same samples, shortened time axis); with --cv N,
+"control_variate": N more samples are split into a fit set and an evaluation
+set, a network on |<phi_k|zeta>|^2 over the 64 near-gap states is trained on
+the fit set and its mean taken over --cv-cheap cheap samples.  --counters
+runs only the workload of the rocprofv3 counter profiles.
 """
 import argparse
 import json
@@ -50,13 +55,18 @@ HPSI_ALGO_BYTES = 16.0
 CHEB_MEASURED_BYTES = 36.68
 # The dominant kernel by time, the projector scatter psi += s B C' (the TDH's
 # KB exponential twice per substep at 1024 vectors, every filter term at 260):
-# algorithmic bytes per (point of a tile that projectors touch x complex
+# algorithmic bytes per (grid point inside some projector's support x complex
 # vector) = read and write of psi there, 16 B (the reads of B and C', under
-# 2 % of that at these batch widths, are left out).
+# 2 % of that at these batch widths, are left out).  The kernel works on
+# whole 512-point tiles; the support points (sgw_kb_stats) are the method's.
 KB_SCATTER_ALGO_BYTES = 16.0
-# its counter bytes per touched point x vector (FETCH_SIZE + WRITE_SIZE,
-# scaled as above): 16.5 at 1024 vectors, 16.8 at 260
-KB_SCATTER_MEASURED_BYTES = 16.6
+# the gather C = B^T psi reads psi on the support: 8 B per support pt x vector
+KB_GATHER_ALGO_BYTES = 8.0
+# counter bytes per touched-tile point x vector (FETCH_SIZE + WRITE_SIZE,
+# scaled as above), the scatter and the gather at 1024 vectors; None once the
+# kernel changes
+KB_SCATTER_MEASURED_BYTES = 16.5
+KB_GATHER_MEASURED_BYTES = 8.6
 
 
 def parse():
@@ -78,7 +88,26 @@ def parse():
     ap.add_argument("--cv", type=int, default=0,
                     help="samples for the control-variate form (0: skip it)")
     ap.add_argument("--cv-cheap", type=int, default=200000)
+    ap.add_argument("--form-steps", type=int, default=2,
+                    help="timed steps of each secondary form (graph replay, BF16, states)")
+    ap.add_argument("--form-warmup", type=int, default=1)
+    ap.add_argument("--no-cfg1", action="store_true", help="skip the 32^3 complex FP64 form")
+    ap.add_argument("--no-cfg3", action="store_true", help="skip the 128^3 BF16-MFMA form")
+    ap.add_argument("--cfg3-ntau", type=int, default=40)
+    ap.add_argument("--counters", action="store_true",
+                    help="counter-profile driver only: a 256 MiB device copy, filter terms "
+                         "at the bench launch shape and H applications on --hpsi-nvec "
+                         "vectors; meant to run under rocprofv3 --pmc")
+    ap.add_argument("--terms", type=int, default=8, help="--counters: filter terms")
+    ap.add_argument("--hpsi-nvec", type=int, default=1024, help="--counters: H batch")
     return ap.parse_args()
+
+
+T_START = time.perf_counter()
+
+
+def progress(msg):
+    print(f"[{time.perf_counter() - T_START:7.1f} s] {msg}", file=sys.stderr, flush=True)
 
 
 def suggested_ncoef(sgw, e_homo, e_lumo, eps, emin, emax, tol):
@@ -150,19 +179,22 @@ def graph_form(args, s, phi, p, sigma1, sig_plain, homo, gam, precision):
                       ecut=s.ecut, max_nvec=256, stream=st.cuda_stream)
     ctx.use_graphs(True)
     B = args.batch
-    for w in range(args.warmup):
+    W, K = args.form_warmup, min(args.form_steps, args.steps)
+    for w in range(W):
         ctx.sigma_estimate(phi, n_zeta=B, first_sample=w * B, **p)
     torch.cuda.synchronize()
     sigs = []
     t0 = time.perf_counter()
-    for k in range(args.steps):
+    for k in range(K):
+        # the same samples as the plain form's first K steps
         sigs.append(ctx.sigma_estimate(phi, n_zeta=B, first_sample=(args.warmup + k) * B, **p)[0])
     torch.cuda.synchronize()
-    t = (time.perf_counter() - t0) / (args.steps * B)
+    t = (time.perf_counter() - t0) / (K * B)
     ctx.close()
     sig = np.concatenate(sigs)
-    d_sigma = float(np.max(np.abs(sig - sig_plain)) / np.max(np.abs(sig_plain)))
-    return {"gpu_s_per_qp": t * (sigma1 / 0.03) ** 2, "gpu_s_per_sample": t,
+    ref = sig_plain[:sig.shape[0]]
+    d_sigma = float(np.max(np.abs(sig - ref)) / np.max(np.abs(ref)))
+    return {"gpu_s_per_qp": t * (sigma1 / 0.03) ** 2, "gpu_s_per_sample": t, "steps": K,
             "sigma_t_max_rel_diff_vs_plain": d_sigma}
 
 
@@ -175,12 +207,13 @@ def states_form(args, ctx, phi2, p, homo, lumo, gam, t_sample):
     import torch
     from paper_2601_21005_amd import sgw
     B = args.batch
-    for w in range(args.warmup):
+    W, K = args.form_warmup, min(args.form_steps, args.steps)
+    for w in range(W):
         ctx.sigma_estimate_states(phi2, n_zeta=B, first_sample=w * B, **p)
     torch.cuda.synchronize()
     sigs, xs = [], []
     t0 = time.perf_counter()
-    for k in range(args.steps):
+    for k in range(K):
         sig, x, _ = ctx.sigma_estimate_states(phi2, n_zeta=B, first_sample=(args.warmup + k) * B,
                                               **p)
         sigs.append(sig)
@@ -246,7 +279,7 @@ def cv_form(args, ctx, s, phis, ev, phi, p, homo, eg, gam, t_sample, sigma1, Z):
         sig.append(a)
         xs.append(x)
         if (b0 + nb) % 64 == 0 or b0 + nb == n:
-            print(f"control variate: {b0 + nb} / {n} samples", file=sys.stderr, flush=True)
+            progress(f"control variate: {b0 + nb} / {n} samples")
     torch.cuda.synchronize()
     t_samples = time.perf_counter() - t0
     sig, xs = np.concatenate(sig), np.concatenate(xs)
@@ -293,6 +326,202 @@ def cv_form(args, ctx, s, phis, ev, phi, p, homo, eg, gam, t_sample, sigma1, Z):
             "sample_time_s": t_samples}
 
 
+def rocfft_comparison(s, nv=256, reps=10):
+    """The library's three FFT passes against rocFFT on the same batch: H
+    applied by a local-only context (forward xy plane, z pencil with the
+    kinetic multiplier and the inverse, inverse xy plane with V psi) against
+    torch.fft.fftn + ifftn (rocFFT) on 256 complex FP32 vectors of the 64^3
+    grid, HIP events on the default stream that both run on."""
+    import torch
+    from paper_2601_21005_amd import sgw
+    n = s.grid.n
+    ctx = sgw.Context(n, s.grid.h, s.v_loc, None, precision=sgw.SGW_C64, ecut=s.ecut,
+                      max_nvec=nv)
+    x = torch.randn((nv, s.grid.N), dtype=torch.complex64, device="cuda")
+    y = torch.empty_like(x)
+    x3 = x.view(nv, n, n, n)
+
+    def timed(f):
+        f()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            f()
+        e1.record()
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ours = timed(lambda: ctx.apply_H(x, y))
+    roc = timed(lambda: torch.fft.ifftn(torch.fft.fftn(x3, dim=(1, 2, 3)), dim=(1, 2, 3)))
+    ctx.close()
+    del x, y
+    ptv = nv * s.grid.N
+    return {"vectors": nv, "grid": n, "library_local_H_ms": ours,
+            "rocfft_fftn_ifftn_ms": roc, "library_gptvec_per_s": ptv / ours / 1e6,
+            "rocfft_gptvec_per_s": ptv / roc / 1e6, "speedup": roc / ours,
+            "note": "library: forward FFT, T(k), inverse FFT and V psi in three passes; "
+                    "rocFFT: forward and inverse transforms only (no multiplier, no V psi)"}
+
+
+def qp_spread(sgw, sig, x, p, eks):
+    """QP energy (graphical root of Eq. 6), Z and the per-sample spread sigma_1
+    (eV) of the linearised per-sample QP correction Z (X_i + Re Sigma_i(w))."""
+    import numpy as np
+    gam = 3.0 / (p["n_tau"] * p["dt"])
+    eg, el, Z = sgw.sgw_qp_solve(sig.mean(0), p["dt"], gam, eks, x.mean())
+    re_i = np.array([sgw.sgw_sigma_omega(si, p["dt"], gam, eg)[0].real for si in sig])
+    return eg, Z, float(Z * np.std(x + re_i, ddof=1) * HA_EV)
+
+
+def cfg1_form(args):
+    """Plain sGW in complex FP64 on the 32^3 Gaussian-well system (8 wells of
+    2 Ha, width 1 bohr; 8 occupied states): 8 samples per step, N_eta = 8,
+    Fermi filter (beta = 50/Ha, mu mid-gap, coefficient tail < 1e-10), 100
+    output steps of 0.2 au (TDH: 4 Strang substeps of 0.05), N_xi = 10000 at
+    f_g = 0.003.  GPU-s per HOMO QP energy at +-0.03 eV."""
+    import numpy as np
+    import torch
+    from paper_2601_21005_amd import ksinput, sgw, systems
+    s = systems.gaussian_wells()
+    ctx = sgw.Context(s.grid.n, s.grid.h, s.v_loc, None, precision=sgw.SGW_C128, max_nvec=96)
+    emin, emax = ctx.lanczos_bounds(60, seed=1, pad=0.01)
+    ev, phis, _ = ksinput.lowest_states(ctx, s.n_occ + 1, emin, emax, s.grid.h ** 3)
+    homo, lumo = float(ev[s.n_occ - 1]), float(ev[s.n_occ])
+    phi = phis[s.n_occ - 1].cpu().numpy()
+    mu, beta = 0.5 * (homo + lumo), 50.0
+    ncoef = 2048
+    while True:
+        a = sgw.sgw_fermi_coefficients(mu, beta, emin, emax, ncoef)
+        tail = np.cumsum(np.abs(a[::-1]))[::-1]
+        ok = np.nonzero(tail < 1e-10)[0]
+        if ok.size and ok[0] < ncoef // 2:
+            ncoef = int(ok[0])
+            break
+        ncoef *= 2
+    p = dict(seed=1001, n_eta=8, n_tau=100, dt=0.2, m_sub=4, mu=mu, beta=beta, ncoef=ncoef,
+             emin=emin, emax=emax, n_xi=10000, f_g=0.003, mode=0, filter=0)
+    B, K = 8, max(2, args.form_steps)
+    ctx.sigma_estimate(phi, n_zeta=B, first_sample=0, **p)         # warm-up
+    torch.cuda.synchronize()
+    sigs, xs = [], []
+    t0 = time.perf_counter()
+    for k in range(K):
+        sig, x, _ = ctx.sigma_estimate(phi, n_zeta=B, first_sample=(1 + k) * B, **p)
+        sigs.append(sig)
+        xs.append(x)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / (K * B)
+    ctx.close()
+    eg, Z, s1 = qp_spread(sgw, np.concatenate(sigs), np.concatenate(xs), p, homo)
+    return {"workload": "32^3 Gaussian wells, complex FP64, N_eta=8, Fermi beta=50, "
+                        "100 x 0.2 au (4 TDH substeps each), N_xi=10000",
+            "samples": K * B, "ncoef": ncoef, "gpu_s_per_sample": t, "sigma1_eV": s1,
+            "gpu_s_per_qp": t * (s1 / 0.03) ** 2, "eqp_homo_eV": eg * HA_EV,
+            "eps_ks_homo_eV": homo * HA_EV}
+
+
+def cfg3_form(args):
+    """The 128^3 cluster shape (Si357H204 stand-in for Si353H196, h = 0.6
+    bohr, 1632 projectors, 816 occupied states): 32 samples x N_eta = 8, so
+    the TDH batch is 32 x 8 x 2 = 512 orbitals in one launch; gapped filter
+    (transition over >= 0.3 Ha around mid-gap, tail < 1e-7); N_xi = 10000 at
+    f_g = 0.003; the time axis shortened to --cfg3-ntau steps of 0.05 au.
+    The same samples in complex FP64 (the reference), and with the projector
+    GEMMs on BF16 MFMA (split BF16 x 2 and plain BF16) in complex FP32:
+    per-sample time, GPU-s per HOMO QP energy at +-0.03 eV and the QP error
+    against the FP64 run."""
+    import numpy as np
+    import torch
+    from paper_2601_21005_amd import ksinput, sgw, systems
+    s = systems.si357h204()
+    dV = s.grid.h ** 3
+
+    def ctx_of(prec):
+        return sgw.Context(s.grid.n, s.grid.h, s.v_loc, s.projectors, precision=prec,
+                           ecut=s.ecut, max_nvec=512)
+    c64 = ctx_of(sgw.SGW_C64)
+    emin, emax = c64.lanczos_bounds(60, seed=1, pad=0.01)
+    t0 = time.perf_counter()
+    ev, phis, _ = ksinput.lowest_states(c64, s.n_occ + 1, emin, emax, dV, tol=1e-4, maxit=80)
+    t_ks = time.perf_counter() - t0
+    c64.close()
+    homo, lumo = float(ev[s.n_occ - 1]), float(ev[s.n_occ])
+    phi = phis[s.n_occ - 1].cpu().numpy()
+    del phis
+    mid, half = 0.5 * (homo + lumo), max(0.5 * (lumo - homo), 0.15)
+    eh, el = mid - half, mid + half
+    ncoef = suggested_ncoef(sgw, eh, el, 1e-7, emin, emax, 1e-7)
+    p = dict(seed=1003, n_eta=8, n_tau=args.cfg3_ntau, dt=0.05, m_sub=1, ncoef=ncoef,
+             emin=emin, emax=emax, n_xi=10000, f_g=0.003, mode=0, filter=1, e_homo=eh,
+             e_lumo=el, filter_eps=1e-7)
+    out = {"workload": f"Si357H204 stand-in, 128^3 h=0.6, 1632 KB projectors, 32 samples x "
+                       f"N_eta=8 (512 TDH orbitals per launch), N_tau={p['n_tau']} x 0.05 au "
+                       f"(shortened from 400), N_xi=10000, gapped filter",
+           "ncoef": ncoef, "ks_states_s": t_ks, "forms": {}}
+    ref = None
+    for prec, name in ((sgw.SGW_C128, "c128"), (sgw.SGW_C64_BF16X2KB, "c64_bf16x2kb"),
+                       (sgw.SGW_C64_BF16KB, "c64_bf16kb")):
+        ctx = ctx_of(prec)
+        ctx.sigma_estimate(phi, n_zeta=2, first_sample=1000, **dict(p, n_tau=2))   # warm-up
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        sig, x, ms = ctx.sigma_estimate(phi, n_zeta=32, first_sample=0, **p)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t1) / 32
+        ctx.close()
+        eg, Z, s1 = qp_spread(sgw, sig, x, p, homo)
+        f = {"gpu_s_per_sample": t, "sigma1_eV": s1, "gpu_s_per_qp": t * (s1 / 0.03) ** 2,
+             "eqp_homo_eV": eg * HA_EV, "phase_ms": {"filter": ms[0], "tdh": ms[1]}}
+        if ref is None:
+            ref = (eg, sig)
+        else:
+            f["qp_err_vs_c128_meV"] = abs(eg - ref[0]) * HA_EV * 1e3
+            f["sigma_t_max_rel_diff_vs_c128"] = float(np.max(np.abs(sig - ref[1])) /
+                                                      np.max(np.abs(ref[1])))
+        out["forms"][name] = f
+        progress(f"cfg3 {name}: {t:.3f} s per sample")
+    return out
+
+
+def counters_driver(args):
+    """Workload for rocprofv3 counter runs (one counter set per run): a plain
+    256 MiB device copy (the reference that scales FETCH_SIZE / WRITE_SIZE to
+    bytes), the filter on the bench launch shape (260 complex vectors = 8
+    samples x 65 real orbitals; terms - 1 launches of the Chebyshev plane
+    pass) and three H applications on --hpsi-nvec vectors (the TDH's launch
+    shape of the projector kernels is 1024)."""
+    import numpy as np
+    import torch
+    from paper_2601_21005_amd import sgw, systems
+    a = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(f"copy bytes read {a.numel() * 4} written {b.numel() * 4}", flush=True)
+    del a, b
+    s = systems.si35h36()
+    nvec = 260
+    ctx = sgw.Context(s.grid.n, s.grid.h, s.v_loc, s.projectors, precision=sgw.SGW_C64,
+                      ecut=s.ecut, max_nvec=max(nvec, args.hpsi_nvec))
+    print(f"kb layout {ctx.kb_stats()}", flush=True)
+    lo, hi = ctx.bounds(0.01)
+    coef = sgw.sgw_fermi_coefficients(-4.65, 66.0, lo, hi, args.terms)
+    x = torch.randn((nvec, s.grid.N), dtype=torch.complex64, device="cuda")
+    x /= float(np.sqrt(s.grid.N))
+    ctx.fermi_filter(x, coef, lo, hi)
+    torch.cuda.synchronize()
+    print(f"filter nvec {nvec} terms {args.terms} N {s.grid.N}", flush=True)
+    del x
+    if args.hpsi_nvec > 0:
+        y = torch.randn((args.hpsi_nvec, s.grid.N), dtype=torch.complex64, device="cuda")
+        hy = torch.empty_like(y)
+        for _ in range(3):
+            ctx.apply_H(y, hy)
+        torch.cuda.synchronize()
+        print(f"H psi nvec {args.hpsi_nvec}: 3 applications", flush=True)
+    ctx.close()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -306,6 +535,9 @@ def main():
     from paper_2601_21005_amd import ksinput, sgw, systems
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     torch.cuda.set_device(0)
+    if args.counters:
+        counters_driver(args)
+        return
     if args.quick:
         args.n_tau, args.n_eta, args.batch = 20, 8, 2
 
@@ -330,10 +562,13 @@ def main():
              e_lumo=lumo, filter_eps=eps)
     B = args.batch
 
+    progress(f"setup done: interval [{emin:.4f}, {emax:.4f}], {ncoef} filter terms")
     for w in range(args.warmup):
         ctx.sigma_estimate(phi, n_zeta=B, first_sample=w * B, **p)
+        progress(f"warm-up {w + 1}/{args.warmup}")
     torch.cuda.synchronize()
-    ctx.kernel_timer(sgw.SGW_TIMER_CHEB_PLANE | sgw.SGW_TIMER_KB_SCATTER)
+    ctx.kernel_timer(sgw.SGW_TIMER_CHEB_PLANE | sgw.SGW_TIMER_KB_SCATTER |
+                     sgw.SGW_TIMER_KB_GATHER)
     sigs, xs, phases = [], [], np.zeros(6)
     t0 = time.perf_counter()
     for k in range(args.steps):
@@ -341,11 +576,17 @@ def main():
         sigs.append(sig)
         xs.append(x)
         phases += ms
+        progress(f"step {k + 1}/{args.steps}: {ms[5]:.0f} ms")
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t0
     ctx.kernel_timer(0)
     k_ms, k_launch, k_pts = ctx.kernel_timer_read(sgw.SGW_TIMER_CHEB_PLANE)
     s_ms, s_launch, s_pts = ctx.kernel_timer_read(sgw.SGW_TIMER_KB_SCATTER)
+    g_ms, g_launch, g_pts = ctx.kernel_timer_read(sgw.SGW_TIMER_KB_GATHER)
+    kbs = ctx.kb_stats()
+    # timer points are touched-tile points x vectors; the method's are the
+    # support points x vectors
+    support_frac = kbs["support_points"] / kbs["tile_points"]
 
     sig = np.concatenate(sigs)
     x = np.concatenate(xs)
@@ -370,25 +611,50 @@ def main():
     torch.cuda.synchronize()
     hpsi_rate = nv * reps * s.grid.N / (time.perf_counter() - t1)
     del xh, yh
+    fft_cmp = rocfft_comparison(s)
     feat = features_roofline(ctx, phis, s)
+    progress("H psi, rocFFT and feature-GEMM lines done")
 
     forms = {"plain": {"gpu_s_per_qp": gpu_s_per_qp, "gpu_s_per_sample": t_sample}}
     if not args.no_bf16:
         forms["c64_graphs"] = graph_form(args, s, phi, p, sigma1, sig, homo, gam,
                                          sgw.SGW_C64)
-        forms["bf16kb_graphs"] = graph_form(args, s, phi, p, sigma1, sig, homo, gam,
-                                           sgw.SGW_C64_BF16KB)
+        progress("graph form done")
         forms["bf16x2kb_graphs"] = graph_form(args, s, phi, p, sigma1, sig, homo, gam,
                                              sgw.SGW_C64_BF16X2KB)
     if not args.no_states:
         phi2 = np.stack([phi, phis[s.n_occ].cpu().numpy()])
         forms["homo_lumo_shared"] = states_form(args, ctx, phi2, p, homo, lumo, gam, t_sample)
+        progress("states form done")
+    if not args.no_cfg1 and not args.quick:
+        forms["cfg1_32_c128_plain"] = cfg1_form(args)
+        progress("cfg1 form done")
+    if not args.no_cfg3 and not args.quick:
+        forms["cfg3_128_bf16"] = cfg3_form(args)
     if args.cv:
         forms["control_variate"] = cv_form(args, ctx, s, phis, ev, phi, p, homo, eg, gam,
                                           t_sample, sigma1, Z)
 
     achieved = CHEB_ALGO_BYTES * k_pts / (k_ms * 1e-3) / 1e9 if k_ms > 0 else None
-    s_achieved = KB_SCATTER_ALGO_BYTES * s_pts / (s_ms * 1e-3) / 1e9 if s_ms > 0 else None
+
+    def kb_line(kernel, algo, measured, ms, launches, pts):
+        """HBM roofline of a projector kernel on the method's bytes (support
+        points) with the tile-granular figures beside it."""
+        if not ms > 0:
+            return None
+        sup = pts * support_frac                      # support pt x vec over the launches
+        a = algo * sup / (ms * 1e-3) / 1e9
+        return {"bound": "hbm", "kernel": kernel, "achieved": a, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": a / HBM_PEAK_GBS,
+                "traffic": (measured * pts / launches if measured else None),
+                "traffic_unit": "B per launch (counters)",
+                "algo_bytes_per_support_ptvec": algo,
+                "traffic_bytes_per_support_ptvec": (measured / support_frac if measured
+                                                    else None),
+                "support_points": kbs["support_points"], "tile_points": kbs["tile_points"],
+                "achieved_on_tile_points": algo * pts / (ms * 1e-3) / 1e9,
+                "launches": launches, "avg_launch_us": 1e3 * ms / launches,
+                "support_ptvec_per_launch": sup / launches}
     line = {
         "metric": METRIC,
         "value": gpu_s_per_qp,
@@ -418,16 +684,14 @@ def main():
         "hpsi_algo_roofline_frac": hpsi_rate * HPSI_ALGO_BYTES / (HBM_PEAK_GBS * 1e9),
         "phase_ms": {"filter": phases[0], "tdh": phases[1], "time_order": phases[2],
                      "zeta_contract": phases[3], "other": phases[4], "total": phases[5]},
-        "roofline": {"bound": "hbm", "kernel": "k_kb_scatter_mma<OpF32,NVB,MJ,LX> (autotuned)",
-                     "achieved": s_achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": s_achieved / HBM_PEAK_GBS if s_achieved else None,
-                     "traffic": (KB_SCATTER_MEASURED_BYTES * s_pts / s_launch
-                                 if s_launch and KB_SCATTER_MEASURED_BYTES else None),
-                     "traffic_unit": "B per launch",
-                     "algo_bytes_per_touched_ptvec": KB_SCATTER_ALGO_BYTES,
-                     "traffic_bytes_per_touched_ptvec": KB_SCATTER_MEASURED_BYTES,
-                     "launches": s_launch,
-                     "avg_launch_us": 1e3 * s_ms / s_launch if s_launch else None},
+        "roofline": kb_line("k_kb_scatter_mma<OpF32,NVB,MJ,LX> (autotuned)",
+                            KB_SCATTER_ALGO_BYTES, KB_SCATTER_MEASURED_BYTES, s_ms, s_launch,
+                            s_pts),
+        "roofline_gather": kb_line("k_kb_gather_mma<OpF32,NVB,MT,LX> (autotuned)",
+                                   KB_GATHER_ALGO_BYTES, KB_GATHER_MEASURED_BYTES, g_ms,
+                                   g_launch, g_pts),
+        "fft_vs_rocfft": fft_cmp,
+        "kb_layout": kbs,
         "roofline_cheb": {"bound": "hbm", "kernel": "k_plane<float,64,64,PLANE_INV_CHEB>",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS if achieved else None,
@@ -441,7 +705,9 @@ def main():
         "roofline_features": feat,
     }
     if not args.no_cpu_baseline:
+        progress("cpu baseline")
         tcpu, parts, cores, sample = cpu_baseline(s, phi, p, args.cpu_terms, ncoef)
+        progress("cpu baseline done")
         line["cpu_baseline"] = {"value": tcpu * (sigma1 / 0.03) ** 2, "unit": "CPU-s",
                                 "cores": cores, "kind": "oracle", "sample": sample,
                                 "seconds_per_sample": tcpu, "parts_s": parts}

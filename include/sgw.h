@@ -322,14 +322,16 @@ sgw_status sgw_qp_solve(const double *sigma_t, int32_t n_tau, double dt,
 sgw_status sgw_sigma_omega(const double *sigma_t, int32_t n_tau, double dt, double gamma,
                            const double *omega, int32_t n_omega, double *out);
 
-/* Launch timers of the two largest kernels (bits of `which`):
+/* Launch timers of the largest kernels (bits of `which`):
  *   SGW_TIMER_CHEB_PLANE  the inverse xy-plane FFT pass that carries the
  *                         Chebyshev-recurrence epilogue (Eq. 3 filter and the
  *                         zeta propagator); points = grid points x vectors;
  *   SGW_TIMER_KB_SCATTER  the projector scatter GEMM psi += s B C' (complex
  *                         FP32 precisions; filter terms, H applications and
  *                         the KB exponential of the TDH steps); points =
- *                         points of the tiles that projectors touch x vectors.
+ *                         points of the tiles that projectors touch x vectors;
+ *   SGW_TIMER_KB_GATHER   the projector gather GEMM C = B^T psi (complex FP32
+ *                         precisions, the same calls); points as the scatter.
  * From sgw_kernel_timer(ctx, bits) on, every launch of the selected kernels
  * on the context's stream is bracketed by a pair of HIP events (launches that
  * sgw_sigma_estimate issues on the context's second stream, the zeta
@@ -340,9 +342,18 @@ sgw_status sgw_sigma_omega(const double *sigma_t, int32_t n_tau, double dt, doub
  * of timed launches and the points they processed, then resets that timer. */
 #define SGW_TIMER_CHEB_PLANE 1
 #define SGW_TIMER_KB_SCATTER 2
+#define SGW_TIMER_KB_GATHER 4
 sgw_status sgw_kernel_timer(sgw_ctx *ctx, int32_t which);
 sgw_status sgw_kernel_timer_read(sgw_ctx *ctx, int32_t which, double *total_ms,
                                  int64_t *launches, int64_t *points);
+
+/* Sizes of the projector layout (the separable non-local part applied with
+ * overlapping spheres, Sec. 3), for byte and flop accounting: out[0] the
+ * 512-point grid tiles that some projector touches, out[1] their points,
+ * out[2] the grid points inside at least one projector's support, out[3]
+ * the (tile, projector) entries, out[4] the nonzero projector values
+ * (point, projector pairs).  All zero without projectors.  out: host [5]. */
+sgw_status sgw_kb_stats(const sgw_ctx *ctx, int64_t *out);
 
 /* HIP graphs for repeated launch sequences.  enable != 0: a Chebyshev series
  * of at most 64 terms (the zeta propagator, Eq. 4) runs as one captured graph

@@ -938,10 +938,21 @@ sgw_status sgw_sigma_omega(const double *sigma_t, int32_t n_tau, double dt, doub
 sgw_status sgw_kernel_timer(sgw_ctx *ctx, int32_t which) {
   if (!ctx) return SGW_EINVAL;
   return guarded(ctx, [&] {
-    SGW_REQUIRE((which & ~(SGW_TIMER_CHEB_PLANE | SGW_TIMER_KB_SCATTER)) == 0, SGW_EINVAL,
-                "unknown timer bits");
+    SGW_REQUIRE((which & ~(SGW_TIMER_CHEB_PLANE | SGW_TIMER_KB_SCATTER | SGW_TIMER_KB_GATHER)) ==
+                    0,
+                SGW_EINVAL, "unknown timer bits");
     ctx->ktimer = which;
   });
+}
+
+sgw_status sgw_kb_stats(const sgw_ctx *ctx, int64_t *out) {
+  if (!ctx || !out) return SGW_EINVAL;
+  out[0] = ctx->kb_ntile;
+  out[1] = (int64_t)ctx->kb_ntile * KB_TP;
+  out[2] = ctx->kb_support_points;
+  out[3] = ctx->kb_nentry;
+  out[4] = ctx->kb_nnz;
+  return SGW_OK;
 }
 
 sgw_status sgw_use_graphs(sgw_ctx *ctx, int32_t enable) {
@@ -960,9 +971,11 @@ sgw_status sgw_kernel_timer_read(sgw_ctx *ctx, int32_t which, double *total_ms,
   if (!ctx) return SGW_EINVAL;
   return guarded(ctx, [&] {
     SGW_REQUIRE(total_ms && launches && points, SGW_EINVAL, "NULL output");
-    SGW_REQUIRE(which == SGW_TIMER_CHEB_PLANE || which == SGW_TIMER_KB_SCATTER, SGW_EINVAL,
-                "which must name one timer");
-    sgw_ctx::KTimer &t = ctx->kt[which == SGW_TIMER_CHEB_PLANE ? 0 : 1];
+    SGW_REQUIRE(which == SGW_TIMER_CHEB_PLANE || which == SGW_TIMER_KB_SCATTER ||
+                    which == SGW_TIMER_KB_GATHER,
+                SGW_EINVAL, "which must name one timer");
+    sgw_ctx::KTimer &t =
+        ctx->kt[which == SGW_TIMER_CHEB_PLANE ? 0 : which == SGW_TIMER_KB_SCATTER ? 1 : 2];
     SGW_HIP(hipStreamSynchronize(ctx->stream));
     double ms = 0;
     for (int64_t i = 0; i < t.used; ++i) {

@@ -121,6 +121,8 @@ struct sgw_ctx {
   sgw::DevBuf d_kb_betaT;            // per tile [512][entries padded to the K group], FP32 or BF16
   sgw::DevBuf d_kb_beta16;           // [entry][512] BF16 (the BF16 precisions)
   int kb_ntile = 0, kb_nentry = 0;
+  int64_t kb_support_points = 0;     // grid points where some beta_p is nonzero
+  int64_t kb_nnz = 0;                // nonzero beta values (point, projector)
   int kb_nek_max = 0;                // largest padded entry count of a tile (scatter LDS)
   int kb_lx = 3, kb_ly = 3;          // tile extent log2 along x and y (512 points)
 
@@ -132,7 +134,8 @@ struct sgw_ctx {
   sgw::DevBuf d_counter;
 
   // launch timers: ktimer bit 0 the inverse plane pass with the Chebyshev
-  // epilogue, bit 1 the KB scatter (launches on the context's stream)
+  // epilogue, bit 1 the KB scatter, bit 2 the KB gather (launches on the
+  // context's stream)
   struct KTimer {
     std::vector<hipEvent_t> events;   // pairs (start, stop)
     int64_t used = 0, points = 0;
@@ -147,7 +150,7 @@ struct sgw_ctx {
     }
   };
   int ktimer = 0;
-  KTimer kt[2];
+  KTimer kt[3];
   int dev = 0;                 // HIP device the context was created on
   // set while a call must not time kernel variants (sgw_apply_H_noalloc):
   // tune() then returns the forced, remembered or cached choice, else 0

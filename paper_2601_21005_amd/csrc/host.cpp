@@ -164,6 +164,17 @@ void build_kb(sgw_ctx *ctx, const sgw_projectors *P) {
       }
   ctx->kb_ntile = ntile;
   ctx->kb_nentry = nentry;
+  // grid points inside some projector's support, and nonzero beta values
+  ctx->kb_support_points = 0;
+  ctx->kb_nnz = 0;
+  for (int t = 0; t < ntile; ++t)
+    for (int i = 0; i < KB_TP; ++i) {
+      int hit = 0;
+      for (int e = kb.tile_off[t]; e < kb.tile_off[t + 1]; ++e)
+        hit += kb.beta[(size_t)e * KB_TP + i] != 0.0;
+      ctx->kb_support_points += hit > 0;
+      ctx->kb_nnz += hit;
+    }
 }
 
 // lambda_max(S) <= max_p sum_q |S_pq|  (Gershgorin)

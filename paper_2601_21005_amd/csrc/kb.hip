@@ -671,7 +671,15 @@ static void gather_t(sgw_ctx *ctx, const void *psi, int64_t nvec, int64_t ld, vo
                                   ctx->kb_lx, (float)ctx->dV, ctx->kb_ntile,
                                   (int)nvb);
       };
-      run(ctx->tune(name, nvec, NGATHER, run));   // the gather overwrites: trials are harmless
+      const int vi = ctx->tune(name, nvec, NGATHER, run);   // the gather overwrites: trials are harmless
+      const bool timed = (ctx->ktimer & 4) && ctx->ns.empty();
+      if (timed) SGW_HIP(hipEventRecord(ctx->kt[2].event(0), ctx->stream));
+      run(vi);
+      if (timed) {
+        SGW_HIP(hipEventRecord(ctx->kt[2].event(1), ctx->stream));
+        ctx->kt[2].used++;
+        ctx->kt[2].points += (int64_t)ctx->kb_ntile * KB_TP * nvec;
+      }
     };
     if (ctx->prec == SGW_C64_BF16KB)
       go(OpBF16{}, "kb_gather_bf16", ctx->d_kb_beta16.as<uint16_t>());

@@ -17,7 +17,7 @@ SGW_OK, SGW_EINVAL, SGW_ENOMEM, SGW_EHIP, SGW_EDIVERGED, SGW_ENOROOT, SGW_EUNSUP
     0, -1, -2, -3, -4, -5, -6
 SGW_C128, SGW_C64, SGW_C64_BF16KB, SGW_C64_BF16X2KB = 0, 1, 2, 3
 SGW_MAX_STATES = 8
-SGW_TIMER_CHEB_PLANE, SGW_TIMER_KB_SCATTER = 1, 2
+SGW_TIMER_CHEB_PLANE, SGW_TIMER_KB_SCATTER, SGW_TIMER_KB_GATHER = 1, 2, 4
 
 STATUS_NAMES = {0: "SGW_OK", -1: "SGW_EINVAL", -2: "SGW_ENOMEM", -3: "SGW_EHIP",
                 -4: "SGW_EDIVERGED", -5: "SGW_ENOROOT", -6: "SGW_EUNSUPPORTED"}
@@ -28,7 +28,7 @@ EXPORTS = ["sgw_create", "sgw_destroy", "sgw_last_error", "sgw_bounds", "sgw_lan
            "sgw_fermi_coefficients", "sgw_gapped_coefficients", "sgw_fermi_filter", "sgw_propagator_coefficients",
            "sgw_cheb_propagate", "sgw_tdh_init", "sgw_tdh_step", "sgw_sigma_estimate",
            "sgw_sigma_estimate_states",
-           "sgw_qp_solve", "sgw_sigma_omega", "sgw_kernel_timer", "sgw_kernel_timer_read",
+           "sgw_qp_solve", "sgw_sigma_omega", "sgw_kernel_timer", "sgw_kernel_timer_read", "sgw_kb_stats",
            "sgw_use_graphs", "sgw_batch_sigma_estimate", "sgw_cv_features", "sgw_mlp_create", "sgw_mlp_destroy", "sgw_mlp_last_error",
            "sgw_mlp_set_standardization", "sgw_mlp_get_params", "sgw_mlp_forward",
            "sgw_mlp_gradient", "sgw_mlp_adam", "sgw_mlp_train", "sgw_cv_cheap_moments",
@@ -123,6 +123,7 @@ def load():
     lib.sgw_use_graphs.argtypes = [vp, i32]
     lib.sgw_batch_sigma_estimate.argtypes = [C.POINTER(SgwBatchItem), i32, i32]
     lib.sgw_kernel_timer_read.argtypes = [vp, i32, dp, C.POINTER(i64), C.POINTER(i64)]
+    lib.sgw_kb_stats.argtypes = [vp, C.POINTER(i64)]
     u64, fp = C.c_uint64, C.c_void_p
     lib.sgw_cv_features.argtypes = [vp, fp, i32, i64, u64, i64, i64, fp]
     lib.sgw_mlp_create.argtypes = [i32, i32, i32, dp, vp, C.POINTER(vp)]
@@ -337,6 +338,14 @@ class Context:
         _check(load().sgw_kernel_timer_read(self.ctx, which, C.byref(ms), C.byref(n),
                                             C.byref(pts)), self.ctx)
         return ms.value, n.value, pts.value
+
+    def kb_stats(self):
+        """Projector layout sizes: dict of touched tiles, their points, the
+        support points, (tile, projector) entries and nonzero values."""
+        out = (C.c_int64 * 5)()
+        _check(load().sgw_kb_stats(self.ctx, out), self.ctx)
+        return dict(zip(("tiles", "tile_points", "support_points", "entries", "nnz"),
+                        list(out)))
 
     def sigma_estimate(self, phi, seed, n_zeta, n_eta, n_tau, dt, m_sub, ncoef, emin, emax,
                        mu=0.0, beta=0.0, n_xi=10000, f_g=0.003, mode=0, prop_tol=1e-14, n_ft=0,

@@ -171,9 +171,10 @@ def test_lanczos_bounds_si35h36_fp32(si35):
 
 
 def test_kernel_timers(tiny8):
-    """The launch timers of the Chebyshev plane pass and the KB scatter count
-    one launch of each per filter term and the points they cover (the 8^3
-    grid is one 512-point tile, which the projectors touch)."""
+    """The launch timers of the Chebyshev plane pass and the KB scatter and
+    gather count one launch of each per filter term and the points they cover
+    (the 8^3 grid is one 512-point tile, which the projectors touch); the
+    projector layout sizes match that tile."""
     s, _ = tiny8
     ctx = make_ctx(s, sgw.SGW_C64, max_nvec=32)
     N, nvec = s.grid.N, 5
@@ -181,7 +182,8 @@ def test_kernel_timers(tiny8):
     x = torch.randn((nvec, N), generator=g, device="cuda", dtype=torch.complex64)
     lo, hi = ctx.bounds()
     coef = sgw.sgw_fermi_coefficients(-0.5, 6.0, lo, hi, 40)
-    ctx.kernel_timer(sgw.SGW_TIMER_CHEB_PLANE | sgw.SGW_TIMER_KB_SCATTER)
+    ctx.kernel_timer(sgw.SGW_TIMER_CHEB_PLANE | sgw.SGW_TIMER_KB_SCATTER |
+                     sgw.SGW_TIMER_KB_GATHER)
     ctx.fermi_filter(x, coef, lo, hi)
     ctx.kernel_timer(0)
     ms, n, pts = ctx.kernel_timer_read(sgw.SGW_TIMER_CHEB_PLANE)
@@ -189,7 +191,15 @@ def test_kernel_timers(tiny8):
     ms, n, pts = ctx.kernel_timer_read(sgw.SGW_TIMER_KB_SCATTER)
     assert n == 39 and pts == 39 * nvec * 512 and ms > 0
     assert ctx.kernel_timer_read(sgw.SGW_TIMER_KB_SCATTER)[:2] == (0.0, 0)   # read resets
-    for bad in (4, -1):
+    ms, n, pts = ctx.kernel_timer_read(sgw.SGW_TIMER_KB_GATHER)
+    assert n == 39 and pts == 39 * nvec * 512 and ms > 0
+    # the oracle's projector matrix gives the support and the nonzero count
+    B = tiny8[1].kb.B.copy()
+    B.eliminate_zeros()
+    st = ctx.kb_stats()
+    assert st["tiles"] == 1 and st["tile_points"] == 512 and st["entries"] == 2
+    assert st["support_points"] == np.unique(B.tocoo().row).size and st["nnz"] == B.nnz
+    for bad in (8, -1):
         with pytest.raises(sgw.SgwError) as e:
             ctx.kernel_timer(bad)
         assert e.value.code == sgw.SGW_EINVAL

@@ -29,7 +29,14 @@ ORDER = [56, 112] + [n for n in LENGTHS if n not in (56, 112)]   # radix 7 first
 # max |H psi| ten times that (the largest entries carry the rounding of the
 # largest terms, T(k) up to E_cut and the potential wells)
 TOL = {sgw.SGW_C128: 1e-12, sgw.SGW_C64: 3e-6}
-SIG_TOL = {sgw.SGW_C128: 1e-9, sgw.SGW_C64: 2e-4}
+# Sigma(t_j) = sum_m c_m(t_j) d_m(t_j) carries the rounding of its terms on
+# the scale sum_m |c_m d_m| (stored with the golden), which is 4-11 times
+# max |Sigma| in these one-sample cases.  The bar is a per-term relative
+# error: 1e-10 in complex FP64, 3e-5 in complex FP32 (about 2.5 times the
+# measured FP32 error of the TDH response u^R at 64^3, 1.2e-5, from which
+# the c_m are projected).  X is a sum of positive terms: relative to |X|.
+SIG_TERM_TOL = {sgw.SGW_C128: 1e-10, sgw.SGW_C64: 3e-5}
+X_TOL = {sgw.SGW_C128: 1e-9, sgw.SGW_C64: 2e-4}
 QP_TOL_EV = {sgw.SGW_C128: 1e-9, sgw.SGW_C64: 1e-4}
 
 
@@ -73,8 +80,11 @@ def run_golden(ctx, s, g):
 def check_golden(sig, x, g, prec):
     sig_o = np.array(g["sigma_re"]) + 1j * np.array(g["sigma_im"])
     x_o = np.array(g["x"])
-    assert rel_err(sig, sig_o) < SIG_TOL[prec]
-    assert rel_err(x, x_o) < SIG_TOL[prec]
+    err = float(np.max(np.abs(sig - sig_o)))
+    print(f"  Sigma: max |err| {err:.3e} = {err / g['sigma_term_scale']:.2e} of the term "
+          f"scale, {rel_err(sig, sig_o):.2e} of max |Sigma|", flush=True)
+    assert err < SIG_TERM_TOL[prec] * g["sigma_term_scale"]
+    assert rel_err(x, x_o) < X_TOL[prec]
     p = g["params"]
     gam = 3.0 / (p["n_tau"] * p["dt"])
     eg, el, z = sgw.sgw_qp_solve(sig.mean(0), p["dt"], gam, EPS_KS, x.mean())
