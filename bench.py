@@ -94,6 +94,10 @@ def parse():
     ap.add_argument("--no-cfg1", action="store_true", help="skip the 32^3 complex FP64 form")
     ap.add_argument("--no-cfg3", action="store_true", help="skip the 128^3 BF16-MFMA form")
     ap.add_argument("--cfg3-ntau", type=int, default=40)
+    ap.add_argument("--cfg4", action="store_true",
+                    help="uneven-batch mode only (32 clusters 40^3..112^3, then 32 small ones)")
+    ap.add_argument("--cfg4-ntau", type=int, default=400)
+    ap.add_argument("--cfg4-workers", type=int, default=8)
     ap.add_argument("--counters", action="store_true",
                     help="counter-profile driver only: a 256 MiB device copy, filter terms "
                          "at the bench launch shape and H applications on --hpsi-nvec "
@@ -483,6 +487,87 @@ def cfg3_form(args):
     return out
 
 
+def cfg4_mode(args):
+    """Uneven batch as configured: 32 seeded H-capped Si clusters (17 to 147
+    Si) on grids 40^3 ... 112^3 (h = 0.6 bohr) with 16 to 128 stochastic
+    orbitals each, complex FP32, one Monte Carlo sample per cluster, N_tau =
+    400 x 0.05 au, N_xi = 10000 at f_g = 0.003, gapped filter.  Times the
+    clusters one after another (one stream each, eager) and through
+    sgw_batch_sigma_estimate (host workers, one stream per cluster, graph
+    replay), checks that every result is bitwise the sequential one, then
+    does the same for 32 small clusters (Si17H36 on 40^3 with 16 orbitals),
+    the regime where single launches leave most of the chip idle.  Prints
+    one JSON line."""
+    import numpy as np
+    import torch
+    from paper_2601_21005_amd import sgw, systems
+
+    def run(batch, label, n_tau, workers):
+        jobs, meta = [], []
+        for i, (s, neta) in enumerate(batch):
+            st = torch.cuda.Stream()
+            ctx = sgw.Context(s.grid.n, s.grid.h, s.v_loc, s.projectors,
+                              precision=sgw.SGW_C64, ecut=s.ecut, max_nvec=256,
+                              stream=st.cuda_stream)
+            lo, hi = ctx.lanczos_bounds(30, seed=1, pad=0.01)
+            mid = lo + 0.12 * (hi - lo)
+            ncoef = suggested_ncoef(sgw, mid - 0.15, mid + 0.15, 1e-7, lo, hi, 1e-7)
+            rs = np.random.default_rng(i)
+            phi = rs.standard_normal(s.grid.N)
+            phi /= np.sqrt(s.grid.h ** 3 * np.sum(phi * phi))
+            kw = dict(seed=1005 + i, n_zeta=1, n_eta=neta, n_tau=n_tau, dt=0.05, m_sub=1,
+                      ncoef=ncoef, emin=lo, emax=hi, n_xi=10000, f_g=0.003, mode=0, filter=1,
+                      e_homo=mid - 0.15, e_lumo=mid + 0.15, filter_eps=1e-7)
+            jobs.append((ctx, phi, kw))
+            meta.append({"name": s.name, "grid": s.grid.n, "n_eta": neta, "ncoef": ncoef})
+        torch.cuda.synchronize()
+        # warm-up of every context (autotuning, allocation) on a short time axis
+        for ctx, phi, kw in jobs:
+            ctx.sigma_estimate(phi, **dict(kw, n_tau=2))
+        torch.cuda.synchronize()
+        progress(f"{label}: {len(jobs)} contexts ready")
+        t0 = time.perf_counter()
+        seq = []
+        for k, (ctx, phi, kw) in enumerate(jobs):
+            t1 = time.perf_counter()
+            seq.append(ctx.sigma_estimate(phi, **kw))
+            torch.cuda.synchronize()
+            meta[k]["alone_s"] = time.perf_counter() - t1
+        t_seq = time.perf_counter() - t0
+        progress(f"{label}: sequential {t_seq:.1f} s")
+        for ctx, phi, kw in jobs:
+            # capture the graphs: the filter pair, one TDH output step and the
+            # zeta sweep of 8 output steps (every sweep of n_tau = 400 reuses it)
+            ctx.use_graphs(True)
+            ctx.sigma_estimate(phi, **dict(kw, n_tau=16))
+            ctx.sigma_estimate(phi, **dict(kw, n_tau=16))
+        torch.cuda.synchronize()
+        progress(f"{label}: graphs captured")
+        t0 = time.perf_counter()
+        bat = sgw.batch_sigma_estimate(jobs, nworkers=workers)
+        torch.cuda.synchronize()
+        t_bat = time.perf_counter() - t0
+        progress(f"{label}: batched {t_bat:.1f} s")
+        same = all(np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+                   for a, b in zip(seq, bat))
+        for m, b in zip(meta, bat):
+            m["batched_ms"] = b[2]
+        for ctx, _, _ in jobs:
+            ctx.close()
+        return {"clusters": len(jobs), "workers": workers, "n_tau": n_tau,
+                "sequential_s": t_seq, "batched_s": t_bat, "speedup": t_seq / t_bat,
+                "bitwise_equal": bool(same), "per_cluster": meta}
+
+    out = {"mode": "cfg4"}
+    out["uneven_32"] = run(systems.uneven_batch_spread(32), "uneven", args.cfg4_ntau,
+                           args.cfg4_workers)
+    small = [systems.cluster_model(*systems.si_cluster(17, seed=2000 + i), n=40, h=0.6,
+                                   ecut=28.0, name="Si17H36") for i in range(32)]
+    out["small_32_at_40"] = run([(s, 16) for s in small], "small", args.cfg4_ntau,
+                                args.cfg4_workers)
+    print(json.dumps(out), flush=True)
+
+
 def counters_driver(args):
     """Workload for rocprofv3 counter runs (one counter set per run): a plain
     256 MiB device copy (the reference that scales FETCH_SIZE / WRITE_SIZE to
@@ -537,6 +622,9 @@ def main():
     torch.cuda.set_device(0)
     if args.counters:
         counters_driver(args)
+        return
+    if args.cfg4:
+        cfg4_mode(args)
         return
     if args.quick:
         args.n_tau, args.n_eta, args.batch = 20, 8, 2

@@ -8,6 +8,7 @@
 #include <fstream>
 #include <mutex>
 #include <sstream>
+#include <thread>
 
 #include "common.h"
 
@@ -190,17 +191,38 @@ double kb_lambda_bound(const sgw_ctx *ctx) {
 }
 
 // ---------------------------------------------------------------- KB exponential
+// C = A B (n x n, row-major); rows of C split over host threads (each row is
+// summed in the same order whatever the thread count)
 static void cmatmul(const std::vector<cd> &A, const std::vector<cd> &B, std::vector<cd> &C,
                     int n) {
   C.assign((size_t)n * n, cd(0, 0));
-  for (int i = 0; i < n; ++i)
-    for (int k = 0; k < n; ++k) {
-      const cd a = A[(size_t)i * n + k];
-      if (a == cd(0, 0)) continue;
-      const cd *b = &B[(size_t)k * n];
-      cd *c = &C[(size_t)i * n];
-      for (int j = 0; j < n; ++j) c[j] += a * b[j];
-    }
+  auto rows = [&](int i0, int i1) {
+    for (int i = i0; i < i1; ++i)
+      for (int k = 0; k < n; ++k) {
+        const cd a = A[(size_t)i * n + k];
+        if (a == cd(0, 0)) continue;
+        const double ar = a.real(), ai = a.imag();
+        const double *b = reinterpret_cast<const double *>(&B[(size_t)k * n]);
+        double *c = reinterpret_cast<double *>(&C[(size_t)i * n]);
+        for (int j = 0; j < n; ++j) {
+          const double br = b[2 * j], bi = b[2 * j + 1];
+          c[2 * j] += ar * br - ai * bi;
+          c[2 * j + 1] += ar * bi + ai * br;
+        }
+      }
+  };
+  const int nt = std::max(1, std::min<int>((int)std::thread::hardware_concurrency(), n / 64));
+  if (nt <= 1) {
+    rows(0, n);
+    return;
+  }
+  std::vector<std::thread> th;
+  const int per = (n + nt - 1) / nt;
+  for (int t = 0; t < nt; ++t) {
+    const int i0 = t * per, i1 = std::min(n, i0 + per);
+    if (i0 < i1) th.emplace_back(rows, i0, i1);
+  }
+  for (auto &x : th) x.join();
 }
 
 // exp(-i tau V_NL) = I + dV B K B^T with K = (-i tau) E phi1(X), X = -i tau S E,

@@ -228,6 +228,31 @@ def uneven_batch(count=32, seed=1004, h=0.6, margin=8.0, ecut=28.0):
     return out
 
 
+def uneven_batch_spread(count=32, seed=1005, h=0.6, margin=4.0, ecut=28.0,
+                        shells=(17, 29, 35, 47, 71, 87, 99, 123, 147)):
+    """Uneven batch spanning the grid range: for each of ``count`` clusters a
+    grid drawn uniformly from BATCH_SIZES (40^3 ... 112^3), a seeded shell
+    size from ``shells`` (17 to 147 Si) among those whose cluster the box
+    holds with ``margin`` bohr on every side, its own jitter seed, and a
+    seeded number of stochastic orbitals from (16, 32, 64, 128).  Returns a
+    list of (System, n_eta)."""
+    rs = np.random.default_rng(seed)
+    radius = {}
+    for n_si in shells:
+        _, pos = si_cluster(n_si, seed=0)
+        radius[n_si] = float(np.max(np.linalg.norm(pos, axis=1))) + 0.1   # + jitter
+    out = []
+    for i in range(count):
+        n = int(BATCH_SIZES[rs.integers(len(BATCH_SIZES))])
+        fits = [k for k in shells if n * h >= 2 * (radius[k] + margin)] or [shells[0]]
+        n_si = int(fits[rs.integers(len(fits))])
+        species, pos = si_cluster(n_si, seed=seed + 1 + i)
+        neta = int((16, 32, 64, 128)[rs.integers(4)])
+        out.append((cluster_model(species, pos, n=n, h=h, ecut=ecut,
+                                  name=f"Si{n_si}H{species.count('H')}"), neta))
+    return out
+
+
 def tiny_system(n=8, h=0.7, with_kb=True, n_occ=2):
     """Small periodic test system (8^3 or 12^3 points): two Gaussian wells
     and, optionally, one s and one p_x KB projector."""
