@@ -98,6 +98,7 @@ def parse():
                     help="uneven-batch mode only (32 clusters 40^3..112^3, then 32 small ones)")
     ap.add_argument("--cfg4-ntau", type=int, default=400)
     ap.add_argument("--cfg4-workers", type=int, default=8)
+    ap.add_argument("--cfg4-small-only", action="store_true")
     ap.add_argument("--counters", action="store_true",
                     help="counter-profile driver only: a 256 MiB device copy, filter terms "
                          "at the bench launch shape and H applications on --hpsi-nvec "
@@ -558,9 +559,11 @@ def cfg4_mode(args):
                 "sequential_s": t_seq, "batched_s": t_bat, "speedup": t_seq / t_bat,
                 "bitwise_equal": bool(same), "per_cluster": meta}
 
-    out = {"mode": "cfg4"}
-    out["uneven_32"] = run(systems.uneven_batch_spread(32), "uneven", args.cfg4_ntau,
-                           args.cfg4_workers)
+    out = {"mode": "cfg4", "workers": args.cfg4_workers,
+           "gpu_max_hw_queues": os.environ.get("GPU_MAX_HW_QUEUES", "runtime default")}
+    if not args.cfg4_small_only:
+        out["uneven_32"] = run(systems.uneven_batch_spread(32), "uneven", args.cfg4_ntau,
+                               args.cfg4_workers)
     small = [systems.cluster_model(*systems.si_cluster(17, seed=2000 + i), n=40, h=0.6,
                                    ecut=28.0, name="Si17H36") for i in range(32)]
     out["small_32_at_40"] = run([(s, 16) for s in small], "small", args.cfg4_ntau,
