@@ -289,10 +289,14 @@ def cv_form(args, ctx, s, phis, ev, phi, p, homo, eg, gam, t_sample, sigma1, Z):
     t_samples = time.perf_counter() - t0
     sig, xs = np.concatenate(sig), np.concatenate(xs)
     y = xs + np.array([sgw.sgw_sigma_omega(si, p["dt"], gam, eg)[0].real for si in sig])
-    k0 = max(0, s.n_occ - 32)
-    sel = phis[k0:k0 + 64].float().contiguous()
+    # input row: |<phi_k|zeta-bar>|^2 and the mean over l of |<phi_k|eta-bar_l>|^2
+    # for the 32 states around the gap (HOMO - 15 ... LUMO + 15)
+    k0 = max(0, s.n_occ - 16)
+    sel = phis[k0:k0 + 32].float().contiguous()
     t1 = time.perf_counter()
-    feats = sgw.cv_features(ctx, sel, p["seed"], first, n)
+    feats = torch.empty((n, 64), dtype=torch.float32, device="cuda")
+    feats[:, :32] = sgw.cv_features(ctx, sel, p["seed"], first, n)
+    sgw.cv_features_eta(ctx, sel, p["seed"], first, n, p["n_eta"], out=feats, col0=32)
     xn = feats.cpu().numpy().astype(np.float64)
     tr, va = slice(0, 3 * n // 8), slice(3 * n // 8, n // 2)
     A, B = slice(n // 2, 3 * n // 4), slice(3 * n // 4, n)
@@ -313,7 +317,8 @@ def cv_form(args, ctx, s, phis, ev, phi, p, homo, eg, gam, t_sample, sigma1, Z):
     net = sgw.Mlp(best)
     net.set_standardization(mean, std)
     g = net.forward(feats).cpu().numpy().astype(np.float64)
-    gm, gv = sgw.cv_cheap_moments(ctx, net, sel, p["seed"], first + n, args.cv_cheap, chunk=65536)
+    gm, gv = sgw.cv_cheap_moments_mixed(ctx, net, sel, sel, p["seed"], p["n_eta"], first + n,
+                                        args.cv_cheap, chunk=16384)
     torch.cuda.synchronize()
     t_cv = time.perf_counter() - t1
     net.close()
@@ -639,7 +644,7 @@ def main():
     # spectral interval by Lanczos on the device (60 steps, 1% pad), as the
     # paper obtains it by power iteration; the rigorous interval is ~17% wider
     emin, emax = ctx.lanczos_bounds(60, seed=1, pad=0.01)
-    nst = s.n_occ + 32 if args.cv else s.n_occ + 1
+    nst = s.n_occ + 16 if args.cv else s.n_occ + 1
     ev, phis, res = ksinput.lowest_states(ctx, nst, emin, emax, dV)
     homo, lumo = float(ev[s.n_occ - 1]), float(ev[s.n_occ])
     gap = lumo - homo

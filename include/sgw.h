@@ -397,7 +397,8 @@ sgw_status sgw_batch_sigma_estimate(sgw_batch_item *items, int32_t n, int32_t nw
  * Sec. 3: samples are averaged until the QP error bar is below 0.03 eV).
  * Per sample i, y_i = X_i + Re Sigma_c,i(omega) enters the QP equation
  * (Eq. 6) linearly.  A network g(x_i) of cheap features x_i of the same white
- * noise zeta_i, fitted to y on a set A, gives the estimate
+ * noise (zeta-bar_i and the eta-bar set of the sample), fitted to y on a set
+ * A, gives the estimate
  *   mean_B(y - c g) + c mean_M(g),  c = Cov_A(y, g) / Var_A(g),
  * over an evaluation set B and M cheap samples (features only).  All
  * products run on MFMA with BF16 operands and FP32 accumulation.
@@ -412,6 +413,18 @@ sgw_status sgw_batch_sigma_estimate(sgw_batch_item *items, int32_t n, int32_t nw
  * SGW_EUNSUPPORTED).  Asynchronous on the context's stream. */
 sgw_status sgw_cv_features(sgw_ctx *ctx, const float *phi, int32_t K, int64_t ld_phi,
                            uint64_t seed, int64_t first_sample, int64_t nsamp, float *x);
+
+/* Features of a sample's occupied-orbital white noise (the eta-bar set that
+ * Sec. 2.1 filters into the stochastic occupied orbitals; their density and
+ * the exchange X_i follow from it):
+ *   x[i][k] = (1/n_eta) sum_l |<phi_k|eta-bar_{i,l}>|^2,  l = 0 .. n_eta - 1,
+ * eta-bar_{i,l} the white noise that sgw_sigma_estimate draws for sample i.
+ * Arguments as sgw_cv_features; rows of x are ldx >= K floats apart (so the
+ * zeta-bar and eta-bar features of one sample can share a row).  Needs
+ * 4 nsamp n_eta K bytes of context scratch. */
+sgw_status sgw_cv_features_eta(sgw_ctx *ctx, const float *phi, int32_t K, int64_t ld_phi,
+                               uint64_t seed, int64_t first_sample, int64_t nsamp,
+                               int32_t n_eta, float *x, int64_t ldx);
 
 /* The network g(x) = w3 . tanh(W2 tanh(W1 xh + b1) + b2) + b3 with
  * xh = (x - mean) / std.  Parameters are packed W1 [h1][din], b1 [h1],
@@ -453,6 +466,14 @@ sgw_status sgw_mlp_train(sgw_mlp *mlp, const float *x, const float *y, int64_t n
 sgw_status sgw_cv_cheap_moments(sgw_ctx *ctx, sgw_mlp *mlp, const float *phi, int32_t K,
                                 int64_t ld_phi, uint64_t seed, int64_t first_sample,
                                 int64_t count, int64_t chunk, double *mean, double *var);
+/* The same for a network whose input row is [the Kz zeta-bar features over
+ * phi_z, the Ke eta-bar features over phi_e (n_eta vectors per sample)],
+ * Kz + Ke = din; either part may be empty (K = 0, its phi NULL). */
+sgw_status sgw_cv_cheap_moments_mixed(sgw_ctx *ctx, sgw_mlp *mlp, const float *phi_z,
+                                      int32_t Kz, const float *phi_e, int32_t Ke,
+                                      int64_t ld_phi, uint64_t seed, int32_t n_eta,
+                                      int64_t first_sample, int64_t count, int64_t chunk,
+                                      double *mean, double *var);
 
 typedef struct {
   double estimate;        /* the control-variate estimate, or the plain one on fallback */

@@ -11,7 +11,9 @@ variate g(x_i), computed from cheap features x_i of the same random vector,
 lowers that spread without bias when E[g] is known well:
 
   features   x_{i,k} = |<phi_k|zeta_i>|^2, k = 1..K, zeta_i the white noise of
-             sample i (+-1/sqrt(dV), the same draw the sample's filter uses);
+             sample i (+-1/sqrt(dV), the same draw the sample's filter uses),
+             and the same over the sample's occupied-orbital noise eta-bar_{i,l},
+             averaged over l (features_eta);
   network    g(x) = w3 . tanh(W2 tanh(W1 xh + b1) + b2) + b3,
              xh = (x - mean) / std with training-set statistics;
   training   mean squared error (1/n) sum (g(x_i) - y_i)^2, full-batch Adam;
@@ -44,6 +46,21 @@ def features(grid, phis, seed, samples):
         a = grid.dV * (phis @ z)
         out[j] = a * a
     return out
+
+
+def features_eta(grid, phis, seed, samples, n_eta):
+    """x[i, k] = (1/n_eta) sum_l |<phi_k|eta-bar_{i,l}>|^2 over the occupied-
+    orbital white noise of sample ``samples[i]`` (stream kind ETA, l = 0 ..
+    n_eta - 1): the draws whose filtered images give the sample's density and
+    its exchange X_i (Sec. 2.1)."""
+    phis = np.atleast_2d(np.asarray(phis, dtype=np.float64))
+    out = np.zeros((len(samples), phis.shape[0]))
+    for j, s in enumerate(samples):
+        for l in range(n_eta):
+            e = rng.white_noise(seed, rng.ETA, int(s), l, grid.N, grid.dV)
+            a = grid.dV * (phis @ e)
+            out[j] += a * a
+    return out / n_eta
 
 
 def standardization(x):

@@ -114,10 +114,13 @@ __global__ void k_phi_bf16(const float *phi, int64_t ld, int K, int64_t N, uint1
 // each 64-point chunk are staged once per workgroup in LDS (two buffers: the
 // next chunk is loaded while the current one is multiplied), so the four
 // waves share one read of phi from the cache.
+// With neta > 0 the columns are the occupied-orbital noise vectors instead:
+// column s is eta-bar_{s / neta, s % neta} (stream kind ETA), and x holds one
+// row per column (averaged over l by k_eta_mean).  Rows of x are ldx apart.
 template <int NS>
 __global__ __launch_bounds__(NT) void k_features(const uint16_t *phi16, int64_t N, int K,
                                                  uint64_t seed, int64_t s0, int64_t nsamp,
-                                                 float dV, float *x) {
+                                                 float dV, float *x, int neta, int64_t ldx) {
   constexpr int PA = 72;                           // LDS row pitch (BF16): 64 points + 8
   __shared__ __align__(16) uint16_t sa[2][64 * PA];
   const int tid = threadIdx.x;
@@ -125,8 +128,11 @@ __global__ __launch_bounds__(NT) void k_features(const uint16_t *phi16, int64_t 
   const int64_t sbase = s0 + ((int64_t)blockIdx.x * 4 + w) * (16 * NS);
   uint64_t key[NS];
 #pragma unroll
-  for (int t = 0; t < NS; ++t)
-    key[t] = rng_key(seed, rng_stream(RNG_ZETA, (uint64_t)(sbase + 16 * t + col), 0));
+  for (int t = 0; t < NS; ++t) {
+    const uint64_t c = (uint64_t)(sbase + 16 * t + col);
+    key[t] = neta > 0 ? rng_key(seed, rng_stream(RNG_ETA, c / (uint64_t)neta, c % (uint64_t)neta))
+                      : rng_key(seed, rng_stream(RNG_ZETA, c, 0));
+  }
   f32x4 acc[4][NS];
 #pragma unroll
   for (int m = 0; m < 4; ++m)
@@ -186,24 +192,52 @@ __global__ __launch_bounds__(NT) void k_features(const uint16_t *phi16, int64_t 
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int k = 16 * m + 4 * q + r;
-        if (k < K) x[(s - s0) * K + k] = dV * acc[m][t][r] * acc[m][t][r];
+        if (k < K) x[(s - s0) * ldx + k] = dV * acc[m][t][r] * acc[m][t][r];
       }
   }
 }
 
 constexpr int FEAT_NS = 4;                     // 256 samples per workgroup
 
+// x[i][k] = (1/neta) sum_l y[i neta + l][k], summed in order of l
+__global__ void k_eta_mean(const float *y, int64_t nsamp, int neta, int K, float *x,
+                           int64_t ldx) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nsamp * K) return;
+  const int64_t s = i / K;
+  const int k = (int)(i % K);
+  float acc = 0.f;
+  for (int l = 0; l < neta; ++l) acc += y[(s * neta + l) * K + k];
+  x[s * ldx + k] = acc / (float)neta;
+}
+
+// features of nsamp samples from s0 into x (rows ldx apart): zeta-bar
+// (neta = 0) or the mean over the sample's neta eta-bar vectors
 void features(sgw_ctx *ctx, const float *phi, int K, int64_t ld, uint64_t seed, int64_t s0,
-              int64_t nsamp, float *x) {
+              int64_t nsamp, float *x, int neta = 0, int64_t ldx = 0) {
   const int64_t N = ctx->N;
+  if (ldx <= 0) ldx = K;
   DevBuf &p16 = ctx->buf("cv_phi16", sizeof(uint16_t) * 64 * (size_t)N);
   hipLaunchKernelGGL(k_phi_bf16, dim3((unsigned)((64 * N + NT - 1) / NT)), dim3(NT), 0,
                      ctx->stream, phi, ld, K, N, p16.as<uint16_t>());
   SGW_HIP(hipGetLastError());
   const int64_t per = 4 * 16 * FEAT_NS;
-  const int64_t nblk = (nsamp + per - 1) / per;
+  if (neta <= 0) {
+    const int64_t nblk = (nsamp + per - 1) / per;
+    hipLaunchKernelGGL(k_features<FEAT_NS>, dim3((unsigned)nblk), dim3(NT), 0, ctx->stream,
+                       p16.as<uint16_t>(), N, K, seed, s0, nsamp, (float)ctx->dV, x, 0, ldx);
+    SGW_HIP(hipGetLastError());
+    return;
+  }
+  const int64_t ncol = nsamp * neta;
+  float *y = ctx->buf("cv_eta_cols", sizeof(float) * (size_t)ncol * K).as<float>();
+  const int64_t nblk = (ncol + per - 1) / per;
   hipLaunchKernelGGL(k_features<FEAT_NS>, dim3((unsigned)nblk), dim3(NT), 0, ctx->stream,
-                     p16.as<uint16_t>(), N, K, seed, s0, nsamp, (float)ctx->dV, x);
+                     p16.as<uint16_t>(), N, K, seed, s0 * neta, ncol, (float)ctx->dV, y, neta,
+                     (int64_t)K);
+  SGW_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_eta_mean, dim3((unsigned)((nsamp * K + NT - 1) / NT)), dim3(NT), 0,
+                     ctx->stream, y, nsamp, neta, K, x, ldx);
   SGW_HIP(hipGetLastError());
 }
 
@@ -506,6 +540,24 @@ sgw_status sgw_cv_features(sgw_ctx *ctx, const float *phi, int32_t K, int64_t ld
   });
 }
 
+sgw_status sgw_cv_features_eta(sgw_ctx *ctx, const float *phi, int32_t K, int64_t ld_phi,
+                               uint64_t seed, int64_t first_sample, int64_t nsamp,
+                               int32_t n_eta, float *x, int64_t ldx) {
+  if (!ctx) return SGW_EINVAL;
+  return guard_ctx(ctx, [&] {
+    SGW_REQUIRE(phi && x, SGW_EINVAL, "NULL argument");
+    SGW_REQUIRE(K >= 1 && K <= 64, SGW_EINVAL, "K must be in 1..64");
+    SGW_REQUIRE(n_eta >= 1 && n_eta < (1 << 20), SGW_EINVAL, "n_eta must be in 1..2^20-1");
+    SGW_REQUIRE(ldx >= K, SGW_EINVAL, "ldx < K");
+    SGW_REQUIRE(ld_phi >= ctx->N, SGW_EINVAL, "ld_phi < number of grid points");
+    SGW_REQUIRE(nsamp >= 0 && first_sample >= 0 && first_sample + nsamp <= ((int64_t)1 << 20),
+                SGW_EINVAL, "sample indices must lie in [0, 2^20)");
+    SGW_REQUIRE(ctx->N % 64 == 0, SGW_EUNSUPPORTED, "features need N divisible by 64");
+    if (nsamp == 0) return;
+    features(ctx, phi, K, ld_phi, seed, first_sample, nsamp, x, n_eta, ldx);
+  });
+}
+
 sgw_status sgw_mlp_create(int32_t din, int32_t h1, int32_t h2, const double *theta0,
                           void *hip_stream, sgw_mlp **out) {
   if (out) *out = nullptr;
@@ -667,6 +719,52 @@ sgw_status sgw_cv_cheap_moments(sgw_ctx *ctx, sgw_mlp *M, const float *phi, int3
     for (int64_t c = 0; c < nch; ++c) {
       const int64_t s0 = first_sample + c * chunk, n = std::min(chunk, count - c * chunk);
       features(ctx, phi, K, ld_phi, seed, s0, n, xf);
+      forward(M, xf, n, a);
+      dsum<1>(ctx->stream, a.g, nullptr, n, part, sums + 2 * c);
+      dsum<2>(ctx->stream, a.g, nullptr, n, part, sums + 2 * c + 1);
+    }
+    std::vector<double> h(2 * nch);
+    SGW_HIP(hipMemcpyAsync(h.data(), sums, sizeof(double) * 2 * nch, hipMemcpyDeviceToHost,
+                           ctx->stream));
+    SGW_HIP(hipStreamSynchronize(ctx->stream));
+    double s1 = 0, s2 = 0;
+    for (int64_t c = 0; c < nch; ++c) { s1 += h[2 * c]; s2 += h[2 * c + 1]; }
+    const double m = s1 / (double)count;
+    *mean = m;
+    *var = std::max(0.0, (s2 - (double)count * m * m) / (double)(count - 1));
+  });
+}
+
+sgw_status sgw_cv_cheap_moments_mixed(sgw_ctx *ctx, sgw_mlp *M, const float *phi_z, int32_t Kz,
+                                      const float *phi_e, int32_t Ke, int64_t ld_phi,
+                                      uint64_t seed, int32_t n_eta, int64_t first_sample,
+                                      int64_t count, int64_t chunk, double *mean, double *var) {
+  if (!ctx || !M) return SGW_EINVAL;
+  return guard_ctx(ctx, [&] {
+    SGW_REQUIRE(mean && var && (Kz == 0 || phi_z) && (Ke == 0 || phi_e), SGW_EINVAL,
+                "NULL argument");
+    SGW_REQUIRE(Kz >= 0 && Kz <= 64 && Ke >= 0 && Ke <= 64 && Kz + Ke >= 1, SGW_EINVAL,
+                "Kz and Ke must be in 0..64, not both 0");
+    SGW_REQUIRE(Kz + Ke == M->din, SGW_EINVAL, "Kz + Ke must equal the network's input size");
+    SGW_REQUIRE(Ke == 0 || (n_eta >= 1 && n_eta < (1 << 20)), SGW_EINVAL,
+                "n_eta must be in 1..2^20-1");
+    SGW_REQUIRE(count >= 2 && chunk >= 1, SGW_EINVAL, "count >= 2 and chunk >= 1 required");
+    SGW_REQUIRE(ld_phi >= ctx->N, SGW_EINVAL, "ld_phi < number of grid points");
+    SGW_REQUIRE(first_sample >= 0 && first_sample + count <= ((int64_t)1 << 20), SGW_EINVAL,
+                "sample indices must lie in [0, 2^20)");
+    SGW_REQUIRE(ctx->N % 64 == 0, SGW_EUNSUPPORTED, "features need N divisible by 64");
+    SGW_REQUIRE(ctx->stream == M->stream, SGW_EINVAL, "context and network need one stream");
+    const int K = Kz + Ke;
+    chunk = std::min(chunk, count);
+    float *xf = ctx->buf("cv_x", sizeof(float) * chunk * K).as<float>();
+    const Acts a = activations(M, chunk);
+    double *part = ctx->buf("cv_part", sizeof(double) * SUM_BLOCKS).as<double>();
+    const int64_t nch = (count + chunk - 1) / chunk;
+    double *sums = ctx->buf("cv_sums", sizeof(double) * 2 * nch).as<double>();
+    for (int64_t c = 0; c < nch; ++c) {
+      const int64_t s0 = first_sample + c * chunk, n = std::min(chunk, count - c * chunk);
+      if (Kz > 0) features(ctx, phi_z, Kz, ld_phi, seed, s0, n, xf, 0, K);
+      if (Ke > 0) features(ctx, phi_e, Ke, ld_phi, seed, s0, n, xf + Kz, n_eta, K);
       forward(M, xf, n, a);
       dsum<1>(ctx->stream, a.g, nullptr, n, part, sums + 2 * c);
       dsum<2>(ctx->stream, a.g, nullptr, n, part, sums + 2 * c + 1);

@@ -29,7 +29,7 @@ EXPORTS = ["sgw_create", "sgw_destroy", "sgw_last_error", "sgw_bounds", "sgw_lan
            "sgw_cheb_propagate", "sgw_tdh_init", "sgw_tdh_step", "sgw_sigma_estimate",
            "sgw_sigma_estimate_states",
            "sgw_qp_solve", "sgw_sigma_omega", "sgw_kernel_timer", "sgw_kernel_timer_read", "sgw_kb_stats",
-           "sgw_use_graphs", "sgw_batch_sigma_estimate", "sgw_cv_features", "sgw_mlp_create", "sgw_mlp_destroy", "sgw_mlp_last_error",
+           "sgw_use_graphs", "sgw_batch_sigma_estimate", "sgw_cv_features", "sgw_cv_features_eta", "sgw_cv_cheap_moments_mixed", "sgw_mlp_create", "sgw_mlp_destroy", "sgw_mlp_last_error",
            "sgw_mlp_set_standardization", "sgw_mlp_get_params", "sgw_mlp_forward",
            "sgw_mlp_gradient", "sgw_mlp_adam", "sgw_mlp_train", "sgw_cv_cheap_moments",
            "sgw_cv_estimate"]
@@ -138,6 +138,9 @@ def load():
     lib.sgw_mlp_adam.argtypes = [vp, dp, d, d, d, d]
     lib.sgw_mlp_train.argtypes = [vp, fp, fp, i64, i32, d, dp]
     lib.sgw_cv_cheap_moments.argtypes = [vp, vp, fp, i32, i64, u64, i64, i64, i64, dp, dp]
+    lib.sgw_cv_features_eta.argtypes = [vp, fp, i32, i64, u64, i64, i64, i32, fp, i64]
+    lib.sgw_cv_cheap_moments_mixed.argtypes = [vp, vp, fp, i32, fp, i32, i64, u64, i32, i64,
+                                               i64, i64, dp, dp]
     lib.sgw_cv_estimate.argtypes = [dp, dp, i64, dp, dp, i64, d, d, i64,
                                     C.POINTER(SgwCvResult)]
     for name in EXPORTS:
@@ -419,6 +422,41 @@ def cv_features(ctx, phi, seed, first_sample, nsamp, out=None):
                                   int(first_sample), int(nsamp), _fdev(out, "x", nsamp * K)),
            ctx.ctx)
     return out
+
+
+def cv_features_eta(ctx, phi, seed, first_sample, nsamp, n_eta, out=None, col0=0):
+    """x[i][k] = mean over l < n_eta of |<phi_k|eta-bar_{i,l}>|^2 (phi: float32
+    [K][N] on the GPU); returns a float32 [nsamp][K] tensor, or writes
+    columns col0 .. col0 + K - 1 of the given [nsamp][ldx] tensor."""
+    import torch
+    K = phi.shape[0]
+    if out is None:
+        out = torch.empty((nsamp, K), dtype=torch.float32, device="cuda")
+    ldx = out.shape[-1]
+    if out.dim() != 2 or out.shape[0] < nsamp or col0 + K > ldx:
+        raise ValueError("out must be [nsamp][ldx] with room for K columns at col0")
+    _fdev(out, "x", nsamp * ldx)
+    ptr = C.c_void_p(out.data_ptr() + 4 * col0)
+    _check(load().sgw_cv_features_eta(ctx.ctx, _fdev(phi, "phi"), K, phi.shape[-1], int(seed),
+                                      int(first_sample), int(nsamp), int(n_eta), ptr, ldx),
+           ctx.ctx)
+    return out
+
+
+def cv_cheap_moments_mixed(ctx, mlp, phi_z, phi_e, seed, n_eta, first_sample, count,
+                           chunk=65536):
+    """Cheap-sample mean and variance of g for the input row [zeta-bar
+    features over phi_z, eta-bar features over phi_e] (either may be None)."""
+    m, v = C.c_double(), C.c_double()
+    kz = 0 if phi_z is None else phi_z.shape[0]
+    ke = 0 if phi_e is None else phi_e.shape[0]
+    ld = (phi_z if phi_z is not None else phi_e).shape[-1]
+    pz = _fdev(phi_z, "phi_z") if phi_z is not None else None
+    pe = _fdev(phi_e, "phi_e") if phi_e is not None else None
+    _check(load().sgw_cv_cheap_moments_mixed(ctx.ctx, mlp.mlp, pz, kz, pe, ke, ld, int(seed),
+                                             int(n_eta), int(first_sample), int(count),
+                                             int(chunk), C.byref(m), C.byref(v)), ctx.ctx)
+    return m.value, v.value
 
 
 def cv_cheap_moments(ctx, mlp, phi, seed, first_sample, count, chunk=65536):

@@ -125,6 +125,36 @@ def test_features_reject_bad_sizes(tiny8):
     ctx.close()
 
 
+@pytest.mark.parametrize("which,K,first,nsamp,neta", [("tiny8", 16, 0, 120, 5),
+                                                       ("cfg1", 32, 700, 40, 8)])
+def test_features_eta_match_oracle(which, K, first, nsamp, neta, request):
+    """Occupied-orbital noise features: the mean over l of a_l^2 with each
+    a_l bounded as in the zeta-bar features (BF16 phi, FP32 sums), written
+    into columns 7 .. 7 + K - 1 of wider rows; against the FP64 oracle and,
+    tightly, the BF16 rounding model."""
+    s, H = request.getfixturevalue(which)
+    g = H.grid
+    rs = np.random.default_rng(32)
+    phi = rs.standard_normal((K, g.N))
+    phi /= np.sqrt(g.dV * np.sum(phi * phi, axis=1))[:, None]
+    phi = phi.astype(np.float32).astype(np.float64)
+    ctx = sgw.Context(s.grid.n, s.grid.h, s.v_loc, None, precision=sgw.SGW_C64, max_nvec=4)
+    out = torch.full((nsamp, K + 9), -1.0, dtype=torch.float32, device="cuda")
+    sgw.cv_features_eta(ctx, f32(phi), 78, first, nsamp, neta, out=out, col0=7)
+    got_all = out.cpu().numpy().astype(np.float64)
+    ctx.close()
+    assert np.all(got_all[:, :7] == -1.0) and np.all(got_all[:, 7 + K:] == -1.0)
+    got = got_all[:, 7:7 + K]
+    ref = cv.features_eta(g, phi, 78, range(first, first + nsamp), neta)
+    da = np.sqrt(g.dV) * np.sum(np.abs(phi), axis=1) * (U_BF16 + g.N * 2.0 ** -24)
+    # |mean_l a_l^2 - mean_l b_l^2| <= mean_l (2 |b_l| da + da^2) <= 2 sqrt(mean b^2) da + da^2
+    assert np.all(np.abs(got - ref) <= 2 * np.sqrt(ref) * da[None] + da[None] ** 2)
+    signs = np.stack([[cv.rng.white_noise_signs(78, cv.rng.stream_id(cv.rng.ETA, i, l), g.N)
+                       for l in range(neta)] for i in range(first, first + nsamp)])
+    model = np.mean(g.dV * np.einsum("kn,iln->ilk", bf16(phi), signs) ** 2, axis=1)
+    assert np.max(np.abs(got - model)) < 1e-4 * np.max(model)
+
+
 # ------------------------------------------------------------------ network
 @pytest.fixture(scope="module")
 def net_case():
@@ -261,6 +291,32 @@ def test_cheap_moments_match_model(tiny8, net_case):
     assert abs(var / go.var(ddof=1) - 1) < 0.05
 
 
+def test_cheap_moments_mixed_match_model(tiny8):
+    """Mean and variance of g over 3000 cheap samples whose input rows are
+    [16 zeta-bar features, 48 eta-bar features (N_eta = 6)], device chunks of
+    700, against the FP64 oracle."""
+    s, H = tiny8
+    g = H.grid
+    th = systems.mlp_init(8)
+    rs = np.random.default_rng(35)
+    phi = rs.standard_normal((64, g.N))
+    phi /= np.sqrt(g.dV * np.sum(phi * phi, axis=1))[:, None]
+    phi = phi.astype(np.float32).astype(np.float64)
+    pz, pe = phi[:16], phi[16:]
+    ctx = sgw.Context(s.grid.n, s.grid.h, s.v_loc, None, precision=sgw.SGW_C64, max_nvec=4)
+    m = sgw.Mlp(th)
+    x = np.hstack([cv.features(g, pz, 11, range(2000, 5000)),
+                   cv.features_eta(g, pe, 11, range(2000, 5000), 6)])
+    mean, std = cv.standardization(x)
+    m.set_standardization(mean, std)
+    mu, var = sgw.cv_cheap_moments_mixed(ctx, m, f32(pz), f32(pe), 11, 6, 2000, 3000, chunk=700)
+    m.close()
+    ctx.close()
+    go, _ = cv.forward(th, (x - mean) / std)
+    assert abs(mu - go.mean()) < 0.02 * go.std()
+    assert abs(var / go.var(ddof=1) - 1) < 0.05
+
+
 # ------------------------------------------------------------------ gain
 def test_control_variate_gain_on_sgw_samples(tiny8, tiny8_eig):
     """Plain sGW on the 8^3 system (N_eta = 32, exact mode) gives per-sample
@@ -291,9 +347,11 @@ def test_control_variate_gain_on_sgw_samples(tiny8, tiny8_eig):
     gam = oqp.default_gamma(p["n_tau"], p["dt"])
     eqp = sgw.sgw_qp_solve(sig.mean(0), p["dt"], gam, e[ho], xs.mean())[0]
     y = xs + np.array([sgw.sgw_sigma_omega(si, p["dt"], gam, eqp)[0].real for si in sig])
-    Vn = V[:64] / np.sqrt(H.grid.dV * np.sum(V[:64] ** 2, axis=1))[:, None]
+    Vn = V[:32] / np.sqrt(H.grid.dV * np.sum(V[:32] ** 2, axis=1))[:, None]
     phi = f32(Vn)
-    x = sgw.cv_features(ctx, phi, p["seed"], 0, n)
+    x = torch.empty((n, 64), dtype=torch.float32, device="cuda")
+    x[:, :32] = sgw.cv_features(ctx, phi, p["seed"], 0, n)
+    sgw.cv_features_eta(ctx, phi, p["seed"], 0, n, p["n_eta"], out=x, col0=32)
     xn = x.cpu().numpy().astype(np.float64)
     tr, va, A, B = slice(0, 1536), slice(1536, 2048), slice(2048, 3072), slice(3072, 4096)
     mean, std = cv.standardization(xn[tr])
@@ -312,7 +370,8 @@ def test_control_variate_gain_on_sgw_samples(tiny8, tiny8_eig):
     m = sgw.Mlp(best)
     m.set_standardization(mean, std)
     g = m.forward(x).cpu().numpy().astype(np.float64)
-    gm, gvar = sgw.cv_cheap_moments(ctx, m, phi, p["seed"], 10000, 50000, chunk=8192)
+    gm, gvar = sgw.cv_cheap_moments_mixed(ctx, m, phi, phi, p["seed"], p["n_eta"], 10000, 50000,
+                                          chunk=8192)
     m.close()
     ctx.close()
     r = sgw.sgw_cv_estimate(y[A], g[A], y[B], g[B], gm, gvar, 50000)

@@ -99,6 +99,41 @@ def test_features_mean_is_norm():
     assert np.all(np.abs(x.mean(axis=0) - 1.0) < 5 * np.sqrt(2.0 / 3000))
 
 
+def test_features_eta_parseval_and_mean():
+    """Occupied-orbital noise features: over a complete dV-orthonormal basis
+    the mean over l of sum_k |<phi_k|eta_l>|^2 is <eta|eta> = N exactly; for a
+    normalised phi the sample mean over 1500 samples x 4 vectors is 1 within
+    5 standard errors (variance below 2 / 4 per sample)."""
+    g = Grid(4, h=0.6)
+    rs = np.random.default_rng(13)
+    Q, _ = np.linalg.qr(rs.standard_normal((g.N, g.N)))
+    x = cv.features_eta(g, Q.T / np.sqrt(g.dV), seed=99, samples=[0, 3, 70], n_eta=3)
+    assert np.allclose(x.sum(axis=1), g.N, rtol=1e-12)
+    g = Grid(8, h=0.5)
+    phi = rs.standard_normal((2, g.N))
+    phi /= np.sqrt(g.dV * np.sum(phi * phi, axis=1))[:, None]
+    x = cv.features_eta(g, phi, seed=5, samples=range(1500), n_eta=4)
+    assert np.all(np.abs(x.mean(axis=0) - 1.0) < 5 * np.sqrt(0.5 / 1500))
+
+
+def test_features_eta_use_the_estimators_draws():
+    """The eta-bar features of sample i are those of the white-noise set that
+    the estimator filters for sample i (and not of another stream): against
+    the projections of sigma.white_noise_sets' eta set."""
+    from oracle.sigma import SGWParams, white_noise_sets
+    g = Grid(8, h=0.5)
+    rs = np.random.default_rng(14)
+    phi = rs.standard_normal((3, g.N))
+    p = SGWParams(seed=21, n_zeta=1, n_eta=6, n_tau=1, dt=0.1, m_sub=1, mu=0.0, beta=1.0,
+                  ncoef=2, emin=-1.0, emax=1.0)
+    for i in (0, 9):
+        zb, eb = white_noise_sets(g, p, i)
+        ref = np.mean((g.dV * eb @ phi.T) ** 2, axis=0)
+        got = cv.features_eta(g, phi, 21, [i], 6)[0]
+        assert np.allclose(got, ref, rtol=1e-13)
+        assert not np.allclose(got, (g.dV * phi @ zb) ** 2, rtol=1e-3)
+
+
 def test_cv_unbiased_and_variance_ratio():
     """y = 2 + 3 u + e (u, e standard normal), g = u with E[g] = 0: over 400
     repetitions the estimator's mean is 2 within 4 standard errors and its
