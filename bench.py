@@ -99,6 +99,13 @@ def parse():
     ap.add_argument("--cfg4-ntau", type=int, default=400)
     ap.add_argument("--cfg4-workers", type=int, default=8)
     ap.add_argument("--cfg4-small-only", action="store_true")
+    ap.add_argument("--cfg5", action="store_true",
+                    help="control-variate mode on the 160^3 Si705H300-shaped cluster")
+    ap.add_argument("--cfg5-first", type=int, default=0)
+    ap.add_argument("--cfg5-count", type=int, default=0)
+    ap.add_argument("--cfg5-load", default="")
+    ap.add_argument("--cfg5-out", default="")
+    ap.add_argument("--cfg5-cheap", type=int, default=0)
     ap.add_argument("--counters", action="store_true",
                     help="counter-profile driver only: a 256 MiB device copy, filter terms "
                          "at the bench launch shape and H applications on --hpsi-nvec "
@@ -576,6 +583,144 @@ def cfg4_mode(args):
     print(json.dumps(out), flush=True)
 
 
+def cfg5_mode(args):
+    """Learned control variate on the Si705H300-shaped cluster (160^3, h = 0.6
+    bohr, 3120 projectors, 1560 occupied states), complex FP32.  Plain sGW
+    samples (N_eta = 8, N_tau = 400 x 0.05 au, N_xi = 10000 at f_g = 0.003,
+    gapped filter with its transition over >= 0.3 Ha around mid-gap) in
+    batches of 32 (512 TDH orbitals per launch), with the features of every
+    sample ([|<phi_k|zeta-bar>|^2, mean_l |<phi_k|eta-bar_l>|^2] over the 32
+    states HOMO - 15 ... LUMO + 15).  Samples computed in earlier calls are
+    read from --cfg5-load (npz files written by --cfg5-out); with
+    --cfg5-cheap M > 0 the network is trained and evaluated (3/8 train, 1/8
+    validation, 1/4 fit of c, 1/4 evaluation) and E[g] taken over M cheap
+    samples.  Prints one JSON line."""
+    import hashlib
+    import numpy as np
+    import torch
+    from paper_2601_21005_amd import ksinput, sgw, systems
+    t0 = time.perf_counter()
+    s = systems.si705h300()
+    dV = s.grid.h ** 3
+    ctx = sgw.Context(s.grid.n, s.grid.h, s.v_loc, s.projectors, precision=sgw.SGW_C64,
+                      ecut=s.ecut, max_nvec=512)
+    emin, emax = ctx.lanczos_bounds(60, seed=1, pad=0.01)
+    progress(f"cfg5: context and interval [{emin:.4f}, {emax:.4f}] "
+             f"({time.perf_counter() - t0:.1f} s)")
+    t1 = time.perf_counter()
+    ev, phis, res, its = ksinput.lowest_states_lean(ctx, s.n_occ + 16, emin, emax, dV)
+    t_ks = time.perf_counter() - t1
+    torch.cuda.empty_cache()
+    homo, lumo = float(ev[s.n_occ - 1]), float(ev[s.n_occ])
+    sel = phis[s.n_occ - 16:s.n_occ + 16].contiguous()
+    phi = phis[s.n_occ - 1].double().cpu().numpy()
+    del phis
+    torch.cuda.empty_cache()
+    digest = hashlib.sha256(sel.cpu().numpy().tobytes()).hexdigest()[:16]
+    progress(f"cfg5: {s.n_occ + 16} KS states in {t_ks:.1f} s ({its} iterations, max residual "
+             f"{res.max():.1e}); HOMO {homo:.6f} LUMO {lumo:.6f} Ha; states digest {digest}")
+    mid, half = 0.5 * (homo + lumo), max(0.5 * (lumo - homo), 0.15)
+    eh, el = mid - half, mid + half
+    ncoef = suggested_ncoef(sgw, eh, el, 1e-7, emin, emax, 1e-7)
+    p = dict(seed=1006, n_eta=8, n_tau=400, dt=0.05, m_sub=1, ncoef=ncoef, emin=emin,
+             emax=emax, n_xi=10000, f_g=0.003, mode=0, filter=1, e_homo=eh, e_lumo=el,
+             filter_eps=1e-7)
+    B = 32
+    sig_l, x_l, f_l, idx_l = [], [], [], []
+    t_samples, n_new = 0.0, 0
+    for f in (args.cfg5_load.split(",") if args.cfg5_load else []):
+        d = np.load(f)
+        if str(d["digest"]) != digest:
+            raise RuntimeError(f"{f}: KS states differ from this run's ({d['digest']} != {digest})")
+        sig_l.append(d["sig"]); x_l.append(d["x"]); f_l.append(d["feat"]); idx_l.append(d["idx"])
+        t_samples += float(d["seconds"])
+    for b0 in range(args.cfg5_first, args.cfg5_first + args.cfg5_count, B):
+        nb = min(B, args.cfg5_first + args.cfg5_count - b0)
+        t2 = time.perf_counter()
+        sig, x, _ = ctx.sigma_estimate(phi, n_zeta=nb, first_sample=b0, **p)
+        torch.cuda.synchronize()
+        t_samples += time.perf_counter() - t2
+        n_new += nb
+        feats = torch.empty((nb, 64), dtype=torch.float32, device="cuda")
+        feats[:, :32] = sgw.cv_features(ctx, sel, p["seed"], b0, nb)
+        sgw.cv_features_eta(ctx, sel, p["seed"], b0, nb, p["n_eta"], out=feats, col0=32)
+        sig_l.append(sig); x_l.append(x); f_l.append(feats.cpu().numpy())
+        idx_l.append(np.arange(b0, b0 + nb))
+        progress(f"cfg5: samples {b0} .. {b0 + nb - 1} ({(time.perf_counter() - t2) / nb:.2f} s "
+                 f"each)")
+    sig, x = np.concatenate(sig_l), np.concatenate(x_l)
+    feat, idx = np.concatenate(f_l), np.concatenate(idx_l)
+    if args.cfg5_out and n_new:
+        new = slice(sig.shape[0] - n_new, sig.shape[0])
+        np.savez_compressed(args.cfg5_out, sig=sig[new], x=x[new], feat=feat[new], idx=idx[new],
+                            digest=digest, seconds=t_samples - sum(
+                                float(np.load(f)["seconds"]) for f in
+                                (args.cfg5_load.split(",") if args.cfg5_load else [])))
+    n = sig.shape[0]
+    t_sample = t_samples / n
+    out = {"mode": "cfg5", "workload": "Si705H300-shaped cluster, 160^3 h=0.6, 3120 KB "
+                                       "projectors, N_eta=8, TDH 400 x 0.05 au, N_xi=10000, "
+                                       "gapped filter, complex FP32",
+           "samples": n, "ncoef": ncoef, "homo_lumo_Ha": [homo, lumo],
+           "interval_Ha": [emin, emax], "ks_states_s": t_ks, "states_digest": digest,
+           "gpu_s_per_sample": t_sample}
+    gam = 3.0 / (p["n_tau"] * p["dt"])
+    eg, el, Z = sgw.sgw_qp_solve(sig.mean(0), p["dt"], gam, homo, x.mean())
+    y = x + np.array([sgw.sgw_sigma_omega(si, p["dt"], gam, eg)[0].real for si in sig])
+    sd = float(Z * np.std(y, ddof=1) * HA_EV)
+    out.update({"eqp_homo_eV": eg * HA_EV, "Z": Z, "plain_sigma1_eV": sd,
+                "plain_gpu_s_per_qp": t_sample * (sd / 0.03) ** 2})
+    if args.cfg5_cheap > 0 and n >= 64:
+        t3 = time.perf_counter()
+        n8 = n - n % 8
+        tr, va = slice(0, 3 * n8 // 8), slice(3 * n8 // 8, n8 // 2)
+        A, Bs = slice(n8 // 2, 3 * n8 // 4), slice(3 * n8 // 4, n8)
+        mean, std = feat[tr].mean(axis=0), feat[tr].std(axis=0)
+        std[std == 0] = 1.0
+        ym, ysd = y[tr].mean(), y[tr].std()
+        xt = torch.from_numpy(feat.astype(np.float32)).cuda()
+        yt = torch.from_numpy(((y - ym) / ysd).astype(np.float32)).cuda()
+        net = sgw.Mlp(systems.mlp_init(3))
+        net.set_standardization(mean, std)
+        best, best_loss = None, np.inf
+        for _ in range(30):
+            net.train(xt[tr].contiguous(), yt[tr].contiguous(), 10, lr=1e-3)
+            gv = net.forward(xt[va].contiguous()).cpu().numpy().astype(np.float64)
+            loss = float(np.mean((gv - (y[va] - ym) / ysd) ** 2))
+            if loss < best_loss:
+                best, best_loss = net.params(), loss
+        net.close()
+        net = sgw.Mlp(best)
+        net.set_standardization(mean, std)
+        g = net.forward(xt).cpu().numpy().astype(np.float64)
+        t_train = time.perf_counter() - t3
+        t4 = time.perf_counter()
+        gm, gv = sgw.cv_cheap_moments_mixed(ctx, net, sel, sel, p["seed"], p["n_eta"],
+                                            1 << 19, min(args.cfg5_cheap, (1 << 20) - (1 << 19)),
+                                            chunk=8192)
+        torch.cuda.synchronize()
+        t_cheap = time.perf_counter() - t4
+        net.close()
+        M = min(args.cfg5_cheap, (1 << 20) - (1 << 19))
+        r = sgw.sgw_cv_estimate(y[A], g[A], y[Bs], g[Bs], gm, gv, M)
+        nB = Bs.stop - Bs.start
+        sd_cv = float(r["sigma_cv"] * np.sqrt(nB))
+        plain_B = float(np.std(y[Bs], ddof=1))
+        s_cv, s_pl = Z * sd_cv * HA_EV, Z * plain_B * HA_EV
+        out["control_variate"] = {
+            "train": tr.stop, "validation": va.stop - va.start, "fit_A": A.stop - A.start,
+            "eval_B": nB, "cheap_samples": M, "rho2_A": r["rho2"],
+            "variance_ratio_B": (sd_cv / plain_B) ** 2, "fallback": r["fallback"],
+            "cv_estimate": r["estimate"], "plain_estimate": r["plain"],
+            "sigma1_cv_eV": s_cv, "sigma1_plain_B_eV": s_pl,
+            "train_s": t_train, "cheap_s": t_cheap,
+            "gpu_s_per_qp_cv": t_sample * (s_cv / 0.03) ** 2 + t_train + t_cheap,
+            "gpu_s_per_qp_plain_same_set": t_sample * (s_pl / 0.03) ** 2}
+        progress(f"cfg5: control variate ratio {(sd_cv / plain_B) ** 2:.3f}")
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def counters_driver(args):
     """Workload for rocprofv3 counter runs (one counter set per run): a plain
     256 MiB device copy (the reference that scales FETCH_SIZE / WRITE_SIZE to
@@ -633,6 +778,9 @@ def main():
         return
     if args.cfg4:
         cfg4_mode(args)
+        return
+    if args.cfg5:
+        cfg5_mode(args)
         return
     if args.quick:
         args.n_tau, args.n_eta, args.batch = 20, 8, 2

@@ -78,3 +78,80 @@ def lowest_states(ctx, nstates, emin, emax, dV, block=None, degree=16, tol=None,
         a = float(w[-1])
     phi = Y[:nstates] / np.sqrt(dV)
     return lam[:nstates].cpu().numpy(), phi, res[:nstates].cpu().numpy()
+
+
+def _gram64(A, B, chunk=1 << 18):
+    """A B^T accumulated in FP64 over column chunks (A, B: (k, N) FP32 on the
+    device); returned on the host."""
+    import torch
+    k = A.shape[0]
+    G = torch.zeros((k, B.shape[0]), dtype=torch.float64, device=A.device)
+    for c0 in range(0, A.shape[1], chunk):
+        G += A[:, c0:c0 + chunk].double() @ B[:, c0:c0 + chunk].double().T
+    return G.cpu()
+
+
+def lowest_states_lean(ctx, nstates, emin, emax, dV, block=None, degree=16, tol=1e-4,
+                       maxit=120, seed=0):
+    """lowest_states for blocks too large to hold in FP64: the block and its
+    filter recurrence are kept in FP32 and updated in place (three blocks and
+    the two complex work arrays of the H applications live at once); the
+    Gram and Rayleigh-Ritz products accumulate in FP64 over chunks of the
+    grid.  Same filter and iteration; residuals converge to about 1e-5."""
+    import torch
+    N = ctx.N
+    k = block or (nstates + max(8, nstates // 5))
+    k += k % 2
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    Y = torch.randn((k, N), generator=g, device="cuda", dtype=torch.float32)
+    win = torch.zeros((k // 2, N), dtype=ctx.cdtype, device="cuda")
+    wout = torch.zeros_like(win)
+    HY = torch.empty_like(Y)
+
+    def apply(X, out):
+        win.copy_(torch.complex(X[0::2], X[1::2]).to(win.dtype))
+        ctx.apply_H(win, wout)
+        out[0::2] = wout.real
+        out[1::2] = wout.imag
+
+    a = emin + 0.1 * (emax - emin)
+    lam = res = None
+    Yp = torch.empty_like(Y)
+    for it in range(maxit):
+        c = 0.5 * (a + emax)
+        e = 0.5 * (emax - a)
+        x0 = (emin - c) / e
+        sig = 1.0 / x0
+        Yp.copy_(Y)                                   # v_0
+        apply(Y, HY)
+        Y.mul_(-c).add_(HY).mul_(sig / e)             # v_1
+        for _ in range(2, degree + 1):
+            sig2 = 1.0 / (2.0 * x0 - sig)
+            apply(Y, HY)
+            # v_{n+1} = (H v_n - c v_n) 2 sig2 / e - sig sig2 v_{n-1}, into Yp
+            Yp.mul_(-sig * sig2).add_(HY, alpha=2.0 * sig2 / e).add_(Y, alpha=-2.0 * c * sig2 / e)
+            Y, Yp = Yp, Y
+            sig = sig2
+        for _ in range(2):                            # Cholesky QR, FP64 Gram
+            G = _gram64(Y, Y)
+            Linv = torch.linalg.inv(torch.linalg.cholesky(G)).float().to(Y.device)
+            torch.matmul(Linv, Y, out=HY)
+            Y, HY = HY, Y
+        apply(Y, HY)
+        Hs = _gram64(Y, HY)
+        Hs = 0.5 * (Hs + Hs.T)
+        w, Q = torch.linalg.eigh(Hs)
+        Qd = Q.float().to(Y.device)
+        torch.matmul(Qd.T, Y, out=Yp)
+        Y, Yp = Yp, Y
+        torch.matmul(Qd.T, HY, out=Yp)                # rotated H Y
+        lam = w
+        wd = w.float().to(Y.device)
+        res = torch.cat([torch.linalg.norm(Yp[r:r + 256] - wd[r:r + 256, None] * Y[r:r + 256],
+                                           dim=1) for r in range(0, k, 256)])
+        if float(res[:nstates].max()) < tol:
+            break
+        a = float(w[-1])
+    del Yp, HY, win, wout
+    phi = Y[:nstates] / float(np.sqrt(dV))
+    return lam[:nstates].cpu().numpy(), phi, res[:nstates].cpu().numpy(), it + 1

@@ -209,6 +209,13 @@ SHELLS = (5, 17, 29, 35, 47, 71, 87, 99, 123, 147)     # atom-centred shell clos
 BATCH_SIZES = (40, 48, 56, 64, 80, 96, 112)            # FFT lengths for the uneven batch
 
 
+def si705h300(seed=1006, n=160, h=0.6, ecut=28.0):
+    """The Si705H300-shaped cluster (705 Si, 300 H caps: 3120 projectors,
+    1560 occupied states) on a 160^3 grid (h = 0.6 bohr)."""
+    species, pos = si_cluster(705, seed=seed)
+    return cluster_model(species, pos, n=n, h=h, ecut=ecut, name="Si705H300")
+
+
 def uneven_batch(count=32, seed=1004, h=0.6, margin=8.0, ecut=28.0):
     """Uneven batch of H-capped Si clusters: for each of ``count`` clusters a
     seeded shell size from SHELLS (5 to 147 Si), its own jitter seed, the

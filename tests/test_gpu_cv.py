@@ -320,14 +320,16 @@ def test_cheap_moments_mixed_match_model(tiny8):
 # ------------------------------------------------------------------ gain
 def test_control_variate_gain_on_sgw_samples(tiny8, tiny8_eig):
     """Plain sGW on the 8^3 system (N_eta = 32, exact mode) gives per-sample
-    y_i = X_i + Re Sigma_c,i(omega*) for 4096 samples.  A network on
-    |<phi_k|zeta_i>|^2 over the 64 lowest states is trained on 1536 of them
-    (early-stopped on 512 more), c is fitted on 1024 others (A) and the
-    estimate taken on the last 1024 (B) with 50000 cheap samples for E[g].
-    The gain must be significant: the variance ratio on B (measured about
-    0.86, nearly all from the HOMO's own projection) plus three of its
-    jackknife standard errors over the B samples stays below 1, and the
-    estimate agrees with the plain mean (no fallback)."""
+    y_i = X_i + Re Sigma_c,i(omega*) for 4096 samples.  A network on the
+    sample's cheap projections -- |<phi_k|zeta-bar_i>|^2 and the mean over l
+    of |<phi_k|eta-bar_{i,l}>|^2 over the 32 lowest states -- is trained on
+    1536 of them (early-stopped on 512 more), c is fitted on 1024 others (A)
+    and the estimate taken on the last 1024 (B) with 50000 cheap samples for
+    E[g].  The variance ratio on B (measured 0.24) plus three of its
+    jackknife standard errors over the B samples stays below 0.6 (linear fits
+    of the same features on the oracle's samples explain 80 % of the
+    variance, so a working estimator reaches about 0.2 up to training noise),
+    and the estimate agrees with the plain mean (no fallback)."""
     s, H = tiny8
     e, V = tiny8_eig
     ho = s.n_occ - 1
@@ -382,7 +384,7 @@ def test_control_variate_gain_on_sgw_samples(tiny8, tiny8_eig):
           f"+- {se:.3f}  cv {r['estimate']:.5f} +- {r['sigma_cv']:.5f}  "
           f"plain {r['plain']:.5f}  fallback {r['fallback']}", flush=True)
     assert not r["fallback"]
-    assert ratio + 3.0 * se < 1.0
+    assert ratio + 3.0 * se < 0.6
 
 
 def variance_ratio_jackknife_se(y, g, c, var_mean_term):
