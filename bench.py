@@ -695,13 +695,13 @@ def cfg5_mode(args):
         g = net.forward(xt).cpu().numpy().astype(np.float64)
         t_train = time.perf_counter() - t3
         t4 = time.perf_counter()
-        gm, gv = sgw.cv_cheap_moments_mixed(ctx, net, sel, sel, p["seed"], p["n_eta"],
-                                            1 << 19, min(args.cfg5_cheap, (1 << 20) - (1 << 19)),
+        # cheap samples: fresh sample indices from 4096 on (the plain ones are below)
+        M = min(args.cfg5_cheap, (1 << 20) - 4096)
+        gm, gv = sgw.cv_cheap_moments_mixed(ctx, net, sel, sel, p["seed"], p["n_eta"], 4096, M,
                                             chunk=8192)
         torch.cuda.synchronize()
         t_cheap = time.perf_counter() - t4
         net.close()
-        M = min(args.cfg5_cheap, (1 << 20) - (1 << 19))
         r = sgw.sgw_cv_estimate(y[A], g[A], y[Bs], g[Bs], gm, gv, M)
         nB = Bs.stop - Bs.start
         sd_cv = float(r["sigma_cv"] * np.sqrt(nB))

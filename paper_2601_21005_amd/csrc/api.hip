@@ -663,6 +663,9 @@ sgw_status sgw_create(const sgw_grid *grid, const double *v_loc, const sgw_proje
       upload(c->d_kb_proj_off, c->kb.proj_off.data(), c->kb.proj_off.size());
       upload(c->d_kb_proj_entries, c->kb.proj_entries.data(), c->kb.proj_entries.size());
       upload(c->d_kb_ekb, c->kb.ekb.data(), c->kb.ekb.size());
+      if (const char *km = std::getenv("SGW_KB_MASK"); km && std::atoi(km) == 0)
+        std::fill(c->kb.mask.begin(), c->kb.mask.end(), ~0u);   // every point live (timing)
+      upload(c->d_kb_mask, c->kb.mask.data(), c->kb.mask.size());
       upload_real(c.get(), c->d_kb_beta, c->kb.beta.data(), c->kb.beta.size());
       if (!c->dbl) kb_upload_operands(c.get());
     }

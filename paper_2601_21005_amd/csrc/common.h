@@ -84,6 +84,7 @@ struct KBHost {
   std::vector<int> proj_off;        // [nproj + 1] CSR of entries per projector
   std::vector<int> proj_entries;    // [nentry] entry ids grouped by projector
   std::vector<double> gram;         // [nproj][nproj] S = <beta_p|beta_q>
+  std::vector<uint32_t> mask;       // [ntile][16] support bits of the tile's points
 };
 
 // ---------------------------------------------------------------- autotuner cache
@@ -120,6 +121,7 @@ struct sgw_ctx {
   sgw::DevBuf d_kb_tile_offT;        // [ntile + 1] per-tile offsets of betaT in entry rows
   sgw::DevBuf d_kb_betaT;            // per tile [512][entries padded to the K group], FP32 or BF16
   sgw::DevBuf d_kb_beta16;           // [entry][512] BF16 (the BF16 precisions)
+  sgw::DevBuf d_kb_mask;             // [ntile][16] uint32: bit p set where some beta_e(p) != 0
   int kb_ntile = 0, kb_nentry = 0;
   int64_t kb_support_points = 0;     // grid points where some beta_p is nonzero
   int64_t kb_nnz = 0;                // nonzero beta values (point, projector)

@@ -168,6 +168,7 @@ void build_kb(sgw_ctx *ctx, const sgw_projectors *P) {
   // grid points inside some projector's support, and nonzero beta values
   ctx->kb_support_points = 0;
   ctx->kb_nnz = 0;
+  kb.mask.assign((size_t)ntile * (KB_TP / 32), 0u);
   for (int t = 0; t < ntile; ++t)
     for (int i = 0; i < KB_TP; ++i) {
       int hit = 0;
@@ -175,6 +176,7 @@ void build_kb(sgw_ctx *ctx, const sgw_projectors *P) {
         hit += kb.beta[(size_t)e * KB_TP + i] != 0.0;
       ctx->kb_support_points += hit > 0;
       ctx->kb_nnz += hit;
+      if (hit) kb.mask[(size_t)t * (KB_TP / 32) + i / 32] |= 1u << (i % 32);
     }
 }
 

@@ -303,7 +303,7 @@ template <class Op, int NVB, int MT, int LX>
 __global__ __launch_bounds__(NTK) void k_kb_gather_mma(
     const float2 *psi, int64_t ld, int64_t nvec, const int *tile_base, const int *tile_off,
     const typename Op::T *beta, float2 *partial, int nx, int ny, float dV, int ntile,
-    int nvb) {
+    int nvb, const uint32_t *tile_mask) {
   using T = typename Op::T;
   constexpr int NC = 2 * NVB, NTL = NC / 16;
   constexpr int EL = 16 / (int)sizeof(T);           // operand elements per lane per group
@@ -317,6 +317,17 @@ __global__ __launch_bounds__(NTK) void k_kb_gather_mma(
   const int base = tile_base[t];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, q = lane >> 4, col = lane & 15;
   const int off = tile_off[t], ne = tile_off[t + 1] - off;
+  // support bits of this wave's 128 points (4 words): groups of points where
+  // no projector reaches contribute exact zeros, so their psi is not loaded
+  // and K groups without support skip their products
+  uint32_t mw[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    mw[i] = __builtin_amdgcn_readfirstlane(tile_mask[(int64_t)t * (KB_TP / 32) + 4 * w + i]);
+  auto group_bits = [&](int g) {       // the GK support bits of K group g (wave-uniform)
+    const int o = g * Op::GK;
+    return Op::GK == 32 ? mw[o >> 5] : (mw[o >> 5] >> (o & 31)) & 0xffffu;
+  };
   // B operands of this wave's quarter of K, kept in registers for all entries
   auto load_b = [&](int64_t v0, u32x4 (*b)[NTL], u32x4 (*blo)[NSN]) {
 #pragma unroll
@@ -327,6 +338,8 @@ __global__ __launch_bounds__(NTK) void k_kb_gather_mma(
       for (int g = 0; g < NG; ++g) {
         const int p = 128 * w + g * Op::GK + EL * q;  // EL consecutive points along x
         const float4 *s4 = reinterpret_cast<const float4 *>(src + tile_point_c<LX>(base, p, nx, ny));
+        const int pl = p - 128 * w;
+        const bool live = ((mw[pl >> 5] >> (pl & 31)) & ((1u << EL) - 1u)) != 0u;
         float e[EL];
         // the lane pair (col, col ^ 1) reads each group of 4 complex values
         // once: the even lane points 0, 1 and the odd lane points 2, 3; then
@@ -335,7 +348,7 @@ __global__ __launch_bounds__(NTK) void k_kb_gather_mma(
         const int od = col & 1;
 #pragma unroll
         for (int i = 0; i < EL / 4; ++i) {
-          const float4 z = s4[2 * i + od];
+          const float4 z = live ? s4[2 * i + od] : make_float4(0.f, 0.f, 0.f, 0.f);
           const float g0 = __shfl_xor(od ? z.x : z.y, 1, 64);
           const float g1 = __shfl_xor(od ? z.z : z.w, 1, 64);
           e[4 * i] = od ? g0 : z.x;
@@ -358,6 +371,7 @@ __global__ __launch_bounds__(NTK) void k_kb_gather_mma(
       for (int n = 0; n < NTL; ++n) acc[j][n] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int g = 0; g < NG; ++g) {
+      if (group_bits(g) == 0u) continue;            // no support: the products are zero
       u32x4 a[MT];
 #pragma unroll
       for (int j = 0; j < MT; ++j) {
@@ -417,7 +431,8 @@ template <class Op, int NVB, int MJ, int LX, bool PF>
 __global__ __launch_bounds__(NTK) void k_kb_scatter_mma(
     const float2 *coef, int64_t nvec, const int *tile_base, const int *tile_off,
     const int *tile_offT, const int *entry_proj, const typename Op::T *betaT, float2 *dst,
-    int64_t ld, float s1, int nx, int ny, int ntile, int nvb, int pe) {
+    int64_t ld, float s1, int nx, int ny, int ntile, int nvb, int pe,
+    const uint32_t *tile_mask) {
   using T = typename Op::T;
   constexpr int NC = 2 * NVB, NTL = NC / 16;
   constexpr int EL = 16 / (int)sizeof(T);
@@ -445,6 +460,19 @@ __global__ __launch_bounds__(NTK) void k_kb_scatter_mma(
 #pragma unroll
   for (int j = 0; j < MJ; ++j)
     rp[j] = tile_point_c<LX>(base, p0 + 16 * (MJ * w + j) + col, nx, ny);
+  // support bits: M tile j (16 points) with none is skipped by the whole wave;
+  // otherwise the lane reads and writes its point only where a projector
+  // reaches (elsewhere the update is an exact zero)
+  uint32_t rowbits[MJ];
+  bool live[MJ];
+#pragma unroll
+  for (int j = 0; j < MJ; ++j) {
+    const int pj = p0 + 16 * (MJ * w + j);
+    const uint32_t word = __builtin_amdgcn_readfirstlane(
+        tile_mask[(int64_t)t * (KB_TP / 32) + (pj >> 5)]);
+    rowbits[j] = (word >> (pj & 31)) & 0xffffu;
+    live[j] = (rowbits[j] >> col) & 1u;
+  }
   float2 *vrow[NTL][2];
   bool vok[NTL][2];
 #pragma unroll
@@ -464,8 +492,8 @@ __global__ __launch_bounds__(NTK) void k_kb_scatter_mma(
     for (int j = 0; j < MJ; ++j)
 #pragma unroll
       for (int n = 0; n < NTL; ++n) {
-        o[j][n][0] = vrow[n][0][rp[j]];
-        o[j][n][1] = vrow[n][1][rp[j]];
+        o[j][n][0] = live[j] ? vrow[n][0][rp[j]] : make_float2(0.f, 0.f);
+        o[j][n][1] = live[j] ? vrow[n][1][rp[j]] : make_float2(0.f, 0.f);
       }
   }
   // betaT rows of this wave's points: the first K group is loaded before the
@@ -525,10 +553,11 @@ __global__ __launch_bounds__(NTK) void k_kb_scatter_mma(
     if (k0 + Op::GK < nek) load_group(k0 + Op::GK, a_nxt, b_nxt);
 #pragma unroll
     for (int j = 0; j < MJ; ++j)
+      if (rowbits[j])
 #pragma unroll
-      for (int n = 0; n < NTL; ++n)
+        for (int n = 0; n < NTL; ++n)
 #pragma unroll
-        for (int h = 0; h < NS; ++h) Op::mma(acc[j][n], b_cur[h][n], a_cur[j]);
+          for (int h = 0; h < NS; ++h) Op::mma(acc[j][n], b_cur[h][n], a_cur[j]);
 #pragma unroll
     for (int j = 0; j < MJ; ++j) a_cur[j] = a_nxt[j];
 #pragma unroll
@@ -541,8 +570,8 @@ __global__ __launch_bounds__(NTK) void k_kb_scatter_mma(
     for (int j = 0; j < MJ; ++j)
 #pragma unroll
       for (int n = 0; n < NTL; ++n) {
-        o[j][n][0] = vrow[n][0][rp[j]];
-        o[j][n][1] = vrow[n][1][rp[j]];
+        o[j][n][0] = live[j] ? vrow[n][0][rp[j]] : make_float2(0.f, 0.f);
+        o[j][n][1] = live[j] ? vrow[n][1][rp[j]] : make_float2(0.f, 0.f);
       }
   }
 #pragma unroll
@@ -550,9 +579,9 @@ __global__ __launch_bounds__(NTK) void k_kb_scatter_mma(
 #pragma unroll
     for (int n = 0; n < NTL; ++n) {
       const f32x4 d = acc[j][n];
-      if (vok[n][0])
+      if (live[j] && vok[n][0])
         vrow[n][0][rp[j]] = make_float2(o[j][n][0].x + s1 * d[0], o[j][n][0].y + s1 * d[1]);
-      if (vok[n][1])
+      if (live[j] && vok[n][1])
         vrow[n][1][rp[j]] = make_float2(o[j][n][1].x + s1 * d[2], o[j][n][1].y + s1 * d[3]);
     }
 }
@@ -569,12 +598,12 @@ template <class Op>
 static void launch_gather_variant(int vi, dim3 g, hipStream_t st, const float2 *psi, int64_t ld,
                                   int64_t nvec, const int *tb, const int *to,
                                   const typename Op::T *beta, float2 *partial, int nx, int ny,
-                                  int lx, float dV, int ntile, int nvb) {
+                                  int lx, float dV, int ntile, int nvb, const uint32_t *mask) {
   const GatherVariant v = kGather[vi];
 #define SGW_G(A, B, X)                                                                           \
   if (v.nvb == A && v.mt == B && lx == X)                                                        \
     hipLaunchKernelGGL((k_kb_gather_mma<Op, A, B, X>), g, dim3(NTK), 0, st, psi, ld, nvec, tb,  \
-                       to, beta, partial, nx, ny, dV, ntile, nvb);
+                       to, beta, partial, nx, ny, dV, ntile, nvb, mask);
   SGW_G(8, 2, 4) SGW_G(8, 4, 4) SGW_G(16, 2, 4) SGW_G(16, 4, 4)
   SGW_G(8, 2, 3) SGW_G(8, 4, 3) SGW_G(16, 2, 3) SGW_G(16, 4, 3)
 #undef SGW_G
@@ -585,7 +614,7 @@ static void launch_scatter_variant(int vi, dim3 g, hipStream_t st, const float2 
                                    int64_t nvec, const int *tb, const int *to, const int *toT,
                                    const int *ep, const typename Op::T *betaT, float2 *dst,
                                    int64_t ld, float s1, int nx, int ny, int lx, int ntile,
-                                   int nvb, int nek_max) {
+                                   int nvb, int nek_max, const uint32_t *mask) {
   const ScatterVariant v = kScatter[vi];
   constexpr int EL = 16 / (int)sizeof(typename Op::T);
   const int pe = nek_max + EL;
@@ -593,7 +622,7 @@ static void launch_scatter_variant(int vi, dim3 g, hipStream_t st, const float2 
 #define SGW_S(A, B, X, F)                                                                        \
   if (v.nvb == A && v.mj == B && v.pf == F && lx == X)                                           \
     hipLaunchKernelGGL((k_kb_scatter_mma<Op, A, B, X, F>), g, dim3(NTK), lds, st, coef, nvec,   \
-                       tb, to, toT, ep, betaT, dst, ld, s1, nx, ny, ntile, nvb, pe);
+                       tb, to, toT, ep, betaT, dst, ld, s1, nx, ny, ntile, nvb, pe, mask);
   SGW_S(8, 8, 4, 0) SGW_S(16, 8, 4, 0) SGW_S(8, 4, 4, 0) SGW_S(16, 4, 4, 0) SGW_S(8, 2, 4, 0)
   SGW_S(16, 2, 4, 0) SGW_S(16, 2, 4, 1)
   SGW_S(8, 8, 3, 0) SGW_S(16, 8, 3, 0) SGW_S(8, 4, 3, 0) SGW_S(16, 4, 3, 0) SGW_S(8, 2, 3, 0)
@@ -669,7 +698,7 @@ static void gather_t(sgw_ctx *ctx, const void *psi, int64_t nvec, int64_t ld, vo
                                   ctx->d_kb_tile_base.as<int>(), ctx->d_kb_tile_off.as<int>(),
                                   beta, reinterpret_cast<float2 *>(partial), ctx->nx, ctx->ny,
                                   ctx->kb_lx, (float)ctx->dV, ctx->kb_ntile,
-                                  (int)nvb);
+                                  (int)nvb, ctx->d_kb_mask.as<uint32_t>());
       };
       const int vi = ctx->tune(name, nvec, NGATHER, run);   // the gather overwrites: trials are harmless
       const bool timed = (ctx->ktimer & 4) && ctx->ns.empty();
@@ -753,7 +782,8 @@ static void scatter_t(sgw_ctx *ctx, const void *coef, int64_t nvec, void *dst, i
                                    ctx->d_kb_tile_base.as<int>(), ctx->d_kb_tile_off.as<int>(),
                                    ctx->d_kb_tile_offT.as<int>(), ctx->d_kb_entry_proj.as<int>(),
                                    betaT, static_cast<float2 *>(dst), ld, s, ctx->nx, ctx->ny,
-                                   ctx->kb_lx, ctx->kb_ntile, (int)nvb, ctx->kb_nek_max);
+                                   ctx->kb_lx, ctx->kb_ntile, (int)nvb, ctx->kb_nek_max,
+                                   ctx->d_kb_mask.as<uint32_t>());
       };
       // trials add 0 * (B C) to dst, which leaves it unchanged
       const int vi = ctx->tune(name, nvec, NSCATTER, [&](int i) { launch(i, 0.0f); });
