@@ -99,6 +99,9 @@ def parse():
     ap.add_argument("--cfg4-ntau", type=int, default=400)
     ap.add_argument("--cfg4-workers", type=int, default=8)
     ap.add_argument("--cfg4-small-only", action="store_true")
+    ap.add_argument("--ecut-study", action="store_true",
+                    help="kinetic-cutoff tuning on the 64^3 cluster")
+    ap.add_argument("--ecut-list", type=float, nargs="+", default=[16.0, 20.0, 28.0, 40.0, 0.0])
     ap.add_argument("--cfg5", action="store_true",
                     help="control-variate mode on the 160^3 Si705H300-shaped cluster")
     ap.add_argument("--cfg5-first", type=int, default=0)
@@ -378,6 +381,32 @@ def rocfft_comparison(s, nv=256, reps=10):
             "rocfft_gptvec_per_s": ptv / roc / 1e6, "speedup": roc / ours,
             "note": "library: forward FFT, T(k), inverse FFT and V psi in three passes; "
                     "rocFFT: forward and inverse transforms only (no multiplier, no V psi)"}
+
+
+def filter_coefficient_dump(sgw, homo, lumo, eps, emin, emax, ncoef):
+    """Magnitudes |a_n| of the occupied-space filter's Chebyshev coefficients
+    at log-spaced n (the analogue of the paper's coefficient plot, Fig. 3):
+    the gapped filter in use (erfc step, 1 - eps / eps at the band edges)
+    beside a Fermi function with the same edge values (beta = 2 ln((1-eps)/
+    eps) / gap), each with the length at which its discarded tail drops below
+    1e-7."""
+    import numpy as np
+    nmax = 4 * ncoef
+    ag = np.abs(sgw.sgw_gapped_coefficients(homo, lumo, eps, emin, emax, nmax))
+    mu, beta = 0.5 * (homo + lumo), 2.0 * np.log((1 - eps) / eps) / (lumo - homo)
+    fer = 8192
+    while True:
+        af = np.abs(sgw.sgw_fermi_coefficients(mu, beta, emin, emax, fer))
+        tail = np.cumsum(af[::-1])[::-1]
+        ok = np.nonzero(tail < 1e-7)[0]
+        if (ok.size and ok[0] < fer // 2) or fer >= 65536:
+            break
+        fer *= 2
+    nf = int(ok[0]) if ok.size else None
+    pts = sorted({0, 1} | {int(round(x)) for x in np.geomspace(2, nmax - 1, 24)})
+    return {"gapped_ncoef": ncoef, "fermi_beta": beta, "fermi_ncoef": nf,
+            "n": pts, "gapped_abs": [float(ag[i]) for i in pts],
+            "fermi_abs": [float(af[i]) if i < af.size else None for i in pts]}
 
 
 def qp_spread(sgw, sig, x, p, eks):
@@ -721,6 +750,51 @@ def cfg5_mode(args):
     print(json.dumps(out), flush=True)
 
 
+def ecut_mode(args):
+    """Kinetic-cutoff tuning on the 64^3 cluster (Sec. 3 clips T(k) to bound
+    the spectral width): for each cutoff the Lanczos interval, the lengths of
+    the gapped filter and of the one-step propagator, the KS HOMO/LUMO, the
+    time per sample and the HOMO QP energy from the same 16 samples (N_eta =
+    64, N_tau = 100, N_xi = 10000), against the unclipped operator."""
+    import numpy as np
+    import torch
+    from paper_2601_21005_amd import ksinput, sgw, systems
+    rows = []
+    for ecut in args.ecut_list:
+        s = systems.si35h36(ecut=ecut)
+        ctx = sgw.Context(s.grid.n, s.grid.h, s.v_loc, s.projectors, precision=sgw.SGW_C64,
+                          ecut=s.ecut, max_nvec=256)
+        emin, emax = ctx.lanczos_bounds(60, seed=1, pad=0.01)
+        ev, phis, _ = ksinput.lowest_states(ctx, s.n_occ + 1, emin, emax, s.grid.h ** 3)
+        homo, lumo = float(ev[s.n_occ - 1]), float(ev[s.n_occ])
+        phi = phis[s.n_occ - 1].cpu().numpy()
+        del phis
+        ncoef = suggested_ncoef(sgw, homo, lumo, 1e-7, emin, emax, 1e-7)
+        nprop = len(sgw.sgw_propagator_coefficients(emin, emax, 0.05, 1e-14))
+        p = dict(seed=1002, n_eta=64, n_tau=100, dt=0.05, m_sub=1, ncoef=ncoef, emin=emin,
+                 emax=emax, n_xi=10000, f_g=0.003, mode=0, filter=1, e_homo=homo, e_lumo=lumo,
+                 filter_eps=1e-7)
+        ctx.sigma_estimate(phi, n_zeta=8, first_sample=1000, **dict(p, n_tau=2))   # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sig, x = [], []
+        for b in range(2):
+            a, xx, _ = ctx.sigma_estimate(phi, n_zeta=8, first_sample=8 * b, **p)
+            sig.append(a)
+            x.append(xx)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / 16
+        ctx.close()
+        sig, x = np.concatenate(sig), np.concatenate(x)
+        eg, Z, s1 = qp_spread(sgw, sig, x, p, homo)
+        rows.append({"ecut_Ha": ecut, "interval_Ha": [emin, emax], "ncoef": ncoef,
+                     "prop_terms": nprop, "homo_Ha": homo, "lumo_Ha": lumo,
+                     "gpu_s_per_sample": t, "eqp_homo_eV": eg * HA_EV, "sigma1_eV": s1})
+        progress(f"ecut {ecut}: [{emin:.3f}, {emax:.3f}] ncoef {ncoef} eqp {eg * HA_EV:.4f} eV "
+                 f"{t:.3f} s/sample")
+    print(json.dumps({"mode": "ecut", "rows": rows}), flush=True)
+
+
 def counters_driver(args):
     """Workload for rocprofv3 counter runs (one counter set per run): a plain
     256 MiB device copy (the reference that scales FETCH_SIZE / WRITE_SIZE to
@@ -782,6 +856,9 @@ def main():
     if args.cfg5:
         cfg5_mode(args)
         return
+    if args.ecut_study:
+        ecut_mode(args)
+        return
     if args.quick:
         args.n_tau, args.n_eta, args.batch = 20, 8, 2
 
@@ -799,6 +876,7 @@ def main():
     phi = phis[s.n_occ - 1].cpu().numpy()
     eps = 1e-7
     ncoef = suggested_ncoef(sgw, homo, lumo, eps, emin, emax, 1e-7)
+    fcoef = filter_coefficient_dump(sgw, homo, lumo, eps, emin, emax, ncoef)
     if args.quick:
         ncoef = min(ncoef, 400)
     p = dict(seed=1002, n_eta=args.n_eta, n_tau=args.n_tau, dt=0.05, m_sub=1, ncoef=ncoef,
@@ -935,6 +1013,7 @@ def main():
                                    KB_GATHER_ALGO_BYTES, KB_GATHER_MEASURED_BYTES, g_ms,
                                    g_launch, g_pts),
         "fft_vs_rocfft": fft_cmp,
+        "filter_coefficients": fcoef,
         "kb_layout": kbs,
         "roofline_cheb": {"bound": "hbm", "kernel": "k_plane<float,64,64,PLANE_INV_CHEB>",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -68,6 +68,14 @@ def rel_err(a, b):
     return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
 
 
+def row_max_err(a, b):
+    """max |a - b| / max |b| per row (max over rows): the element-wise check
+    beside the normwise one."""
+    import numpy as np
+    a, b = np.atleast_2d(a), np.atleast_2d(b)
+    return float(np.max(np.max(np.abs(a - b), axis=-1) / np.max(np.abs(b), axis=-1)))
+
+
 def norm_err(a, b):
     """||a - b|| / ||b|| per row (max over rows)."""
     import numpy as np

@@ -3,7 +3,7 @@ import numpy as np
 import pytest
 import torch
 
-from conftest import make_ctx, norm_err
+from conftest import make_ctx, norm_err, row_max_err
 from oracle import chebyshev as cheb
 from oracle import qp as oqp
 from paper_2601_21005_amd import sgw
@@ -52,6 +52,7 @@ def test_filter_tiny12(tiny12l, tiny12l_eig, prec, tol):
     xin = to_dev(ctx, x).cpu().numpy().astype(np.complex128)
     ref = cheb.apply_series(H, cheb.fermi_coefficients(mu, beta, lo, hi, n), lo, hi, xin)
     assert norm_err(xd.cpu().numpy(), ref) < tol
+    assert row_max_err(xd.cpu().numpy(), ref) < 10 * tol
     ctx.close()
 
 
@@ -70,6 +71,7 @@ def test_filter_gaussian_wells_long(cfg1, prec, tol):
     ctx.fermi_filter(xd, sgw.sgw_fermi_coefficients(mu, beta, lo, hi, n), lo, hi)
     ref = cheb.apply_series(H, cheb.fermi_coefficients(mu, beta, lo, hi, n), lo, hi, x)
     assert norm_err(xd.cpu().numpy(), ref) < tol
+    assert row_max_err(xd.cpu().numpy(), ref) < 10 * tol
     ctx.close()
 
 
@@ -99,6 +101,7 @@ def test_propagator_tiny12_many_steps(tiny12l, prec, tol):
     for _ in range(10):
         ref = cheb.propagate(H, lo, hi, 0.2, ref)
     assert norm_err(xd.cpu().numpy(), ref) < tol
+    assert row_max_err(xd.cpu().numpy(), ref) < 10 * tol
     ctx.close()
 
 
@@ -115,4 +118,5 @@ def test_propagator_si35h36_one_step_fp32(si35):
     ctx.cheb_propagate(xd, 0.05, 1, lo, hi)
     ref = cheb.propagate(H, lo, hi, 0.05, xin)
     assert norm_err(xd.cpu().numpy(), ref) < 1e-6
+    assert row_max_err(xd.cpu().numpy(), ref) < 10 * 1e-6
     ctx.close()

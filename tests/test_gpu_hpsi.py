@@ -3,7 +3,7 @@ import numpy as np
 import pytest
 import torch
 
-from conftest import make_ctx, norm_err, rel_err
+from conftest import make_ctx, norm_err, rel_err, row_max_err
 from paper_2601_21005_amd import sgw
 
 pytestmark = pytest.mark.gpu
@@ -40,6 +40,7 @@ def test_hpsi_tiny_with_kb(tiny8, prec):
     s, H = tiny8
     got, ref = run_hpsi(s, H, prec)
     assert norm_err(got, ref) < TOL[prec]
+    assert row_max_err(got, ref) < 10 * TOL[prec]
 
 
 @pytest.mark.parametrize("prec", [sgw.SGW_C128, sgw.SGW_C64])
@@ -47,6 +48,7 @@ def test_hpsi_tiny12_padded_ld(tiny12l, prec):
     s, H = tiny12l
     got, ref = run_hpsi(s, H, prec, nvec=3, pad=40)
     assert norm_err(got, ref) < TOL[prec]
+    assert row_max_err(got, ref) < 10 * TOL[prec]
 
 
 @pytest.mark.parametrize("prec", [sgw.SGW_C128, sgw.SGW_C64])
@@ -54,6 +56,7 @@ def test_hpsi_gaussian_wells_32(cfg1, prec):
     s, H = cfg1
     got, ref = run_hpsi(s, H, prec, nvec=7)
     assert norm_err(got, ref) < TOL[prec]
+    assert row_max_err(got, ref) < 10 * TOL[prec]
 
 
 def test_hpsi_gaussian_wells_160():
@@ -67,6 +70,7 @@ def test_hpsi_gaussian_wells_160():
     for prec in (sgw.SGW_C128, sgw.SGW_C64):
         got, ref = run_hpsi(s, H, prec, nvec=2)
         assert norm_err(got, ref) < TOL[prec], prec
+        assert row_max_err(got, ref) < 10 * TOL[prec], prec
 
 
 @pytest.mark.parametrize("prec", [sgw.SGW_C128, sgw.SGW_C64])
@@ -75,6 +79,7 @@ def test_hpsi_si35h36_64(si35, prec):
     s, H = si35
     got, ref = run_hpsi(s, H, prec, nvec=9)
     assert norm_err(got, ref) < TOL[prec]
+    assert row_max_err(got, ref) < 10 * TOL[prec]
     assert rel_err(got, ref) < 10 * TOL[prec]
 
 

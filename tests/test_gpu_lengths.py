@@ -15,7 +15,7 @@ import numpy as np
 import pytest
 import torch
 
-from conftest import build_oracle_h, make_ctx, norm_err, rel_err
+from conftest import build_oracle_h, make_ctx, norm_err, rel_err, row_max_err
 from paper_2601_21005_amd import sgw
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -68,6 +68,7 @@ def test_hpsi_length(n, prec):
     ctx.close()
     ref = H.apply(xd.cpu().numpy().astype(np.complex128))
     assert norm_err(got, ref) < TOL[prec]
+    assert row_max_err(got, ref) < 10 * TOL[prec]
     assert rel_err(got, ref) < 10 * TOL[prec]
 
 

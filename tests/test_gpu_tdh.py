@@ -3,7 +3,7 @@ import numpy as np
 import pytest
 import torch
 
-from conftest import make_ctx, norm_err, rel_err
+from conftest import make_ctx, norm_err, rel_err, row_max_err
 from oracle.tdh import TDH
 from paper_2601_21005_amd import sgw
 
@@ -49,6 +49,7 @@ def test_tdh_tiny8_kb(tiny8, prec, tol):
     r = run(s, H, prec, S=2, neta=4, nsub=6, tau=0.05)
     for k in ("eta", "deta"):
         assert norm_err(r[k][0].reshape(-1, s.grid.N), r[k][1].reshape(-1, s.grid.N)) < tol, k
+        assert row_max_err(r[k][0].reshape(-1, s.grid.N), r[k][1].reshape(-1, s.grid.N)) < 10 * tol, k
     assert rel_err(r["u"][0], r["u"][1]) < 10 * tol
     assert rel_err(r["v"][0], r["v"][1]) < 10 * tol
 
@@ -59,6 +60,7 @@ def test_tdh_gaussian_wells(cfg1, prec, tol):
     r = run(s, H, prec, S=3, neta=8, nsub=8, tau=0.05, seed=1)
     for k in ("eta", "deta"):
         assert norm_err(r[k][0].reshape(-1, s.grid.N), r[k][1].reshape(-1, s.grid.N)) < tol, k
+        assert row_max_err(r[k][0].reshape(-1, s.grid.N), r[k][1].reshape(-1, s.grid.N)) < 10 * tol, k
     assert rel_err(r["u"][0], r["u"][1]) < 20 * tol
 
 
@@ -68,3 +70,4 @@ def test_tdh_si35h36_fp32_per_step(si35):
     r = run(s, H, sgw.SGW_C64, S=1, neta=8, nsub=1, tau=0.05, seed=2)
     for k in ("eta", "deta"):
         assert norm_err(r[k][0].reshape(-1, s.grid.N), r[k][1].reshape(-1, s.grid.N)) < 1e-6, k
+        assert row_max_err(r[k][0].reshape(-1, s.grid.N), r[k][1].reshape(-1, s.grid.N)) < 10 * 1e-6, k
