@@ -189,8 +189,8 @@ struct sgw_ctx {
     return arch + "/" + name + "/" + std::to_string(nx) + "x" + std::to_string(ny) + "x" +
            std::to_string(nz) + "/p" + std::to_string((int)prec) + "/" + std::to_string(nvec);
   }
-  // Time every variant twice (the second run counts) and keep the lowest
-  // index whose time is within 3% of the fastest.
+  // Time every variant four times after a warm-up (the fastest run counts)
+  // and keep the lowest index whose time is within 3% of the fastest.
   template <typename F> int tune(const char *name, int64_t nvec, int nvar, F &&trial) {
     const auto fit = forced.find(name);
     if (fit != forced.end() && fit->second >= 0 && fit->second < nvar) return fit->second;
@@ -212,13 +212,15 @@ struct sgw_ctx {
     std::vector<float> ms(nvar, 1e30f);
     for (int i = 0; i < nvar; ++i) {
       trial(i);                               // warm-up
-      (void)hipEventRecord(e0, stream);
-      trial(i);
-      (void)hipEventRecord(e1, stream);
-      (void)hipEventSynchronize(e1);
-      float t = 0;
-      (void)hipEventElapsedTime(&t, e0, e1);
-      if (hipGetLastError() == hipSuccess) ms[i] = t;
+      for (int rep = 0; rep < 4; ++rep) {
+        (void)hipEventRecord(e0, stream);
+        trial(i);
+        (void)hipEventRecord(e1, stream);
+        (void)hipEventSynchronize(e1);
+        float t = 0;
+        (void)hipEventElapsedTime(&t, e0, e1);
+        if (hipGetLastError() == hipSuccess) ms[i] = std::min(ms[i], t);
+      }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

@@ -303,7 +303,7 @@ template <class Op, int NVB, int MT, int LX>
 __global__ __launch_bounds__(NTK) void k_kb_gather_mma(
     const float2 *psi, int64_t ld, int64_t nvec, const int *tile_base, const int *tile_off,
     const typename Op::T *beta, float2 *partial, int nx, int ny, float dV, int ntile,
-    int nvb, const uint32_t *tile_mask) {
+    int nvb) {
   using T = typename Op::T;
   constexpr int NC = 2 * NVB, NTL = NC / 16;
   constexpr int EL = 16 / (int)sizeof(T);           // operand elements per lane per group
@@ -317,17 +317,6 @@ __global__ __launch_bounds__(NTK) void k_kb_gather_mma(
   const int base = tile_base[t];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, q = lane >> 4, col = lane & 15;
   const int off = tile_off[t], ne = tile_off[t + 1] - off;
-  // support bits of this wave's 128 points (4 words): groups of points where
-  // no projector reaches contribute exact zeros, so their psi is not loaded
-  // and K groups without support skip their products
-  uint32_t mw[4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-    mw[i] = __builtin_amdgcn_readfirstlane(tile_mask[(int64_t)t * (KB_TP / 32) + 4 * w + i]);
-  auto group_bits = [&](int g) {       // the GK support bits of K group g (wave-uniform)
-    const int o = g * Op::GK;
-    return Op::GK == 32 ? mw[o >> 5] : (mw[o >> 5] >> (o & 31)) & 0xffffu;
-  };
   // B operands of this wave's quarter of K, kept in registers for all entries
   auto load_b = [&](int64_t v0, u32x4 (*b)[NTL], u32x4 (*blo)[NSN]) {
 #pragma unroll
@@ -338,8 +327,6 @@ __global__ __launch_bounds__(NTK) void k_kb_gather_mma(
       for (int g = 0; g < NG; ++g) {
         const int p = 128 * w + g * Op::GK + EL * q;  // EL consecutive points along x
         const float4 *s4 = reinterpret_cast<const float4 *>(src + tile_point_c<LX>(base, p, nx, ny));
-        const int pl = p - 128 * w;
-        const bool live = ((mw[pl >> 5] >> (pl & 31)) & ((1u << EL) - 1u)) != 0u;
         float e[EL];
         // the lane pair (col, col ^ 1) reads each group of 4 complex values
         // once: the even lane points 0, 1 and the odd lane points 2, 3; then
@@ -348,7 +335,7 @@ __global__ __launch_bounds__(NTK) void k_kb_gather_mma(
         const int od = col & 1;
 #pragma unroll
         for (int i = 0; i < EL / 4; ++i) {
-          const float4 z = live ? s4[2 * i + od] : make_float4(0.f, 0.f, 0.f, 0.f);
+          const float4 z = s4[2 * i + od];
           const float g0 = __shfl_xor(od ? z.x : z.y, 1, 64);
           const float g1 = __shfl_xor(od ? z.z : z.w, 1, 64);
           e[4 * i] = od ? g0 : z.x;
@@ -371,7 +358,6 @@ __global__ __launch_bounds__(NTK) void k_kb_gather_mma(
       for (int n = 0; n < NTL; ++n) acc[j][n] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int g = 0; g < NG; ++g) {
-      if (group_bits(g) == 0u) continue;            // no support: the products are zero
       u32x4 a[MT];
 #pragma unroll
       for (int j = 0; j < MT; ++j) {
@@ -460,9 +446,12 @@ __global__ __launch_bounds__(NTK) void k_kb_scatter_mma(
 #pragma unroll
   for (int j = 0; j < MJ; ++j)
     rp[j] = tile_point_c<LX>(base, p0 + 16 * (MJ * w + j) + col, nx, ny);
-  // support bits: M tile j (16 points) with none is skipped by the whole wave;
-  // otherwise the lane reads and writes its point only where a projector
-  // reaches (elsewhere the update is an exact zero)
+  // support bits: M tile j (16 points) with none is skipped by the whole wave
+  // (no products, no read or write of psi there: the update is an exact
+  // zero).  A live M tile is read and written whole: with 16 x 8 x 4 tiles it
+  // is one 128-byte row of each vector, and storing only its supported
+  // points would leave partly written cache lines that the next pass over
+  // psi pays for.
   uint32_t rowbits[MJ];
   bool live[MJ];
 #pragma unroll
@@ -471,7 +460,7 @@ __global__ __launch_bounds__(NTK) void k_kb_scatter_mma(
     const uint32_t word = __builtin_amdgcn_readfirstlane(
         tile_mask[(int64_t)t * (KB_TP / 32) + (pj >> 5)]);
     rowbits[j] = (word >> (pj & 31)) & 0xffffu;
-    live[j] = (rowbits[j] >> col) & 1u;
+    live[j] = rowbits[j] != 0u;
   }
   float2 *vrow[NTL][2];
   bool vok[NTL][2];
@@ -598,12 +587,12 @@ template <class Op>
 static void launch_gather_variant(int vi, dim3 g, hipStream_t st, const float2 *psi, int64_t ld,
                                   int64_t nvec, const int *tb, const int *to,
                                   const typename Op::T *beta, float2 *partial, int nx, int ny,
-                                  int lx, float dV, int ntile, int nvb, const uint32_t *mask) {
+                                  int lx, float dV, int ntile, int nvb) {
   const GatherVariant v = kGather[vi];
 #define SGW_G(A, B, X)                                                                           \
   if (v.nvb == A && v.mt == B && lx == X)                                                        \
     hipLaunchKernelGGL((k_kb_gather_mma<Op, A, B, X>), g, dim3(NTK), 0, st, psi, ld, nvec, tb,  \
-                       to, beta, partial, nx, ny, dV, ntile, nvb, mask);
+                       to, beta, partial, nx, ny, dV, ntile, nvb);
   SGW_G(8, 2, 4) SGW_G(8, 4, 4) SGW_G(16, 2, 4) SGW_G(16, 4, 4)
   SGW_G(8, 2, 3) SGW_G(8, 4, 3) SGW_G(16, 2, 3) SGW_G(16, 4, 3)
 #undef SGW_G
@@ -698,7 +687,7 @@ static void gather_t(sgw_ctx *ctx, const void *psi, int64_t nvec, int64_t ld, vo
                                   ctx->d_kb_tile_base.as<int>(), ctx->d_kb_tile_off.as<int>(),
                                   beta, reinterpret_cast<float2 *>(partial), ctx->nx, ctx->ny,
                                   ctx->kb_lx, (float)ctx->dV, ctx->kb_ntile,
-                                  (int)nvb, ctx->d_kb_mask.as<uint32_t>());
+                                  (int)nvb);
       };
       const int vi = ctx->tune(name, nvec, NGATHER, run);   // the gather overwrites: trials are harmless
       const bool timed = (ctx->ktimer & 4) && ctx->ns.empty();
