@@ -65,7 +65,7 @@ KB_GATHER_ALGO_BYTES = 8.0
 # counter bytes per touched-tile point x vector (FETCH_SIZE + WRITE_SIZE,
 # scaled as above), the scatter and the gather at 1024 vectors; None once the
 # kernel changes
-KB_SCATTER_MEASURED_BYTES = 16.5
+KB_SCATTER_MEASURED_BYTES = 14.0
 KB_GATHER_MEASURED_BYTES = 8.6
 
 
