@@ -303,11 +303,12 @@ template <class Op, int NVB, int MT, int LX>
 __global__ __launch_bounds__(NTK) void k_kb_gather_mma(
     const float2 *psi, int64_t ld, int64_t nvec, const int *tile_base, const int *tile_off,
     const typename Op::T *beta, float2 *partial, int nx, int ny, float dV, int ntile,
-    int nvb) {
+    int nvb, const uint32_t *__restrict__ tile_mask) {
   using T = typename Op::T;
   constexpr int NC = 2 * NVB, NTL = NC / 16;
   constexpr int EL = 16 / (int)sizeof(T);           // operand elements per lane per group
   constexpr int NG = 128 / Op::GK;                  // K groups of one wave (128 points)
+  static_assert(Op::GK == 16 || Op::GK == 32, "K group of 16 or 32 points");
   constexpr int NS = Op::SPLIT ? NG : 1, NSN = Op::SPLIT ? NTL : 1;
   __shared__ __align__(16) float red[4 * MT * NTL * 256];   // cross-wave sums
   int t;
@@ -317,8 +318,30 @@ __global__ __launch_bounds__(NTK) void k_kb_gather_mma(
   const int base = tile_base[t];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, q = lane >> 4, col = lane & 15;
   const int off = tile_off[t], ne = tile_off[t + 1] - off;
-  // B operands of this wave's quarter of K, kept in registers for all entries
+  // bit g of glive: some point of this wave's K group g (GK consecutive tile
+  // points) lies in a projector's support.  A group without one holds only
+  // zero beta values: its psi values are not loaded and its products (exact
+  // zeros) are not taken.  The condition is uniform over the wave.
+  uint32_t glive = 0;
+  const int wu = __builtin_amdgcn_readfirstlane(w);   // scalar loads of the four words
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const uint32_t word = tile_mask[(int64_t)t * (KB_TP / 32) + 4 * wu + i];
+    if constexpr (Op::GK == 16)
+      glive |= ((word & 0xffffu) ? 1u : 0u) << (2 * i) | ((word >> 16) ? 1u : 0u) << (2 * i + 1);
+    else
+      glive |= (word ? 1u : 0u) << i;
+  }
+  glive = __builtin_amdgcn_readfirstlane(glive);
+  auto live = [&](int g) { return (glive >> g) & 1u; };
+  // B operands of this wave's quarter of K, kept in registers for all entries:
+  // every load of a live group is issued first, the lane exchanges follow
   auto load_b = [&](int64_t v0, u32x4 (*b)[NTL], u32x4 (*blo)[NSN]) {
+    constexpr int NZ = EL / 4;
+    float4 z[NG][NTL][NZ];
+    // the lane pair (col, col ^ 1) reads each group of 4 complex values once:
+    // the even lane points 0, 1 and the odd lane points 2, 3
+    const int od = col & 1;
 #pragma unroll
     for (int n = 0; n < NTL; ++n) {
       const int64_t v = min(v0 + 8 * n + (col >> 1), nvec - 1);
@@ -327,27 +350,50 @@ __global__ __launch_bounds__(NTK) void k_kb_gather_mma(
       for (int g = 0; g < NG; ++g) {
         const int p = 128 * w + g * Op::GK + EL * q;  // EL consecutive points along x
         const float4 *s4 = reinterpret_cast<const float4 *>(src + tile_point_c<LX>(base, p, nx, ny));
-        float e[EL];
-        // the lane pair (col, col ^ 1) reads each group of 4 complex values
-        // once: the even lane points 0, 1 and the odd lane points 2, 3; then
-        // they swap the parts the other needs (real parts to the even lane,
-        // imaginary parts to the odd lane)
-        const int od = col & 1;
 #pragma unroll
-        for (int i = 0; i < EL / 4; ++i) {
-          const float4 z = s4[2 * i + od];
-          const float g0 = __shfl_xor(od ? z.x : z.y, 1, 64);
-          const float g1 = __shfl_xor(od ? z.z : z.w, 1, 64);
-          e[4 * i] = od ? g0 : z.x;
-          e[4 * i + 1] = od ? g1 : z.z;
-          e[4 * i + 2] = od ? z.y : g0;
-          e[4 * i + 3] = od ? z.w : g1;
+        for (int i = 0; i < NZ; ++i) z[g][n][i] = live(g) ? s4[2 * i + od] : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+    }
+    // then they swap the parts the other needs (real parts to the even lane,
+    // imaginary parts to the odd lane)
+#pragma unroll
+    for (int n = 0; n < NTL; ++n)
+#pragma unroll
+      for (int g = 0; g < NG; ++g) {
+        float e[EL];
+#pragma unroll
+        for (int i = 0; i < NZ; ++i) {
+          const float4 zz = z[g][n][i];
+          const float g0 = __shfl_xor(od ? zz.x : zz.y, 1, 64);
+          const float g1 = __shfl_xor(od ? zz.z : zz.w, 1, 64);
+          e[4 * i] = od ? g0 : zz.x;
+          e[4 * i + 1] = od ? g1 : zz.z;
+          e[4 * i + 2] = od ? zz.y : g0;
+          e[4 * i + 3] = od ? zz.w : g1;
         }
         if constexpr (Op::SPLIT) Op::pack2(e, b[g][n], blo[g][n]);
         else b[g][n] = Op::pack(e);
       }
+  };
+  // A operands (beta rows of MT entry tiles, one K group) alternate between
+  // two register sets: group g + 1 is requested before the products of group
+  // g (after the last group, the next pass's first one), so one group's loads
+  // are in flight behind the products (three in flight, with a ring of four,
+  // cost a wave per SIMD in registers and ran 5 % slower).  Entry rows past
+  // ne read row ne - 1: in bounds, and their products are never stored.
+  constexpr int D = 1, RA = 2;
+  static_assert(NG % RA == 0, "the A operands alternate with the K groups");
+  auto load_a = [&](int mg, int g, u32x4 *a) {
+#pragma unroll
+    for (int j = 0; j < MT; ++j) {
+      const int e = min(mg + 16 * j + col, ne - 1);   // A row = lane % 16
+      a[j] = ld16(beta + (int64_t)(off + e) * KB_TP + 128 * w + g * Op::GK + EL * q);
     }
   };
+  u32x4 a[RA][MT];
+#pragma unroll
+  for (int g = 0; g < D; ++g)
+    if (live(g)) load_a(0, g, a[g]);
   u32x4 b[NG][NTL], blo[NS][NSN];
   load_b(v0, b, blo);
   for (int mg = 0; mg < ne; mg += 16 * MT) {
@@ -358,19 +404,15 @@ __global__ __launch_bounds__(NTK) void k_kb_gather_mma(
       for (int n = 0; n < NTL; ++n) acc[j][n] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int g = 0; g < NG; ++g) {
-      u32x4 a[MT];
-#pragma unroll
-      for (int j = 0; j < MT; ++j) {
-        const int e = min(mg + 16 * j + col, ne - 1);   // A row = lane % 16
-        a[j] = ld16(beta + (int64_t)(off + e) * KB_TP + 128 * w + g * Op::GK + EL * q);
-      }
+      if (live((g + D) % NG)) load_a(g + D < NG ? mg : mg + 16 * MT, (g + D) % NG, a[(g + D) % RA]);
+      if (!live(g)) continue;
 #pragma unroll
       for (int j = 0; j < MT; ++j)
         if (mg + 16 * j < ne)
 #pragma unroll
           for (int n = 0; n < NTL; ++n) {
-            Op::mma(acc[j][n], a[j], b[g][n]);
-            if constexpr (Op::SPLIT) Op::mma(acc[j][n], a[j], blo[g][n]);
+            Op::mma(acc[j][n], a[g % RA][j], b[g][n]);
+            if constexpr (Op::SPLIT) Op::mma(acc[j][n], a[g % RA][j], blo[g][n]);
           }
     }
     // a barrier between the last products and the LDS writes of their
@@ -587,12 +629,12 @@ template <class Op>
 static void launch_gather_variant(int vi, dim3 g, hipStream_t st, const float2 *psi, int64_t ld,
                                   int64_t nvec, const int *tb, const int *to,
                                   const typename Op::T *beta, float2 *partial, int nx, int ny,
-                                  int lx, float dV, int ntile, int nvb) {
+                                  int lx, float dV, int ntile, int nvb, const uint32_t *mask) {
   const GatherVariant v = kGather[vi];
 #define SGW_G(A, B, X)                                                                           \
   if (v.nvb == A && v.mt == B && lx == X)                                                        \
     hipLaunchKernelGGL((k_kb_gather_mma<Op, A, B, X>), g, dim3(NTK), 0, st, psi, ld, nvec, tb,  \
-                       to, beta, partial, nx, ny, dV, ntile, nvb);
+                       to, beta, partial, nx, ny, dV, ntile, nvb, mask);
   SGW_G(8, 2, 4) SGW_G(8, 4, 4) SGW_G(16, 2, 4) SGW_G(16, 4, 4)
   SGW_G(8, 2, 3) SGW_G(8, 4, 3) SGW_G(16, 2, 3) SGW_G(16, 4, 3)
 #undef SGW_G
@@ -687,7 +729,7 @@ static void gather_t(sgw_ctx *ctx, const void *psi, int64_t nvec, int64_t ld, vo
                                   ctx->d_kb_tile_base.as<int>(), ctx->d_kb_tile_off.as<int>(),
                                   beta, reinterpret_cast<float2 *>(partial), ctx->nx, ctx->ny,
                                   ctx->kb_lx, (float)ctx->dV, ctx->kb_ntile,
-                                  (int)nvb);
+                                  (int)nvb, ctx->d_kb_mask.as<uint32_t>());
       };
       const int vi = ctx->tune(name, nvec, NGATHER, run);   // the gather overwrites: trials are harmless
       const bool timed = (ctx->ktimer & 4) && ctx->ns.empty();

@@ -127,23 +127,26 @@ def test_bounds_match_oracle(si35, tiny8):
                                           ("kb_gather_bf16x2", "kb_scatter_bf16x2"))])
 def test_kb_variants_bit_identical(si35, monkeypatch, prec, names):
     """Every autotuned KB kernel variant adds the same products in the same
-    order: H psi is bitwise the same whichever variant runs."""
+    order: H psi is bitwise the same whichever variant runs, on a batch of 20
+    vectors and on one of 100 (six full blocks of 16 and a ragged one)."""
     s, H = si35
     rs = np.random.default_rng(9)
-    x = rs.standard_normal((20, s.grid.N)) + 1j * rs.standard_normal((20, s.grid.N))
-    ref = None
+    x = rs.standard_normal((100, s.grid.N)) + 1j * rs.standard_normal((100, s.grid.N))
+    xd = torch.from_numpy(x).to(torch.complex64).cuda()
+    ref = {}
     for g, sc in [(g, 0) for g in range(4)] + [(0, sc) for sc in range(1, 7)]:
         monkeypatch.setenv("SGW_FORCE_VARIANT", f"{names[0]}={g},{names[1]}={sc}")
-        ctx = make_ctx(s, prec, max_nvec=32)
-        xd = torch.from_numpy(x).to(torch.complex64).cuda()
-        yd = torch.empty_like(xd)
-        ctx.apply_H(xd, yd)
-        out = yd.cpu().numpy()
+        ctx = make_ctx(s, prec, max_nvec=128)
+        for nv in (20, 100):
+            yd = torch.empty_like(xd[:nv])
+            ctx.apply_H(xd[:nv], yd)
+            out = yd.cpu().numpy()
+            if nv not in ref:
+                ref[nv] = out
+            else:
+                assert np.array_equal(out, ref[nv]), (g, sc, nv)
         ctx.close()
-        if ref is None:
-            ref = out
-        else:
-            assert np.array_equal(out, ref), (g, sc)
+    assert np.array_equal(ref[20], ref[100][:20])
 
 
 def test_lanczos_bounds_match_oracle(tiny8, tiny8_eig):
