@@ -456,7 +456,7 @@ __global__ __launch_bounds__(NTK) void k_kb_gather_mma(
 // destination values are loaded first, so their latency overlaps the
 // staging and the products (more registers, fewer waves per SIMD).
 template <class Op, int NVB, int MJ, int LX, bool PF>
-__global__ __launch_bounds__(NTK) void k_kb_scatter_mma(
+__device__ __forceinline__ void scatter_mma(
     const float2 *coef, int64_t nvec, const int *tile_base, const int *tile_off,
     const int *tile_offT, const int *entry_proj, const typename Op::T *betaT, float2 *dst,
     int64_t ld, float s1, int nx, int ny, int ntile, int nvb, int pe,
@@ -617,13 +617,39 @@ __global__ __launch_bounds__(NTK) void k_kb_scatter_mma(
     }
 }
 
+template <class Op, int NVB, int MJ, int LX, bool PF>
+__global__ __launch_bounds__(NTK) void k_kb_scatter_mma(
+    const float2 *coef, int64_t nvec, const int *tile_base, const int *tile_off,
+    const int *tile_offT, const int *entry_proj, const typename Op::T *betaT, float2 *dst,
+    int64_t ld, float s1, int nx, int ny, int ntile, int nvb, int pe,
+    const uint32_t *tile_mask) {
+  scatter_mma<Op, NVB, MJ, LX, PF>(coef, nvec, tile_base, tile_off, tile_offT, entry_proj, betaT, dst, ld, s1, nx, ny, ntile, nvb, pe, tile_mask);
+}
+
+// the same code held to 64 registers per lane, i.e. eight waves per SIMD (the
+// accumulators then sit in ordinary vector registers): instantiated only
+// where that fits without spilling
+template <class Op, int NVB, int MJ, int LX, bool PF>
+__global__ __launch_bounds__(NTK) __attribute__((amdgpu_waves_per_eu(8, 8))) void
+k_kb_scatter_mma_w8(
+    const float2 *coef, int64_t nvec, const int *tile_base, const int *tile_off,
+    const int *tile_offT, const int *entry_proj, const typename Op::T *betaT, float2 *dst,
+    int64_t ld, float s1, int nx, int ny, int ntile, int nvb, int pe,
+    const uint32_t *tile_mask) {
+  scatter_mma<Op, NVB, MJ, LX, PF>(coef, nvec, tile_base, tile_off, tile_offT, entry_proj, betaT, dst, ld, s1, nx, ny, ntile, nvb, pe, tile_mask);
+}
+
 // variants (autotuned per context, operand type and batch width)
+// (w: the instance held to that many waves per SIMD, 0: the compiler's
+// choice; the tuner keeps the first variant within 3 % of the fastest, so a
+// held instance comes before its twin)
 struct GatherVariant { int nvb, mt; };
 static const GatherVariant kGather[] = {{8, 2}, {8, 4}, {16, 2}, {16, 4}};
-struct ScatterVariant { int nvb, mj, pf; };
-static const ScatterVariant kScatter[] = {{8, 8, 0}, {16, 8, 0}, {8, 4, 0}, {16, 4, 0},
-                                          {8, 2, 0}, {16, 2, 0}, {16, 2, 1}};
-constexpr int NGATHER = 4, NSCATTER = 7;
+struct ScatterVariant { int nvb, mj, pf, w; };
+static const ScatterVariant kScatter[] = {{8, 8, 0, 0}, {16, 8, 0, 0}, {8, 4, 0, 0},
+                                          {16, 4, 0, 0}, {8, 2, 0, 8}, {8, 2, 0, 0},
+                                          {16, 2, 0, 8}, {16, 2, 0, 0}, {16, 2, 1, 0}};
+constexpr int NGATHER = 4, NSCATTER = 9;
 
 template <class Op>
 static void launch_gather_variant(int vi, dim3 g, hipStream_t st, const float2 *psi, int64_t ld,
@@ -650,14 +676,20 @@ static void launch_scatter_variant(int vi, dim3 g, hipStream_t st, const float2 
   constexpr int EL = 16 / (int)sizeof(typename Op::T);
   const int pe = nek_max + EL;
   const size_t lds = (Op::SPLIT ? 2 : 1) * 2 * (size_t)v.nvb * pe * sizeof(typename Op::T);
-#define SGW_S(A, B, X, F)                                                                        \
-  if (v.nvb == A && v.mj == B && v.pf == F && lx == X)                                           \
-    hipLaunchKernelGGL((k_kb_scatter_mma<Op, A, B, X, F>), g, dim3(NTK), lds, st, coef, nvec,   \
-                       tb, to, toT, ep, betaT, dst, ld, s1, nx, ny, ntile, nvb, pe, mask);
-  SGW_S(8, 8, 4, 0) SGW_S(16, 8, 4, 0) SGW_S(8, 4, 4, 0) SGW_S(16, 4, 4, 0) SGW_S(8, 2, 4, 0)
-  SGW_S(16, 2, 4, 0) SGW_S(16, 2, 4, 1)
-  SGW_S(8, 8, 3, 0) SGW_S(16, 8, 3, 0) SGW_S(8, 4, 3, 0) SGW_S(16, 4, 3, 0) SGW_S(8, 2, 3, 0)
-  SGW_S(16, 2, 3, 0) SGW_S(16, 2, 3, 1)
+#define SGW_S(A, B, X, F, W, K)                                                                  \
+  if (v.nvb == A && v.mj == B && v.pf == F && v.w == W && lx == X)                               \
+    hipLaunchKernelGGL((K<Op, A, B, X, F>), g, dim3(NTK), lds, st, coef, nvec, tb, to, toT, ep, \
+                       betaT, dst, ld, s1, nx, ny, ntile, nvb, pe, mask);
+  SGW_S(8, 8, 4, 0, 0, k_kb_scatter_mma) SGW_S(16, 8, 4, 0, 0, k_kb_scatter_mma)
+  SGW_S(8, 4, 4, 0, 0, k_kb_scatter_mma) SGW_S(16, 4, 4, 0, 0, k_kb_scatter_mma)
+  SGW_S(8, 2, 4, 0, 0, k_kb_scatter_mma) SGW_S(16, 2, 4, 0, 0, k_kb_scatter_mma)
+  SGW_S(16, 2, 4, 1, 0, k_kb_scatter_mma)
+  SGW_S(8, 2, 4, 0, 8, k_kb_scatter_mma_w8) SGW_S(16, 2, 4, 0, 8, k_kb_scatter_mma_w8)
+  SGW_S(8, 8, 3, 0, 0, k_kb_scatter_mma) SGW_S(16, 8, 3, 0, 0, k_kb_scatter_mma)
+  SGW_S(8, 4, 3, 0, 0, k_kb_scatter_mma) SGW_S(16, 4, 3, 0, 0, k_kb_scatter_mma)
+  SGW_S(8, 2, 3, 0, 0, k_kb_scatter_mma) SGW_S(16, 2, 3, 0, 0, k_kb_scatter_mma)
+  SGW_S(16, 2, 3, 1, 0, k_kb_scatter_mma)
+  SGW_S(8, 2, 3, 0, 8, k_kb_scatter_mma_w8) SGW_S(16, 2, 3, 0, 8, k_kb_scatter_mma_w8)
 #undef SGW_S
 }
 

@@ -134,7 +134,7 @@ def test_kb_variants_bit_identical(si35, monkeypatch, prec, names):
     x = rs.standard_normal((100, s.grid.N)) + 1j * rs.standard_normal((100, s.grid.N))
     xd = torch.from_numpy(x).to(torch.complex64).cuda()
     ref = {}
-    for g, sc in [(g, 0) for g in range(4)] + [(0, sc) for sc in range(1, 7)]:
+    for g, sc in [(g, 0) for g in range(4)] + [(0, sc) for sc in range(1, 9)]:
         monkeypatch.setenv("SGW_FORCE_VARIANT", f"{names[0]}={g},{names[1]}={sc}")
         ctx = make_ctx(s, prec, max_nvec=128)
         for nv in (20, 100):
