@@ -66,7 +66,7 @@ KB_GATHER_ALGO_BYTES = 8.0
 # scaled as above), the scatter and the gather at 1024 vectors; None once the
 # kernel changes
 KB_SCATTER_MEASURED_BYTES = 14.0
-KB_GATHER_MEASURED_BYTES = 8.6
+KB_GATHER_MEASURED_BYTES = 7.34
 
 
 def parse():
@@ -344,6 +344,41 @@ def cv_form(args, ctx, s, phis, ev, phi, p, homo, eg, gam, t_sample, sigma1, Z):
             "fallback": r["fallback"], "sigma1_eV": sigma1_cv, "plain_sigma1_eV": sigma1,
             "feature_and_training_s": t_cv, "cheap_samples": args.cv_cheap,
             "sample_time_s": t_samples}
+
+
+def hbm_ceilings(nbytes=2 << 30, reps=10):
+    """Streaming rates that library kernels reach on plain access patterns
+    (torch's elementwise kernels and the runtime's copy on buffers of nbytes):
+    write only (fill), read-modify-write in place (add) and a copy between two
+    buffers, in GB/s of algorithmic bytes.  They are lower bounds of what the
+    device can stream, set beside the nominal 8 TB/s: a kernel that reads and
+    rewrites psi in place, like the projector scatter, is held to the
+    read-modify-write rate."""
+    import torch
+    n = nbytes // 8
+    a = torch.zeros(n, dtype=torch.complex64, device="cuda")
+    b = torch.empty_like(a)
+    f = a.view(torch.float32)
+
+    def rate(fn, moved):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        e1.synchronize()
+        return moved * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+
+    out = {"write": rate(lambda: a.fill_(0), nbytes),
+           "rmw": rate(lambda: f.add_(1.0), 2 * nbytes),
+           "copy": rate(lambda: b.copy_(a), 2 * nbytes), "unit": "GB/s",
+           "bytes": nbytes, "method": "torch fill_ / add_ / copy_ on complex64 buffers"}
+    del a, b, f
+    torch.cuda.empty_cache()
+    return out
 
 
 def rocfft_comparison(s, nv=256, reps=10):
@@ -934,6 +969,7 @@ def main():
     hpsi_rate = nv * reps * s.grid.N / (time.perf_counter() - t1)
     del xh, yh
     fft_cmp = rocfft_comparison(s)
+    ceilings = hbm_ceilings()
     feat = features_roofline(ctx, phis, s)
     progress("H psi, rocFFT and feature-GEMM lines done")
 
@@ -1006,13 +1042,14 @@ def main():
         "hpsi_algo_roofline_frac": hpsi_rate * HPSI_ALGO_BYTES / (HBM_PEAK_GBS * 1e9),
         "phase_ms": {"filter": phases[0], "tdh": phases[1], "time_order": phases[2],
                      "zeta_contract": phases[3], "other": phases[4], "total": phases[5]},
-        "roofline": kb_line("k_kb_scatter_mma<OpF32,NVB,MJ,LX> (autotuned)",
+        "roofline": kb_line("k_kb_scatter_mma[_w8]<OpF32,NVB,MJ,LX> (autotuned)",
                             KB_SCATTER_ALGO_BYTES, KB_SCATTER_MEASURED_BYTES, s_ms, s_launch,
                             s_pts),
         "roofline_gather": kb_line("k_kb_gather_mma<OpF32,NVB,MT,LX> (autotuned)",
                                    KB_GATHER_ALGO_BYTES, KB_GATHER_MEASURED_BYTES, g_ms,
                                    g_launch, g_pts),
         "fft_vs_rocfft": fft_cmp,
+        "hbm_ceilings": ceilings,
         "filter_coefficients": fcoef,
         "kb_layout": kbs,
         "roofline_cheb": {"bound": "hbm", "kernel": "k_plane<float,64,64,PLANE_INV_CHEB>",
