@@ -136,18 +136,19 @@ std::string num_key(std::initializer_list<double> xs) {
 
 // ---------------------------------------------------------------- Chebyshev
 // Term k of the fused recurrence on (cur = v_k, old = v_{k-1}):
-// old <- v_{k+1}; acc_mode 1 / 2: acc = / += b_{k-1} v_{k-1} + b_k v_k.  With
-// coef_dev the coefficients are read on the device at coef_dev[d_counter[0]]
-// and the entry before.
+// old <- v_{k+1} (out <- v_{k+1} when out is given); acc_mode 1 / 2: acc = /
+// += b_{k-1} v_{k-1} + b_k v_k.  With coef_dev the coefficients are read on
+// the device at coef_dev[d_counter[0]] and the entry before.
 void cheb_term(sgw_ctx *ctx, void *cur, void *old, void *acc, void *tmp, void *kbC,
                int64_t nvec, bool first, int acc_mode, const double *bprev, const double *b,
-               double c, double invR, const double *coef_dev) {
+               double c, double invR, const double *coef_dev, void *out = nullptr) {
   const int64_t N = ctx->N;
   const double s2 = first ? 1.0 : 2.0;
   if (ctx->has_kb) kb_gather_e(ctx, cur, nvec, N, kbC);
   EpiArgs e;
   e.x = cur;
   e.vold = old;
+  e.vout = out;
   e.acc = acc;
   e.vloc = ctx->d_vloc.p;
   e.c = c;
@@ -160,7 +161,7 @@ void cheb_term(sgw_ctx *ctx, void *cur, void *old, void *acc, void *tmp, void *k
   e.coef_dev = coef_dev;
   e.term_dev = coef_dev ? ctx->d_counter.as<int>() : nullptr;
   fft3d_apply(ctx, cur, tmp, nullptr, nvec, N, MUL_KIN, 0.0, PLANE_INV_CHEB, e);
-  if (ctx->has_kb) kb_scatter(ctx, kbC, nvec, old, N, s2 * invR, 0.0, nullptr, 0.0, 0.0);
+  if (ctx->has_kb) kb_scatter(ctx, kbC, nvec, out ? out : old, N, s2 * invR, 0.0, nullptr, 0.0, 0.0);
 }
 
 constexpr int SHORT_SERIES = 64;   // up to this many terms a series is one graph
@@ -251,10 +252,14 @@ void *cheb_series(sgw_ctx *ctx, void *v0, void *w1, void *acc, void *tmp, int64_
 // with zeros to the longest.  The zeta propagation takes the states of G
 // consecutive output steps from one sweep (the Jacobi-Anger coefficients of
 // the times dt, 2 dt, ..., G dt, Eq. 4), instead of G series of one step
-// each.  The pairs b_{k-1} v_{k-1} + b_k v_k go into the accumulators before
-// term k (odd k) overwrites v_{k-1}.  v0 and w1 are overwritten; with graphs
-// on, the sweep is replayed whole (one graph per buffers and coefficients).
-void cheb_sweep(sgw_ctx *ctx, void *v0, void *w1, void *acc, void *tmp, int64_t nvec,
+// each.  Term k >= 1 is written to slot (k - 1) mod kSweepGroup of a ring
+// (term 0 is v0 itself), and the G sums take the terms in groups of
+// kSweepGroup: each group's terms are read once for all G accumulators, as
+// soon as the group is complete and before term k + 1 takes the slot of
+// term k + 1 - kSweepGroup (at most kSweepGroup - 1 terms are pending then).
+// v0 is left as it was.  With graphs on, the sweep is replayed whole (one
+// graph per buffers and coefficients).
+void cheb_sweep(sgw_ctx *ctx, void *v0, void *acc, void *tmp, int64_t nvec,
                 const std::vector<std::vector<double>> &coefs, double emin, double emax) {
   const int G = (int)coefs.size();
   SGW_REQUIRE(G >= 1 && G <= kMaxSweep, SGW_EINVAL, "sweep: bad number of outputs");
@@ -263,40 +268,43 @@ void cheb_sweep(sgw_ctx *ctx, void *v0, void *w1, void *acc, void *tmp, int64_t 
   const double c = 0.5 * (emax + emin), R = 0.5 * (emax - emin), invR = 1.0 / R;
   void *kbC = nullptr;
   if (ctx->has_kb) kbC = ctx->buf("kbC", ctx->csize() * ctx->kb.nproj * nvec).p;
-  auto cur_of = [&](int k) { return (k % 2 == 0) ? v0 : w1; };
-  auto old_of = [&](int k) { return (k % 2 == 0) ? w1 : v0; };
+  const size_t slot = ctx->csize() * (size_t)ctx->N * nvec;
+  char *ring = static_cast<char *>(ctx->buf("sweep_ring", slot * kSweepGroup).p);
+  auto term = [&](int k) -> void * {
+    return k == 0 ? v0 : static_cast<void *>(ring + slot * ((k - 1) % kSweepGroup));
+  };
   auto b_of = [&](int g, int n, int part) {
     return 2 * n + 1 < (int)coefs[g].size() ? coefs[g][2 * n + part] : 0.0;
   };
-  // acc_g (=/+=) b_g,n0 v_n0 (+ b_g,n1 v_n1)
-  auto accs = [&](const void *a, int n0, const void *b, int n1, bool assign) {
-    ChebAccCoefs cf{};
-    for (int g = 0; g < G; ++g) {
-      cf.c[g][0] = b_of(g, n0, 0);
-      cf.c[g][1] = b_of(g, n0, 1);
-      cf.c[g][2] = b ? b_of(g, n1, 0) : 0.0;
-      cf.c[g][3] = b ? b_of(g, n1, 1) : 0.0;
+  // acc_g (= for the first group, else +=) sum_{k0 <= k < k1} b_g,k v_k
+  auto group = [&](int k0, int k1) {
+    ChebAccTerms t{};
+    for (int j = 0; j < k1 - k0; ++j) {
+      t.x[j] = term(k0 + j);
+      for (int g = 0; g < G; ++g) {
+        t.c[g][2 * j] = b_of(g, k0 + j, 0);
+        t.c[g][2 * j + 1] = b_of(g, k0 + j, 1);
+      }
     }
-    launch_cheb_accs(ctx, a, b, acc, nvec, G, cf, assign);
+    launch_cheb_accs(ctx, t, k1 - k0, acc, nvec, G, k0 == 0);
   };
   auto run = [&]() {
+    int f = 0;                          // first term not yet in the sums
     for (int k = 0; k + 1 < nc; ++k) {
-      if (k % 2 == 1) accs(old_of(k), k - 1, cur_of(k), k, k == 1);
-      cheb_term(ctx, cur_of(k), old_of(k), nullptr, tmp, kbC, nvec, k == 0, 0, nullptr, nullptr,
-                c, invR, nullptr);
+      cheb_term(ctx, term(k), k == 0 ? v0 : term(k - 1), nullptr, tmp, kbC, nvec, k == 0, 0,
+                nullptr, nullptr, c, invR, nullptr, term(k + 1));
+      if (k + 2 - f == kSweepGroup) {
+        group(f, k + 2);
+        f = k + 2;
+      }
     }
-    // the loop ran terms 0 .. nc - 2 and took the pairs up to the last odd one
-    const int k = nc - 1;
-    if (k % 2 == 1)
-      accs(old_of(k), k - 1, cur_of(k), k, k == 1);
-    else
-      accs(cur_of(k), k, nullptr, 0, k == 0);
+    if (f < nc || nc == 0) group(f, nc);
   };
   if (!(ctx->graphs && !ctx->ktimer) || nc > 2 * SHORT_SERIES) {
     run();
     return;
   }
-  std::string key = "sweep|" + ptr_key({v0, w1, acc, tmp, kbC}) +
+  std::string key = "sweep|" + ptr_key({v0, acc, tmp, kbC, ring}) +
                     num_key({(double)nvec, c, invR, (double)G});
   for (const auto &cg : coefs) {
     key += "/";
@@ -1182,10 +1190,9 @@ sgw_status sgw_sigma_estimate_states(sgw_ctx *ctx, const sgw_sigma_params *P, in
       if (ovl && !ctx->aux) SGW_HIP(hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
       hipStream_t zs = ovl ? ctx->aux : ctx->stream;
       const char *zns = ovl ? "|z" : "";
-      void *zb, *zacc, *zt;
+      void *zacc, *zt;
       {
         OnStream on(ctx, zs, zns);
-        zb = ctx->buf("z_b", cs * N * 2 * S).p;
         zacc = ctx->buf("z_acc", cs * N * 2 * S * G).p;
         zt = ctx->buf("z_tmp", cs * N * 2 * S).p;
       }
@@ -1204,7 +1211,7 @@ sgw_status sgw_sigma_estimate_states(sgw_ctx *ctx, const sgw_sigma_params *P, in
             launch_copy(ctx, static_cast<char *>(zacc) + cs * N * nz * (G - 1), N, zeta, N, nz);
           const int gn = std::min(G, nt1 - j);
           const std::vector<std::vector<double>> sub(pbs.begin(), pbs.begin() + gn);
-          cheb_sweep(ctx, zeta, zb, zacc, zt, nz, sub, P->emin, P->emax);
+          cheb_sweep(ctx, zeta, zacc, zt, nz, sub, P->emin, P->emax);
         }
         return static_cast<char *>(zacc) + cs * N * 2 * S * g;
       };

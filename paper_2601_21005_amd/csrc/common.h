@@ -269,6 +269,7 @@ enum MulMode : int { MUL_NONE = 0, MUL_KIN = 1, MUL_PROP = 2, MUL_COUL = 3 };
 struct EpiArgs {
   const void *x = nullptr;    // complex: current vector (HPSI, CHEB)
   void *vold = nullptr;       // complex: v_{n-1} in, v_{n+1} out (CHEB)
+  void *vout = nullptr;       // complex: v_{n+1} out instead of vold when set (CHEB)
   void *acc = nullptr;        // complex: accumulated series (CHEB)
   const void *vloc = nullptr; // real [N]
   const void *vh0 = nullptr;  // real per field (POISSON)

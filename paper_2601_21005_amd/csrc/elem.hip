@@ -111,49 +111,50 @@ void launch_axpy2(sgw_ctx *ctx, const void *a, const void *b, int64_t ld, void *
 }
 
 // Several Chebyshev sums over one recurrence: acc_g (= when assign, else +=)
-// c0_g a + c1_g b for g < G, in that order (b nullable: one term).  The
-// accumulators are G-major, acc + (g nvec + v) N.
+// sum_j c_g,j x_j for g < G over a group of nterm terms, added in order of j.
+// The group's terms are read once (all loads first) for all G accumulators,
+// which are G-major, acc + (g nvec + v) N.
 template <typename R>
-__global__ void k_cheb_accs(const cplx<R> *a, const cplx<R> *b, cplx<R> *acc, int64_t N,
-                            int64_t nvec, int G, ChebAccCoefs cf, int assign) {
+__global__ void k_cheb_accs(ChebAccTerms t, int nterm, cplx<R> *acc, int64_t N, int64_t nvec,
+                            int G, int assign) {
   const int64_t r = (int64_t)blockIdx.x * NT + threadIdx.x;
   const int64_t v = blockIdx.y;
   if (r >= N) return;
-  const cplx<R> x = a[v * N + r];
-  cplx<R> y;
-  y.x = y.y = 0;
-  if (b) y = b[v * N + r];
+  cplx<R> x[kSweepGroup];
+#pragma unroll
+  for (int j = 0; j < kSweepGroup; ++j)
+    if (j < nterm) x[j] = static_cast<const cplx<R> *>(t.x[j])[v * N + r];
 #pragma unroll
   for (int g = 0; g < kMaxSweep; ++g) {
     if (g < G) {
       cplx<R> *o = acc + ((int64_t)g * nvec + v) * N + r;
-      const R c0r = (R)cf.c[g][0], c0i = (R)cf.c[g][1], c1r = (R)cf.c[g][2], c1i = (R)cf.c[g][3];
       cplx<R> s;
       s.x = s.y = 0;
       if (!assign) s = *o;
-      s.x += c0r * x.x - c0i * x.y;
-      s.y += c0r * x.y + c0i * x.x;
-      if (b) {
-        s.x += c1r * y.x - c1i * y.y;
-        s.y += c1r * y.y + c1i * y.x;
+#pragma unroll
+      for (int j = 0; j < kSweepGroup; ++j) {
+        if (j < nterm) {
+          const R cr = (R)t.c[g][2 * j], ci = (R)t.c[g][2 * j + 1];
+          s.x += cr * x[j].x - ci * x[j].y;
+          s.y += cr * x[j].y + ci * x[j].x;
+        }
       }
       *o = s;
     }
   }
 }
 
-void launch_cheb_accs(sgw_ctx *ctx, const void *a, const void *b, void *acc, int64_t nvec,
-                      int G, const ChebAccCoefs &cf, bool assign) {
-  SGW_REQUIRE(G >= 1 && G <= kMaxSweep && nvec <= 65535, SGW_EINVAL, "cheb_accs: bad sizes");
+void launch_cheb_accs(sgw_ctx *ctx, const ChebAccTerms &t, int nterm, void *acc, int64_t nvec,
+                      int G, bool assign) {
+  SGW_REQUIRE(G >= 1 && G <= kMaxSweep && nterm >= 0 && nterm <= kSweepGroup && nvec <= 65535,
+              SGW_EINVAL, "cheb_accs: bad sizes");
   if (nvec == 0) return;
   if (ctx->dbl)
-    hipLaunchKernelGGL(k_cheb_accs<double>, grid1(ctx->N, nvec), dim3(NT), 0, ctx->stream,
-                       static_cast<const double2 *>(a), static_cast<const double2 *>(b),
-                       static_cast<double2 *>(acc), ctx->N, nvec, G, cf, assign ? 1 : 0);
+    hipLaunchKernelGGL(k_cheb_accs<double>, grid1(ctx->N, nvec), dim3(NT), 0, ctx->stream, t,
+                       nterm, static_cast<double2 *>(acc), ctx->N, nvec, G, assign ? 1 : 0);
   else
-    hipLaunchKernelGGL(k_cheb_accs<float>, grid1(ctx->N, nvec), dim3(NT), 0, ctx->stream,
-                       static_cast<const float2 *>(a), static_cast<const float2 *>(b),
-                       static_cast<float2 *>(acc), ctx->N, nvec, G, cf, assign ? 1 : 0);
+    hipLaunchKernelGGL(k_cheb_accs<float>, grid1(ctx->N, nvec), dim3(NT), 0, ctx->stream, t,
+                       nterm, static_cast<float2 *>(acc), ctx->N, nvec, G, assign ? 1 : 0);
   SGW_HIP(hipGetLastError());
 }
 

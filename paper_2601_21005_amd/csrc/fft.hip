@@ -59,6 +59,7 @@ __device__ __forceinline__ void epilogue(const PassArgs &a, int64_t v, int64_t r
       const R V = static_cast<const R *>(a.e.vloc)[r];
       const R c = (R)a.e.c, iR = (R)a.e.invR, s2 = (R)a.e.scale2;
       C *vold = static_cast<C *>(a.e.vold);
+      C *vout = a.e.vout ? static_cast<C *>(a.e.vout) : vold;
       C *acc = static_cast<C *>(a.e.acc);
       C p;
       p.x = p.y = 0;
@@ -66,7 +67,7 @@ __device__ __forceinline__ void epilogue(const PassArgs &a, int64_t v, int64_t r
       C nv;
       nv.x = s2 * ((val.x + (V - c) * x.x) * iR) - p.x;
       nv.y = s2 * ((val.y + (V - c) * x.y) * iR) - p.y;
-      vold[o] = nv;
+      vout[o] = nv;
       if (a.e.acc_mode) {
         R b0r = (R)a.e.cprev_re, b0i = (R)a.e.cprev_im, b1r = (R)a.e.coef_re, b1i = (R)a.e.coef_im;
         if (a.e.coef_dev) {
@@ -134,6 +135,7 @@ __global__ __launch_bounds__(NT_FFT) void k_plane(PassArgs a) {
     // (the stores to vold / acc would otherwise order every later load)
     const C *xp = static_cast<const C *>(a.e.x) + v * a.ld_x + plane;
     C *vp = static_cast<C *>(a.e.vold) + v * a.ld_x + plane;
+    C *wp = (a.e.vout ? static_cast<C *>(a.e.vout) : static_cast<C *>(a.e.vold)) + v * a.ld_x + plane;
     C *ap = static_cast<C *>(a.e.acc) + v * a.ld_x + plane;
     const R *Vp = static_cast<const R *>(a.e.vloc) + plane;
     const bool first = a.e.first != 0;
@@ -173,7 +175,7 @@ __global__ __launch_bounds__(NT_FFT) void k_plane(PassArgs a) {
         C nv;
         nv.x = s2 * ((val.x + (Vs[q] - c) * x.x) * iR) - pv.x;
         nv.y = s2 * ((val.y + (Vs[q] - c) * x.y) * iR) - pv.y;
-        vp[e] = nv;
+        wp[e] = nv;
         if (am) {
           C sm = ss[q];
           sm.x += b0r * pv.x - b0i * pv.y;
@@ -465,6 +467,7 @@ void fft3d_apply_t(sgw_ctx *ctx, const void *src, void *tmp, void *dst, int64_t 
     // shift epilogue vector pointers to this chunk
     if (a.e.x) a.e.x = static_cast<const C *>(a.e.x) + v0 * ld;
     if (a.e.vold) a.e.vold = static_cast<C *>(a.e.vold) + v0 * ld;
+    if (a.e.vout) a.e.vout = static_cast<C *>(a.e.vout) + v0 * ld;
     if (a.e.acc) a.e.acc = static_cast<C *>(a.e.acc) + v0 * ld;
     if (a.e.vh0) a.e.vh0 = static_cast<const R *>(a.e.vh0) + v0 * N;
     if (a.e.r0) a.e.r0 = static_cast<R *>(a.e.r0) + v0 * N;

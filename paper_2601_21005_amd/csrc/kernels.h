@@ -22,9 +22,15 @@ void launch_axpy2(sgw_ctx *ctx, const void *a, const void *b, int64_t ld, void *
 // acc_g[v] (= when assign, else +=) c0_g a[v] + c1_g b[v] (b nullable); all
 // vectors N apart, the accumulators G-major (acc + (g nvec + v) N).
 constexpr int kMaxSweep = 8;
-struct ChebAccCoefs { double c[kMaxSweep][4]; };   // (c0 re, c0 im, c1 re, c1 im)
-void launch_cheb_accs(sgw_ctx *ctx, const void *a, const void *b, void *acc, int64_t nvec,
-                      int G, const ChebAccCoefs &cf, bool assign);
+constexpr int kSweepGroup = 8;   // terms per accumulation of a sweep
+// a group of up to kSweepGroup terms x_j and their coefficients for the G
+// sums (c[g][2 j], c[g][2 j + 1]: re, im)
+struct ChebAccTerms {
+  const void *x[kSweepGroup];
+  double c[kMaxSweep][2 * kSweepGroup];
+};
+void launch_cheb_accs(sgw_ctx *ctx, const ChebAccTerms &t, int nterm, void *acc, int64_t nvec,
+                      int G, bool assign);
 // dst[v] = src[v]
 void launch_copy(sgw_ctx *ctx, const void *src, int64_t lds, void *dst, int64_t ldd,
                  int64_t nvec);

@@ -149,6 +149,34 @@ def test_kb_variants_bit_identical(si35, monkeypatch, prec, names):
     assert np.array_equal(ref[20], ref[100][:20])
 
 
+@pytest.mark.parametrize("prec", [sgw.SGW_C64, sgw.SGW_C64_BF16KB, sgw.SGW_C64_BF16X2KB])
+def test_kb_support_masks_change_no_value(si35, monkeypatch, prec):
+    """The KB kernels skip the 16-point rows (gather: K groups) that no
+    projector reaches; the products skipped are exact zeros, so H psi equals
+    the one with every row live (SGW_KB_MASK=0) -- on the 64^3 cluster (16 x
+    8 x 4 tiles) and on a 17-Si cluster at 40^3 (8 x 8 x 8 tiles)."""
+    from paper_2601_21005_amd import systems
+    species, pos = systems.si_cluster(17, seed=3)
+    s40 = systems.cluster_model(species, pos, n=40, h=0.6, ecut=28.0)
+    for s in (si35[0], s40):
+        rs = np.random.default_rng(12)
+        x = rs.standard_normal((36, s.grid.N)) + 1j * rs.standard_normal((36, s.grid.N))
+        xd = torch.from_numpy(x).to(torch.complex64).cuda()
+        out = {}
+        for m in ("1", "0"):
+            monkeypatch.setenv("SGW_KB_MASK", m)
+            ctx = make_ctx(s, prec, max_nvec=64)
+            st = ctx.kb_stats()
+            yd = torch.empty_like(xd)
+            ctx.apply_H(xd, yd)
+            out[m] = yd.cpu().numpy()
+            ctx.close()
+        print(f"{s.grid.n}^3: support points {st['support_points']} of {st['tile_points']} "
+              "tile points", flush=True)
+        assert st["support_points"] < st["tile_points"]
+        assert np.array_equal(out["1"], out["0"])
+
+
 def test_lanczos_bounds_match_oracle(tiny8, tiny8_eig):
     """40 Lanczos steps from the same start vector on the device (C128) and
     in the oracle give the same interval, and it encloses the spectrum."""
