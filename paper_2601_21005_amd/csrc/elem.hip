@@ -523,10 +523,21 @@ __global__ __launch_bounds__(NT) void k_xi_real(const R *u, const int *blocks,
   const R *us = u + (int64_t)s * N;
   const int p = lane & 31;
   R acc = 0;
-  for (int g = lane >> 5; g < nseg; g += 2) {
-    const uint64_t w = sm64(key + (uint64_t)(m * nseg + g));
-    const R val = us[(int64_t)row[g] * 32 + p];
-    acc += ((w >> p) & 1ull) ? -val : val;
+  // the block indices of 64 segments at a time, one per lane, then passed
+  // to the half-waves by lane exchange (no dependent load per segment); the
+  // exchange runs on the whole wave, the segment on its half-wave
+  for (int g0 = 0; g0 < nseg; g0 += 64) {
+    const int rowv = g0 + lane < nseg ? row[g0 + lane] : 0;
+    const int g1 = min(nseg, g0 + 64);
+    for (int gp = g0; gp < g1; gp += 2) {
+      const int g = gp + (lane >> 5);
+      const int rb = __shfl(rowv, min(g, g1 - 1) - g0, 64);
+      if (g < g1) {
+        const uint64_t w = sm64(key + (uint64_t)(m * nseg + g));
+        const R val = us[(int64_t)rb * 32 + p];
+        acc += ((w >> p) & 1ull) ? -val : val;
+      }
+    }
   }
   acc = wave_sum(acc);
   const int64_t off = out_off + (step_dev ? (int64_t)step_dev[0] * step_stride : 0);
@@ -548,14 +559,22 @@ __global__ __launch_bounds__(NT) void k_xi_zeta(const cplx<R> *zeta, const R *ph
   const cplx<R> *zt = zp + N;
   const int p = lane & 31;
   R a0 = 0, a1 = 0, b0 = 0, b1 = 0;
-  for (int g = lane >> 5; g < nseg; g += 2) {
-    const uint64_t w = sm64(key + (uint64_t)(m * nseg + g));
-    const int64_t r = (int64_t)row[g] * 32 + p;
-    R f = phi[r];
-    if ((w >> p) & 1ull) f = -f;
-    const cplx<R> x = zp[r], y = zt[r];
-    a0 += f * x.x; a1 += f * x.y;
-    b0 += f * y.x; b1 += f * y.y;
+  for (int g0 = 0; g0 < nseg; g0 += 64) {   // block indices as in k_xi_real
+    const int rowv = g0 + lane < nseg ? row[g0 + lane] : 0;
+    const int g1 = min(nseg, g0 + 64);
+    for (int gp = g0; gp < g1; gp += 2) {
+      const int g = gp + (lane >> 5);
+      const int rb = __shfl(rowv, min(g, g1 - 1) - g0, 64);
+      if (g < g1) {
+        const uint64_t w = sm64(key + (uint64_t)(m * nseg + g));
+        const int64_t r = (int64_t)rb * 32 + p;
+        R f = phi[r];
+        if ((w >> p) & 1ull) f = -f;
+        const cplx<R> x = zp[r], y = zt[r];
+        a0 += f * x.x; a1 += f * x.y;
+        b0 += f * y.x; b1 += f * y.y;
+      }
+    }
   }
   a0 = wave_sum(a0); a1 = wave_sum(a1); b0 = wave_sum(b0); b1 = wave_sum(b1);
   if (lane == 0) {
