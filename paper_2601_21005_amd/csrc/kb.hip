@@ -108,37 +108,21 @@ __global__ void k_kb_reduce(const cplx<R> *partial, const int *proj_off, const i
   out[(int64_t)p * nvec + v] = cmake<cplx<R>>(sr, si);
 }
 
-// out[p][v] = sum_q K[p][q] in[q][v] in FP64, q ascending.  A thread takes
-// KB_MIXP consecutive rows p for one v, so each in[q][v] is read once for all
-// of them (the inputs stay in the L2; reading them once per row made the
-// kernel bound by that traffic).
-constexpr int KB_MIXP = 4;
 template <typename R>
 __global__ void k_kb_mix(const cplx<R> *K, const cplx<R> *in, cplx<R> *out, int np,
                          int64_t nvec) {
   const int64_t v = (int64_t)blockIdx.x * NTK + threadIdx.x;
-  const int p0 = blockIdx.y * KB_MIXP;
+  const int p = blockIdx.y;
   if (v >= nvec) return;
-  double sr[KB_MIXP], si[KB_MIXP];
-  const cplx<R> *k[KB_MIXP];
-#pragma unroll
-  for (int i = 0; i < KB_MIXP; ++i) {
-    sr[i] = si[i] = 0;
-    k[i] = K + (int64_t)min(p0 + i, np - 1) * np;   // rows past np: computed, not stored
-  }
-#pragma unroll 4
+  double sr = 0, si = 0;
+  const cplx<R> *k = K + (int64_t)p * np;
+#pragma unroll 8
   for (int q = 0; q < np; ++q) {
-    const cplx<R> b = in[(int64_t)q * nvec + v];
-#pragma unroll
-    for (int i = 0; i < KB_MIXP; ++i) {
-      const cplx<R> a = k[i][q];
-      sr[i] += (double)a.x * b.x - (double)a.y * b.y;
-      si[i] += (double)a.x * b.y + (double)a.y * b.x;
-    }
+    const cplx<R> a = k[q], b = in[(int64_t)q * nvec + v];
+    sr += (double)a.x * b.x - (double)a.y * b.y;
+    si += (double)a.x * b.y + (double)a.y * b.x;
   }
-#pragma unroll
-  for (int i = 0; i < KB_MIXP; ++i)
-    if (p0 + i < np) out[(int64_t)(p0 + i) * nvec + v] = cmake<cplx<R>>(sr[i], si[i]);
+  out[(int64_t)p * nvec + v] = cmake<cplx<R>>(sr, si);
 }
 
 template <typename R>
@@ -827,7 +811,7 @@ size_t kb_partial_bytes_per_vec(const sgw_ctx *ctx) {
 
 void kb_mix_dense(sgw_ctx *ctx, const void *K, const void *coef_in, void *coef_out,
                   int64_t nvec) {
-  const dim3 g((nvec + NTK - 1) / NTK, (ctx->kb.nproj + KB_MIXP - 1) / KB_MIXP);
+  const dim3 g((nvec + NTK - 1) / NTK, ctx->kb.nproj);
   if (ctx->dbl)
     hipLaunchKernelGGL(k_kb_mix<double>, g, dim3(NTK), 0, ctx->stream,
                        static_cast<const double2 *>(K), static_cast<const double2 *>(coef_in),
