@@ -116,12 +116,20 @@ __global__ void k_kb_mix(const cplx<R> *K, const cplx<R> *in, cplx<R> *out, int 
   if (v >= nvec) return;
   double sr = 0, si = 0;
   const cplx<R> *k = K + (int64_t)p * np;
-#pragma unroll 8
-  for (int q = 0; q < np; ++q) {
-    const cplx<R> a = k[q], b = in[(int64_t)q * nvec + v];
+  auto add = [&](cplx<R> a, cplx<R> b) {
     sr += (double)a.x * b.x - (double)a.y * b.y;
     si += (double)a.x * b.y + (double)a.y * b.x;
+  };
+  // the inputs of eight q are requested before they are summed (in order of q)
+  int q = 0;
+  for (; q + 8 <= np; q += 8) {
+    cplx<R> b[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) b[j] = in[(int64_t)(q + j) * nvec + v];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) add(k[q + j], b[j]);
   }
+  for (; q < np; ++q) add(k[q], in[(int64_t)q * nvec + v]);
   out[(int64_t)p * nvec + v] = cmake<cplx<R>>(sr, si);
 }
 
