@@ -525,17 +525,27 @@ __global__ __launch_bounds__(NT) void k_xi_real(const R *u, const int *blocks,
   R acc = 0;
   // the block indices of 64 segments at a time, one per lane, then passed
   // to the half-waves by lane exchange (no dependent load per segment); the
-  // exchange runs on the whole wave, the segment on its half-wave
+  // exchange runs on the whole wave, the segment on its half-wave.  Four
+  // segments per half-wave are loaded before they are added (in order of g);
+  // indices past the last segment repeat it (in bounds, not added).
   for (int g0 = 0; g0 < nseg; g0 += 64) {
     const int rowv = g0 + lane < nseg ? row[g0 + lane] : 0;
     const int g1 = min(nseg, g0 + 64);
-    for (int gp = g0; gp < g1; gp += 2) {
-      const int g = gp + (lane >> 5);
-      const int rb = __shfl(rowv, min(g, g1 - 1) - g0, 64);
-      if (g < g1) {
-        const uint64_t w = sm64(key + (uint64_t)(m * nseg + g));
-        const R val = us[(int64_t)rb * 32 + p];
-        acc += ((w >> p) & 1ull) ? -val : val;
+    for (int gp = g0; gp < g1; gp += 8) {
+      R val[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int g = gp + 2 * u + (lane >> 5);
+        const int rb = __shfl(rowv, min(g, g1 - 1) - g0, 64);
+        val[u] = us[(int64_t)rb * 32 + p];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int g = gp + 2 * u + (lane >> 5);
+        if (g < g1) {
+          const uint64_t w = sm64(key + (uint64_t)(m * nseg + g));
+          acc += ((w >> p) & 1ull) ? -val[u] : val[u];
+        }
       }
     }
   }
@@ -559,20 +569,30 @@ __global__ __launch_bounds__(NT) void k_xi_zeta(const cplx<R> *zeta, const R *ph
   const cplx<R> *zt = zp + N;
   const int p = lane & 31;
   R a0 = 0, a1 = 0, b0 = 0, b1 = 0;
-  for (int g0 = 0; g0 < nseg; g0 += 64) {   // block indices as in k_xi_real
+  for (int g0 = 0; g0 < nseg; g0 += 64) {   // block indices and loads as in k_xi_real
     const int rowv = g0 + lane < nseg ? row[g0 + lane] : 0;
     const int g1 = min(nseg, g0 + 64);
-    for (int gp = g0; gp < g1; gp += 2) {
-      const int g = gp + (lane >> 5);
-      const int rb = __shfl(rowv, min(g, g1 - 1) - g0, 64);
-      if (g < g1) {
-        const uint64_t w = sm64(key + (uint64_t)(m * nseg + g));
-        const int64_t r = (int64_t)rb * 32 + p;
-        R f = phi[r];
-        if ((w >> p) & 1ull) f = -f;
-        const cplx<R> x = zp[r], y = zt[r];
-        a0 += f * x.x; a1 += f * x.y;
-        b0 += f * y.x; b1 += f * y.y;
+    for (int gp = g0; gp < g1; gp += 8) {
+      R fv[4];
+      cplx<R> xv[4], yv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int g = gp + 2 * u + (lane >> 5);
+        const int64_t r = (int64_t)__shfl(rowv, min(g, g1 - 1) - g0, 64) * 32 + p;
+        fv[u] = phi[r];
+        xv[u] = zp[r];
+        yv[u] = zt[r];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int g = gp + 2 * u + (lane >> 5);
+        if (g < g1) {
+          const uint64_t w = sm64(key + (uint64_t)(m * nseg + g));
+          R f = fv[u];
+          if ((w >> p) & 1ull) f = -f;
+          a0 += f * xv[u].x; a1 += f * xv[u].y;
+          b0 += f * yv[u].x; b1 += f * yv[u].y;
+        }
       }
     }
   }
