@@ -1280,11 +1280,13 @@ sgw_status sgw_sigma_estimate_states(sgw_ctx *ctx, const sgw_sigma_params *P, in
       if (ovl) {
         SGW_HIP(hipEventRecord(ev[8], zs));
         SGW_HIP(hipStreamWaitEvent(ctx->stream, ev[8], 0));
-        for (int j = 0; j < nt1; ++j)
-          for (int k = 0; k < K; ++k)
-            launch_contract_xi(ctx, cto + cto_state * k, dpa + dstep * ((size_t)j * K + k),
-                               dta + dstep * ((size_t)j * K + k), S, P->n_xi, nt1, j,
-                               d_sig + (size_t)4 * S * nt1 * k);
+        // all steps of a state in one launch (overlaps of step j at (j K + k) dstep)
+        for (int k = 0; k < K; ++k)
+          for (int j0 = 0; j0 < nt1; j0 += 65535)
+            launch_contract_xi(ctx, cto + cto_state * k, dpa + dstep * ((size_t)j0 * K + k),
+                               dta + dstep * ((size_t)j0 * K + k), S, P->n_xi, nt1, j0,
+                               d_sig + (size_t)4 * S * nt1 * k, std::min(65535, nt1 - j0),
+                               (int64_t)(dstep / cs) * K);
       }
       void *dp = nullptr, *dtl = nullptr;
       double *partial = nullptr;

@@ -694,13 +694,18 @@ bool launch_time_order(sgw_ctx *ctx, const void *in, void *out, int64_t nrows, i
 }
 
 // ============================================================ contraction
-// sig[(s nt1 + j) 4 + {0,1,2,3}] = (Sigma^+, Sigma^-) of step j, FP64 sums
+// sig[(s nt1 + j) 4 + {0,1,2,3}] = (Sigma^+, Sigma^-) of step j, FP64 sums.
+// One launch may cover several steps: step j0 + blockIdx.y reads its overlaps
+// at dp, dt + blockIdx.y * dstride.
 template <typename R>
 __global__ __launch_bounds__(NT) void k_contract_xi(const cplx<R> *cto, const cplx<R> *dp,
-                                                    const cplx<R> *dt, int n_xi, int nt1, int j,
-                                                    double *sig) {
+                                                    const cplx<R> *dt, int n_xi, int nt1, int j0,
+                                                    int64_t dstride, double *sig) {
   __shared__ double sh[NT];
   const int s = blockIdx.x;
+  const int j = j0 + blockIdx.y;
+  dp += blockIdx.y * dstride;
+  dt += blockIdx.y * dstride;
   const cplx<R> *c = cto + ((int64_t)s * nt1 + j) * n_xi;
   const cplx<R> *a = dp + (int64_t)s * n_xi;
   const cplx<R> *b = dt + (int64_t)s * n_xi;
@@ -725,15 +730,18 @@ __global__ __launch_bounds__(NT) void k_contract_xi(const cplx<R> *cto, const cp
 }
 
 void launch_contract_xi(sgw_ctx *ctx, const void *cto, const void *dp, const void *dt, int S,
-                        int n_xi, int nt1, int j, double *d_sig) {
+                        int n_xi, int nt1, int j, double *d_sig, int nsteps, int64_t dstride) {
+  SGW_REQUIRE(nsteps >= 1 && j + nsteps <= nt1 && nsteps <= 65535, SGW_EINVAL,
+              "contract_xi: bad step range");
+  const dim3 g(S, nsteps);
   if (ctx->dbl)
-    hipLaunchKernelGGL(k_contract_xi<double>, dim3(S), dim3(NT), 0, ctx->stream,
+    hipLaunchKernelGGL(k_contract_xi<double>, g, dim3(NT), 0, ctx->stream,
                        static_cast<const double2 *>(cto), static_cast<const double2 *>(dp),
-                       static_cast<const double2 *>(dt), n_xi, nt1, j, d_sig);
+                       static_cast<const double2 *>(dt), n_xi, nt1, j, dstride, d_sig);
   else
-    hipLaunchKernelGGL(k_contract_xi<float>, dim3(S), dim3(NT), 0, ctx->stream,
+    hipLaunchKernelGGL(k_contract_xi<float>, g, dim3(NT), 0, ctx->stream,
                        static_cast<const float2 *>(cto), static_cast<const float2 *>(dp),
-                       static_cast<const float2 *>(dt), n_xi, nt1, j, d_sig);
+                       static_cast<const float2 *>(dt), n_xi, nt1, j, dstride, d_sig);
   SGW_HIP(hipGetLastError());
 }
 

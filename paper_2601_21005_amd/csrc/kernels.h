@@ -88,8 +88,10 @@ void launch_xi_zeta(sgw_ctx *ctx, const void *zeta, const void *phi, const int *
 bool launch_time_order(sgw_ctx *ctx, const void *in, void *out, int64_t nrows,
                        int64_t n_inner, int nt1, int nft, const void *d_tw);
 // sig_p[s][j] += sum_m c[s][j][m] dp[s][m];  sig_m[s][j] += sum_m c (-conj dt)
+// steps j .. j + nsteps - 1 in one launch, their overlaps dstride elements apart
 void launch_contract_xi(sgw_ctx *ctx, const void *cto, const void *dp, const void *dt,
-                        int S, int n_xi, int nt1, int j, double *d_sig);
+                        int S, int n_xi, int nt1, int j, double *d_sig, int nsteps = 1,
+                        int64_t dstride = 0);
 // exact mode: sig[s][j] (+: dV sum phi z+ u ; -: -dV sum phi conj(z~) u)
 void launch_contract_exact(sgw_ctx *ctx, const void *uto, const void *zeta, const void *phi,
                            int S, int nt1, int j, double *d_partial, double *d_sig);
