@@ -635,8 +635,9 @@ __global__ __launch_bounds__(NTK) void k_kb_scatter_mma(
 }
 
 // the same code held to 64 registers per lane, i.e. eight waves per SIMD (the
-// accumulators then sit in ordinary vector registers): instantiated only
-// where that fits without spilling
+// accumulators then sit in ordinary vector registers): instantiated for the
+// variants of two M tiles per wave, which fit without spilling in FP32 and
+// BF16 (the split-BF16 instances spill a few registers; the tuner weighs that)
 template <class Op, int NVB, int MJ, int LX, bool PF>
 __global__ __launch_bounds__(NTK) __attribute__((amdgpu_waves_per_eu(8, 8))) void
 k_kb_scatter_mma_w8(
