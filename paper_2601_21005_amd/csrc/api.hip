@@ -138,10 +138,13 @@ std::string num_key(std::initializer_list<double> xs) {
 // Term k of the fused recurrence on (cur = v_k, old = v_{k-1}):
 // old <- v_{k+1} (out <- v_{k+1} when out is given); acc_mode 1 / 2: acc = /
 // += b_{k-1} v_{k-1} + b_k v_k.  With coef_dev the coefficients are read on
-// the device at coef_dev[d_counter[0]] and the entry before.
+// the device at coef_dev[d_counter[0]] and the entry before.  With tmp2 the z
+// pencils write it rather than tmp (out of place: the Chebyshev batches stream
+// faster so; the TDH's larger batches do not, and keep them in place).
 void cheb_term(sgw_ctx *ctx, void *cur, void *old, void *acc, void *tmp, void *kbC,
                int64_t nvec, bool first, int acc_mode, const double *bprev, const double *b,
-               double c, double invR, const double *coef_dev, void *out = nullptr) {
+               double c, double invR, const double *coef_dev, void *out = nullptr,
+               void *tmp2 = nullptr) {
   const int64_t N = ctx->N;
   const double s2 = first ? 1.0 : 2.0;
   if (ctx->has_kb) kb_gather_e(ctx, cur, nvec, N, kbC);
@@ -160,7 +163,7 @@ void cheb_term(sgw_ctx *ctx, void *cur, void *old, void *acc, void *tmp, void *k
   e.scale2 = s2;
   e.coef_dev = coef_dev;
   e.term_dev = coef_dev ? ctx->d_counter.as<int>() : nullptr;
-  fft3d_apply(ctx, cur, tmp, nullptr, nvec, N, MUL_KIN, 0.0, PLANE_INV_CHEB, e);
+  fft3d_apply(ctx, cur, tmp, nullptr, nvec, N, MUL_KIN, 0.0, PLANE_INV_CHEB, e, 0, tmp2);
   if (ctx->has_kb) kb_scatter(ctx, kbC, nvec, out ? out : old, N, s2 * invR, 0.0, nullptr, 0.0, 0.0);
 }
 
@@ -185,13 +188,15 @@ void *cheb_series(sgw_ctx *ctx, void *v0, void *w1, void *acc, void *tmp, int64_
   }
   void *kbC = nullptr;
   if (ctx->has_kb) kbC = ctx->buf("kbC", ctx->csize() * ctx->kb.nproj * nvec).p;
+  void *tmp2 = ctx->buf("cheb_tmp2", ctx->csize() * N * nvec).p;
   auto cur_of = [&](int k) { return (k % 2 == 0) ? v0 : w1; };
   auto old_of = [&](int k) { return (k % 2 == 0) ? w1 : v0; };
   auto mode_of = [&](int k) { return k % 2 == 0 ? 0 : (k == 1 ? 1 : 2); };
   auto eager = [&](int k0, int k1) {       // terms k0 .. k1 - 1, host coefficients
     for (int k = k0; k < k1; ++k)
       cheb_term(ctx, cur_of(k), old_of(k), acc, tmp, kbC, nvec, k == 0, mode_of(k),
-                k > 0 ? &coef[2 * (k - 1)] : nullptr, &coef[2 * k], c, invR, nullptr);
+                k > 0 ? &coef[2 * (k - 1)] : nullptr, &coef[2 * k], c, invR, nullptr, nullptr,
+                tmp2);
   };
   auto last = [&]() {
     const int k = nc - 1;                  // the loop ran terms 0 .. nc - 2
@@ -207,7 +212,7 @@ void *cheb_series(sgw_ctx *ctx, void *v0, void *w1, void *acc, void *tmp, int64_
     eager(0, nc - 1);
     return last();
   }
-  const std::string base = ptr_key({v0, w1, acc, tmp, kbC}) + num_key({(double)nvec, c, invR});
+  const std::string base = ptr_key({v0, w1, acc, tmp, tmp2, kbC}) + num_key({(double)nvec, c, invR});
   if (nc <= SHORT_SERIES) {
     std::string key = "series|" + base;
     for (double x : coef) key += num_key({x});
@@ -232,7 +237,7 @@ void *cheb_series(sgw_ctx *ctx, void *v0, void *w1, void *acc, void *tmp, int64_
     hipGraphExec_t ex = captured(ctx, key, [&] {
       for (int k = 2; k < 4; ++k) {
         cheb_term(ctx, cur_of(k), old_of(k), acc, tmp, kbC, nvec, false, mode_of(k), nullptr,
-                  nullptr, c, invR, dc.as<double>());
+                  nullptr, c, invR, dc.as<double>(), nullptr, tmp2);
         launch_counter(ctx, 0, 1, true);
       }
     });
@@ -270,6 +275,7 @@ void cheb_sweep(sgw_ctx *ctx, void *v0, void *acc, void *tmp, int64_t nvec,
   if (ctx->has_kb) kbC = ctx->buf("kbC", ctx->csize() * ctx->kb.nproj * nvec).p;
   const size_t slot = ctx->csize() * (size_t)ctx->N * nvec;
   char *ring = static_cast<char *>(ctx->buf("sweep_ring", slot * kSweepGroup).p);
+  void *tmp2 = ctx->buf("sweep_tmp2", slot).p;
   auto term = [&](int k) -> void * {
     return k == 0 ? v0 : static_cast<void *>(ring + slot * ((k - 1) % kSweepGroup));
   };
@@ -292,7 +298,7 @@ void cheb_sweep(sgw_ctx *ctx, void *v0, void *acc, void *tmp, int64_t nvec,
     int f = 0;                          // first term not yet in the sums
     for (int k = 0; k + 1 < nc; ++k) {
       cheb_term(ctx, term(k), k == 0 ? v0 : term(k - 1), nullptr, tmp, kbC, nvec, k == 0, 0,
-                nullptr, nullptr, c, invR, nullptr, term(k + 1));
+                nullptr, nullptr, c, invR, nullptr, term(k + 1), tmp2);
       if (k + 2 - f == kSweepGroup) {
         group(f, k + 2);
         f = k + 2;
@@ -304,7 +310,7 @@ void cheb_sweep(sgw_ctx *ctx, void *v0, void *acc, void *tmp, int64_t nvec,
     run();
     return;
   }
-  std::string key = "sweep|" + ptr_key({v0, acc, tmp, kbC, ring}) +
+  std::string key = "sweep|" + ptr_key({v0, acc, tmp, tmp2, kbC, ring}) +
                     num_key({(double)nvec, c, invR, (double)G});
   for (const auto &cg : coefs) {
     key += "/";

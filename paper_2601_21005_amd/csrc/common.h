@@ -293,10 +293,11 @@ struct EpiArgs {
 // result written through the inverse pass mode into dst / epilogue outputs.
 // tmp holds nvec vectors ld_tmp apart (0: N); it may be dst itself when
 // ld_tmp equals ld (every pass after the first works in place per plane,
-// pencil or line).
+// pencil or line).  With tmp2 (the layout of tmp) the z pencils read tmp and
+// write tmp2, and the inverse passes take tmp2; without it they work in tmp.
 void fft3d_apply(sgw_ctx *ctx, const void *src, void *tmp, void *dst, int64_t nvec,
                  int64_t ld, MulMode mul, double tau, PlaneMode inv_mode,
-                 const EpiArgs &epi, int64_t ld_tmp = 0);
+                 const EpiArgs &epi, int64_t ld_tmp = 0, void *tmp2 = nullptr);
 
 // KB (kb.hip)
 // C[p][v] = <beta_p|psi_v>  (kb_gather_e: times E_p)

@@ -299,12 +299,14 @@ __global__ __launch_bounds__(NT_FFT) void k_pencil(PassArgs a) {
   const int64_t stride = a.axis == 2 ? (int64_t)a.nx * a.ny : (int64_t)a.nx;
   const int64_t base = a.axis == 2 ? x0 + (int64_t)w * a.nx : x0 + (int64_t)w * a.nx * a.ny;
   for (int i = tid; i < NLEN; i += NT_FFT) tw[i] = static_cast<const C *>(a.tw0)[i];
+  // in place on dst, or from src (ld_src) into dst when src is given
   C *data = static_cast<C *>(a.dst) + v * a.ld_dst + base;
+  const C *in = a.src ? static_cast<const C *>(a.src) + v * a.ld_src + base : data;
 #pragma unroll
   for (int q = 0; q < (E + NT_FFT - 1) / NT_FFT; ++q) {
     const int e = tid + q * NT_FFT;
     if (E % NT_FFT == 0 || e < E) {
-      C val = data[(e / TX) * stride + (e % TX)];
+      C val = in[(e / TX) * stride + (e % TX)];
       if (a.inverse) val = cconj(val);
       s[(e / TX) * P + (e % TX)] = val;
     }
@@ -439,7 +441,7 @@ bool fft_pencils_cover(int nx, int ny, int nz, bool dbl) {
 template <typename R>
 void fft3d_apply_t(sgw_ctx *ctx, const void *src, void *tmp, void *dst, int64_t nvec,
                    int64_t ld, MulMode mul, double tau, PlaneMode inv_mode,
-                   const EpiArgs &epi, int64_t ldt) {
+                   const EpiArgs &epi, int64_t ldt, void *tmp2) {
   using C = cplx<R>;
   SizeOps ox, oy, oz;
   SGW_REQUIRE(get_ops<R>(ctx->nx, ox) && get_ops<R>(ctx->ny, oy) && get_ops<R>(ctx->nz, oz),
@@ -462,6 +464,7 @@ void fft3d_apply_t(sgw_ctx *ctx, const void *src, void *tmp, void *dst, int64_t 
     const int64_t nv = std::min<int64_t>(65535, nvec - v0);
     const C *srcv = static_cast<const C *>(src) + v0 * ld;
     C *tmpv = static_cast<C *>(tmp) + v0 * ldt;
+    C *tmp2v = tmp2 ? static_cast<C *>(tmp2) + v0 * ldt : tmpv;   // z pencils' output
     C *dstv = dst ? static_cast<C *>(dst) + v0 * ld : nullptr;
     PassArgs a = base;
     // shift epilogue vector pointers to this chunk
@@ -489,7 +492,8 @@ void fft3d_apply_t(sgw_ctx *ctx, const void *src, void *tmp, void *dst, int64_t 
     SGW_HIP(hipGetLastError());
     // z: forward, multiply, inverse
     PassArgs pz = a;
-    pz.dst = tmpv; pz.ld_dst = ldt; pz.axis = 2; pz.tw0 = twz; pz.inverse = 0; pz.mul = mul;
+    pz.dst = tmp2v; pz.ld_dst = ldt; pz.axis = 2; pz.tw0 = twz; pz.inverse = 0; pz.mul = mul;
+    if (tmp2) { pz.src = tmpv; pz.ld_src = ldt; }
     // z pencils: rows of 32 complex when the lengths allow it (SGW_FORCE_VARIANT
     // pencil=0 keeps rows of 16); every column is the same 1D transform either way
     const auto fp = ctx->forced.find("pencil");
@@ -502,11 +506,11 @@ void fft3d_apply_t(sgw_ctx *ctx, const void *src, void *tmp, void *dst, int64_t 
     SGW_HIP(hipGetLastError());
     // inverse xy with the epilogue
     PassArgs b = a;
-    b.src = tmpv; b.ld_src = ldt; b.dst = dstv; b.ld_dst = ld; b.mode = inv_mode; b.inverse = 1;
+    b.src = tmp2v; b.ld_src = ldt; b.dst = dstv; b.ld_dst = ld; b.mode = inv_mode; b.inverse = 1;
     const bool timed = (ctx->ktimer & 1) && inv_mode == PLANE_INV_CHEB && ctx->ns.empty();
     if (!use_plane) {
       PassArgs py = a;
-      py.dst = tmpv; py.ld_dst = ldt; py.axis = 1; py.tw0 = twy; py.inverse = 1; py.mul = MUL_NONE;
+      py.dst = tmp2v; py.ld_dst = ldt; py.axis = 1; py.tw0 = twy; py.inverse = 1; py.mul = MUL_NONE;
       oy.pencil(dim3((ctx->nx / oy.tx) * ctx->nz, nv), st, py);
     }
     if (timed) SGW_HIP(hipEventRecord(ctx->kt[0].event(0), st));
@@ -528,13 +532,13 @@ void fft3d_apply_t(sgw_ctx *ctx, const void *src, void *tmp, void *dst, int64_t 
 
 void fft3d_apply(sgw_ctx *ctx, const void *src, void *tmp, void *dst, int64_t nvec,
                  int64_t ld, MulMode mul, double tau, PlaneMode inv_mode,
-                 const EpiArgs &epi, int64_t ld_tmp) {
+                 const EpiArgs &epi, int64_t ld_tmp, void *tmp2) {
   if (nvec <= 0) return;
   const int64_t ldt = ld_tmp > 0 ? ld_tmp : ctx->N;
   if (ctx->dbl)
-    fft3d_apply_t<double>(ctx, src, tmp, dst, nvec, ld, mul, tau, inv_mode, epi, ldt);
+    fft3d_apply_t<double>(ctx, src, tmp, dst, nvec, ld, mul, tau, inv_mode, epi, ldt, tmp2);
   else
-    fft3d_apply_t<float>(ctx, src, tmp, dst, nvec, ld, mul, tau, inv_mode, epi, ldt);
+    fft3d_apply_t<float>(ctx, src, tmp, dst, nvec, ld, mul, tau, inv_mode, epi, ldt, tmp2);
 }
 
 }  // namespace sgw
