@@ -140,11 +140,14 @@ std::string num_key(std::initializer_list<double> xs) {
 // += b_{k-1} v_{k-1} + b_k v_k.  With coef_dev the coefficients are read on
 // the device at coef_dev[d_counter[0]] and the entry before.  With tmp2 the z
 // pencils write it rather than tmp (out of place: the Chebyshev batches stream
-// faster so; the TDH's larger batches do not, and keep them in place).
+// faster so; the TDH's larger batches do not, and keep them in place).  rev
+// (odd terms) starts the FFT passes from the last vector: each pass then
+// begins on the vectors the pass before it wrote last, which are still in the
+// last-level cache.
 void cheb_term(sgw_ctx *ctx, void *cur, void *old, void *acc, void *tmp, void *kbC,
                int64_t nvec, bool first, int acc_mode, const double *bprev, const double *b,
                double c, double invR, const double *coef_dev, void *out = nullptr,
-               void *tmp2 = nullptr) {
+               void *tmp2 = nullptr, bool rev = false) {
   const int64_t N = ctx->N;
   const double s2 = first ? 1.0 : 2.0;
   if (ctx->has_kb) kb_gather_e(ctx, cur, nvec, N, kbC);
@@ -163,7 +166,7 @@ void cheb_term(sgw_ctx *ctx, void *cur, void *old, void *acc, void *tmp, void *k
   e.scale2 = s2;
   e.coef_dev = coef_dev;
   e.term_dev = coef_dev ? ctx->d_counter.as<int>() : nullptr;
-  fft3d_apply(ctx, cur, tmp, nullptr, nvec, N, MUL_KIN, 0.0, PLANE_INV_CHEB, e, 0, tmp2);
+  fft3d_apply(ctx, cur, tmp, nullptr, nvec, N, MUL_KIN, 0.0, PLANE_INV_CHEB, e, 0, tmp2, rev);
   if (ctx->has_kb) kb_scatter(ctx, kbC, nvec, out ? out : old, N, s2 * invR, 0.0, nullptr, 0.0, 0.0);
 }
 
@@ -196,7 +199,7 @@ void *cheb_series(sgw_ctx *ctx, void *v0, void *w1, void *acc, void *tmp, int64_
     for (int k = k0; k < k1; ++k)
       cheb_term(ctx, cur_of(k), old_of(k), acc, tmp, kbC, nvec, k == 0, mode_of(k),
                 k > 0 ? &coef[2 * (k - 1)] : nullptr, &coef[2 * k], c, invR, nullptr, nullptr,
-                tmp2);
+                tmp2, k % 2 == 1);
   };
   auto last = [&]() {
     const int k = nc - 1;                  // the loop ran terms 0 .. nc - 2
@@ -237,7 +240,7 @@ void *cheb_series(sgw_ctx *ctx, void *v0, void *w1, void *acc, void *tmp, int64_
     hipGraphExec_t ex = captured(ctx, key, [&] {
       for (int k = 2; k < 4; ++k) {
         cheb_term(ctx, cur_of(k), old_of(k), acc, tmp, kbC, nvec, false, mode_of(k), nullptr,
-                  nullptr, c, invR, dc.as<double>(), nullptr, tmp2);
+                  nullptr, c, invR, dc.as<double>(), nullptr, tmp2, k % 2 == 1);
         launch_counter(ctx, 0, 1, true);
       }
     });
@@ -298,7 +301,7 @@ void cheb_sweep(sgw_ctx *ctx, void *v0, void *acc, void *tmp, int64_t nvec,
     int f = 0;                          // first term not yet in the sums
     for (int k = 0; k + 1 < nc; ++k) {
       cheb_term(ctx, term(k), k == 0 ? v0 : term(k - 1), nullptr, tmp, kbC, nvec, k == 0, 0,
-                nullptr, nullptr, c, invR, nullptr, term(k + 1), tmp2);
+                nullptr, nullptr, c, invR, nullptr, term(k + 1), tmp2, k % 2 == 1);
       if (k + 2 - f == kSweepGroup) {
         group(f, k + 2);
         f = k + 2;
@@ -417,8 +420,10 @@ void tdh_substeps(sgw_ctx *ctx, sgw_tdh_state *st, int64_t ldp, int nk, int nsub
     launch_tdh_local(ctx, st->psi, ldp, st->v, st->u, st->nsample, st->neta, nk,
                      (k == 0 && open) ? 0.5 * tau : tau);
     if (ctx->has_kb) kb_exp_apply(ctx, st->psi, ldp, nv, 0.5 * tau);
+    // the first pass from the last vector (where the local step ended), the
+    // last one ending on the first (where the density starts)
     fft3d_apply(ctx, st->psi, tmp, st->psi, nv, ldp, MUL_PROP, tau, PLANE_INV_STORE,
-                EpiArgs());
+                EpiArgs(), 0, nullptr, true);
     if (ctx->has_kb) kb_exp_apply(ctx, st->psi, ldp, nv, 0.5 * tau);
     launch_tdh_density(ctx, st->psi, ldp, rho, st->nsample, st->neta, nk, st->weight);
     tdh_potentials(ctx, rho, S, nk, PLANE_INV_POISSON, st->v, st->u, st->vh0);

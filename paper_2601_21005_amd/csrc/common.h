@@ -295,9 +295,12 @@ struct EpiArgs {
 // ld_tmp equals ld (every pass after the first works in place per plane,
 // pencil or line).  With tmp2 (the layout of tmp) the z pencils read tmp and
 // write tmp2, and the inverse passes take tmp2; without it they work in tmp.
+// Successive passes take the vectors in alternate directions, the first in
+// descending order when rev is set.
 void fft3d_apply(sgw_ctx *ctx, const void *src, void *tmp, void *dst, int64_t nvec,
                  int64_t ld, MulMode mul, double tau, PlaneMode inv_mode,
-                 const EpiArgs &epi, int64_t ld_tmp = 0, void *tmp2 = nullptr);
+                 const EpiArgs &epi, int64_t ld_tmp = 0, void *tmp2 = nullptr,
+                 bool rev = false);
 
 // KB (kb.hip)
 // C[p][v] = <beta_p|psi_v>  (kb_gather_e: times E_p)

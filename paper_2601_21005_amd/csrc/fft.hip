@@ -27,6 +27,7 @@ struct PassArgs {
   int inverse = 0;
   int mul = 0;           // MulMode (pencil z)
   int axis = 2;          // pencil: 1 = y, 2 = z
+  int rev = 0;           // 1: vectors in descending order of blockIdx.y
   double tau = 0, ecut = 0, invN = 0;
   int64_t N = 0;
   EpiArgs e;
@@ -112,7 +113,7 @@ __global__ __launch_bounds__(NT_FFT) void k_plane(PassArgs a) {
   __shared__ C twx[NX], twy[NY];
   const int tid = threadIdx.x;
   const int z = blockIdx.x;
-  const int64_t v = blockIdx.y;
+  const int64_t v = a.rev ? gridDim.y - 1 - blockIdx.y : blockIdx.y;
   for (int i = tid; i < NX; i += NT_FFT) twx[i] = static_cast<const C *>(a.tw0)[i];
   for (int i = tid; i < NY; i += NT_FFT) twy[i] = static_cast<const C *>(a.tw1)[i];
   const int64_t plane = (int64_t)z * E;
@@ -229,7 +230,7 @@ __global__ __launch_bounds__(NT_FFT) void k_xlines(PassArgs a) {
   __shared__ C s[NL * P];
   __shared__ C twx[NX];
   const int tid = threadIdx.x;
-  const int64_t v = blockIdx.y;
+  const int64_t v = a.rev ? gridDim.y - 1 - blockIdx.y : blockIdx.y;
   const int64_t nlines = (int64_t)a.ny * a.nz;
   const int64_t l0 = (int64_t)blockIdx.x * NL;
   for (int i = tid; i < NX; i += NT_FFT) twx[i] = static_cast<const C *>(a.tw0)[i];
@@ -294,7 +295,7 @@ __global__ __launch_bounds__(NT_FFT) void k_pencil(PassArgs a) {
   const int nxb = a.nx / TX;
   const int xb = blockIdx.x % nxb;
   const int w = blockIdx.x / nxb;       // z (axis y) or y (axis z)
-  const int64_t v = blockIdx.y;
+  const int64_t v = a.rev ? gridDim.y - 1 - blockIdx.y : blockIdx.y;
   const int x0 = xb * TX;
   const int64_t stride = a.axis == 2 ? (int64_t)a.nx * a.ny : (int64_t)a.nx;
   const int64_t base = a.axis == 2 ? x0 + (int64_t)w * a.nx : x0 + (int64_t)w * a.nx * a.ny;
@@ -441,7 +442,7 @@ bool fft_pencils_cover(int nx, int ny, int nz, bool dbl) {
 template <typename R>
 void fft3d_apply_t(sgw_ctx *ctx, const void *src, void *tmp, void *dst, int64_t nvec,
                    int64_t ld, MulMode mul, double tau, PlaneMode inv_mode,
-                   const EpiArgs &epi, int64_t ldt, void *tmp2) {
+                   const EpiArgs &epi, int64_t ldt, void *tmp2, bool rev) {
   using C = cplx<R>;
   SizeOps ox, oy, oz;
   SGW_REQUIRE(get_ops<R>(ctx->nx, ox) && get_ops<R>(ctx->ny, oy) && get_ops<R>(ctx->nz, oz),
@@ -478,7 +479,11 @@ void fft3d_apply_t(sgw_ctx *ctx, const void *src, void *tmp, void *dst, int64_t 
     a.ld_x = ld;
     // forward xy
     PassArgs f = a;
+    // successive passes run the vectors in alternate directions, each starting
+    // on those the pass before wrote last
+    int dir = rev ? 1 : 0;
     f.src = srcv; f.dst = tmpv; f.ld_src = ld; f.ld_dst = ldt; f.mode = PLANE_FWD; f.inverse = 0;
+    f.rev = dir;
     if (use_plane) {
       f.tw0 = twx; f.tw1 = twy;
       ox.plane(dim3(ctx->nz, nv), st, f);
@@ -487,6 +492,8 @@ void fft3d_apply_t(sgw_ctx *ctx, const void *src, void *tmp, void *dst, int64_t 
       ox.xlines(dim3((ctx->ny * ctx->nz + ox.nl - 1) / ox.nl, nv), st, f);
       PassArgs py = a;
       py.dst = tmpv; py.ld_dst = ldt; py.axis = 1; py.tw0 = twy; py.inverse = 0; py.mul = MUL_NONE;
+      dir ^= 1;
+      py.rev = dir;
       oy.pencil(dim3((ctx->nx / oy.tx) * ctx->nz, nv), st, py);
     }
     SGW_HIP(hipGetLastError());
@@ -494,6 +501,8 @@ void fft3d_apply_t(sgw_ctx *ctx, const void *src, void *tmp, void *dst, int64_t 
     PassArgs pz = a;
     pz.dst = tmp2v; pz.ld_dst = ldt; pz.axis = 2; pz.tw0 = twz; pz.inverse = 0; pz.mul = mul;
     if (tmp2) { pz.src = tmpv; pz.ld_src = ldt; }
+    dir ^= 1;
+    pz.rev = dir;
     // z pencils: rows of 32 complex when the lengths allow it (SGW_FORCE_VARIANT
     // pencil=0 keeps rows of 16); every column is the same 1D transform either way
     const auto fp = ctx->forced.find("pencil");
@@ -511,8 +520,12 @@ void fft3d_apply_t(sgw_ctx *ctx, const void *src, void *tmp, void *dst, int64_t 
     if (!use_plane) {
       PassArgs py = a;
       py.dst = tmp2v; py.ld_dst = ldt; py.axis = 1; py.tw0 = twy; py.inverse = 1; py.mul = MUL_NONE;
+      dir ^= 1;
+      py.rev = dir;
       oy.pencil(dim3((ctx->nx / oy.tx) * ctx->nz, nv), st, py);
     }
+    dir ^= 1;
+    b.rev = dir;
     if (timed) SGW_HIP(hipEventRecord(ctx->kt[0].event(0), st));
     if (use_plane) {
       b.tw0 = twx; b.tw1 = twy;
@@ -532,13 +545,13 @@ void fft3d_apply_t(sgw_ctx *ctx, const void *src, void *tmp, void *dst, int64_t 
 
 void fft3d_apply(sgw_ctx *ctx, const void *src, void *tmp, void *dst, int64_t nvec,
                  int64_t ld, MulMode mul, double tau, PlaneMode inv_mode,
-                 const EpiArgs &epi, int64_t ld_tmp, void *tmp2) {
+                 const EpiArgs &epi, int64_t ld_tmp, void *tmp2, bool rev) {
   if (nvec <= 0) return;
   const int64_t ldt = ld_tmp > 0 ? ld_tmp : ctx->N;
   if (ctx->dbl)
-    fft3d_apply_t<double>(ctx, src, tmp, dst, nvec, ld, mul, tau, inv_mode, epi, ldt, tmp2);
+    fft3d_apply_t<double>(ctx, src, tmp, dst, nvec, ld, mul, tau, inv_mode, epi, ldt, tmp2, rev);
   else
-    fft3d_apply_t<float>(ctx, src, tmp, dst, nvec, ld, mul, tau, inv_mode, epi, ldt, tmp2);
+    fft3d_apply_t<float>(ctx, src, tmp, dst, nvec, ld, mul, tau, inv_mode, epi, ldt, tmp2, rev);
 }
 
 }  // namespace sgw
