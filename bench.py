@@ -1045,7 +1045,9 @@ def main():
         "roofline": kb_line("k_kb_scatter_mma[_w8]<OpF32,NVB,MJ,LX> (autotuned)",
                             KB_SCATTER_ALGO_BYTES, KB_SCATTER_MEASURED_BYTES, s_ms, s_launch,
                             s_pts),
-        "roofline_gather": kb_line("k_kb_gather_mma<OpF32,NVB,MT,LX> (autotuned)",
+        "roofline_gather": kb_line("k_kb_gather_mma<OpF32,NVB,MT,LX> (autotuned; the "
+                                   "TDH's 1024-vector launches: the filter's run untimed "
+                                   "on the second stream beside the FFT passes)",
                                    KB_GATHER_ALGO_BYTES, KB_GATHER_MEASURED_BYTES, g_ms,
                                    g_launch, g_pts),
         "fft_vs_rocfft": fft_cmp,

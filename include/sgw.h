@@ -185,7 +185,14 @@ sgw_status sgw_gapped_coefficients(double e_homo, double e_lumo, double eps, dou
  * k < nvec, by the three-term recurrence.  The filter is real, so complex
  * vectors may carry two real orbitals each (real and imaginary parts).
  * coef: host [ncoef].  [emin, emax] must enclose spec(H); a recurrence that
- * grows anyway returns SGW_EDIVERGED (v is then undefined). */
+ * grows anyway returns SGW_EDIVERGED (v is then undefined).  With projectors,
+ * each term's projections of v_n are computed on a second stream of the
+ * context beside the term's FFT passes (they only read v_n), and the stream
+ * of the context waits for them before the projector update; the call thus
+ * orders itself on the context's stream as before, and its results are
+ * bitwise those of one stream, which SGW_KB_OVERLAP=0 at sgw_create selects
+ * (the same holds for sgw_cheb_propagate and the filter of
+ * sgw_sigma_estimate). */
 sgw_status sgw_fermi_filter(sgw_ctx *ctx, void *v, int64_t nvec, int64_t ld,
                             const double *coef, int32_t ncoef, double emin,
                             double emax);
@@ -333,10 +340,12 @@ sgw_status sgw_sigma_omega(const double *sigma_t, int32_t n_tau, double dt, doub
  *   SGW_TIMER_KB_GATHER   the projector gather GEMM C = B^T psi (complex FP32
  *                         precisions, the same calls); points as the scatter.
  * From sgw_kernel_timer(ctx, bits) on, every launch of the selected kernels
- * on the context's stream is bracketed by a pair of HIP events (launches that
- * sgw_sigma_estimate issues on the context's second stream, the zeta
- * propagation running beside the TDH steps, are not timed: they share the
- * device with the TDH kernels); bits = 0 stops timing, other bits are
+ * on the context's stream is bracketed by a pair of HIP events (launches on
+ * the context's second stream -- the zeta propagation of sgw_sigma_estimate
+ * beside the TDH steps, the Chebyshev terms' projector gathers beside their
+ * FFT passes -- are not timed: they share the device with other kernels;
+ * with SGW_KB_OVERLAP=0 the gathers run on the context's stream and are
+ * timed); bits = 0 stops timing, other bits are
  * SGW_EINVAL.  sgw_kernel_timer_read(ctx, which, ...) takes one timer,
  * synchronises the stream and returns its summed event time (ms), the number
  * of timed launches and the points they processed, then resets that timer. */

@@ -86,6 +86,21 @@ void check_ptr(const void *p, const char *what) {
   SGW_REQUIRE(((uintptr_t)p & 15) == 0, SGW_EINVAL, std::string(what) + " is not 16-byte aligned");
 }
 
+// Issue work on another stream of the context, with its own scratch buffers.
+struct OnStream {
+  sgw_ctx *c;
+  hipStream_t s0;
+  std::string n0;
+  OnStream(sgw_ctx *ctx, hipStream_t s, const char *ns) : c(ctx), s0(ctx->stream), n0(ctx->ns) {
+    c->stream = s;
+    c->ns = ns;
+  }
+  ~OnStream() {
+    c->stream = s0;
+    c->ns = n0;
+  }
+};
+
 // ---------------------------------------------------------------- graphs
 // Capture the launches of `body` on the context's stream into a graph kept
 // under `key` (nothing runs during the capture); a later call with the same
@@ -147,10 +162,22 @@ std::string num_key(std::initializer_list<double> xs) {
 void cheb_term(sgw_ctx *ctx, void *cur, void *old, void *acc, void *tmp, void *kbC,
                int64_t nvec, bool first, int acc_mode, const double *bprev, const double *b,
                double c, double invR, const double *coef_dev, void *out = nullptr,
-               void *tmp2 = nullptr, bool rev = false) {
+               void *tmp2 = nullptr, bool rev = false, bool ovl = false) {
   const int64_t N = ctx->N;
   const double s2 = first ? 1.0 : 2.0;
-  if (ctx->has_kb) kb_gather_e(ctx, cur, nvec, N, kbC);
+  if (ctx->has_kb && ovl) {
+    // the projections of v_n on the second stream, beside the FFT passes
+    // (both only read v_n); the scatter waits for them
+    SGW_HIP(hipEventRecord(ctx->kb_fork[0], ctx->stream));
+    SGW_HIP(hipStreamWaitEvent(ctx->aux, ctx->kb_fork[0], 0));
+    {
+      OnStream on(ctx, ctx->aux, "|k");
+      kb_gather_e(ctx, cur, nvec, N, kbC);
+    }
+    SGW_HIP(hipEventRecord(ctx->kb_fork[1], ctx->aux));
+  } else if (ctx->has_kb) {
+    kb_gather_e(ctx, cur, nvec, N, kbC);
+  }
   EpiArgs e;
   e.x = cur;
   e.vold = old;
@@ -167,6 +194,7 @@ void cheb_term(sgw_ctx *ctx, void *cur, void *old, void *acc, void *tmp, void *k
   e.coef_dev = coef_dev;
   e.term_dev = coef_dev ? ctx->d_counter.as<int>() : nullptr;
   fft3d_apply(ctx, cur, tmp, nullptr, nvec, N, MUL_KIN, 0.0, PLANE_INV_CHEB, e, 0, tmp2, rev);
+  if (ctx->has_kb && ovl) SGW_HIP(hipStreamWaitEvent(ctx->stream, ctx->kb_fork[1], 0));
   if (ctx->has_kb) kb_scatter(ctx, kbC, nvec, out ? out : old, N, s2 * invR, 0.0, nullptr, 0.0, 0.0);
 }
 
@@ -192,6 +220,8 @@ void *cheb_series(sgw_ctx *ctx, void *v0, void *w1, void *acc, void *tmp, int64_
   void *kbC = nullptr;
   if (ctx->has_kb) kbC = ctx->buf("kbC", ctx->csize() * ctx->kb.nproj * nvec).p;
   void *tmp2 = ctx->buf("cheb_tmp2", ctx->csize() * N * nvec).p;
+  const bool ovl = ctx->has_kb && ctx->kb_overlap && ctx->ns.empty();
+  if (ovl) ctx->make_aux();
   auto cur_of = [&](int k) { return (k % 2 == 0) ? v0 : w1; };
   auto old_of = [&](int k) { return (k % 2 == 0) ? w1 : v0; };
   auto mode_of = [&](int k) { return k % 2 == 0 ? 0 : (k == 1 ? 1 : 2); };
@@ -199,7 +229,7 @@ void *cheb_series(sgw_ctx *ctx, void *v0, void *w1, void *acc, void *tmp, int64_
     for (int k = k0; k < k1; ++k)
       cheb_term(ctx, cur_of(k), old_of(k), acc, tmp, kbC, nvec, k == 0, mode_of(k),
                 k > 0 ? &coef[2 * (k - 1)] : nullptr, &coef[2 * k], c, invR, nullptr, nullptr,
-                tmp2, k % 2 == 1);
+                tmp2, k % 2 == 1, ovl);
   };
   auto last = [&]() {
     const int k = nc - 1;                  // the loop ran terms 0 .. nc - 2
@@ -240,7 +270,7 @@ void *cheb_series(sgw_ctx *ctx, void *v0, void *w1, void *acc, void *tmp, int64_
     hipGraphExec_t ex = captured(ctx, key, [&] {
       for (int k = 2; k < 4; ++k) {
         cheb_term(ctx, cur_of(k), old_of(k), acc, tmp, kbC, nvec, false, mode_of(k), nullptr,
-                  nullptr, c, invR, dc.as<double>(), nullptr, tmp2, k % 2 == 1);
+                  nullptr, c, invR, dc.as<double>(), nullptr, tmp2, k % 2 == 1, ovl);
         launch_counter(ctx, 0, 1, true);
       }
     });
@@ -560,21 +590,6 @@ void apply_h_noalloc(sgw_ctx *ctx, const void *psi, void *hpsi, int64_t nvec, in
   }
 }
 
-// Issue work on another stream of the context, with its own scratch buffers.
-struct OnStream {
-  sgw_ctx *c;
-  hipStream_t s0;
-  std::string n0;
-  OnStream(sgw_ctx *ctx, hipStream_t s, const char *ns) : c(ctx), s0(ctx->stream), n0(ctx->ns) {
-    c->stream = s;
-    c->ns = ns;
-  }
-  ~OnStream() {
-    c->stream = s0;
-    c->ns = n0;
-  }
-};
-
 int next_pow2(int n) {
   int p = 1;
   while (p < n) p *= 2;
@@ -633,6 +648,7 @@ sgw_status sgw_create(const sgw_grid *grid, const double *v_loc, const sgw_proje
     }
     if (const char *fc = std::getenv("SGW_FILTER_CHUNK")) c->filter_chunk = std::atoi(fc);
     if (const char *ov = std::getenv("SGW_ZETA_OVERLAP")) c->overlap = std::atoi(ov) != 0;
+    if (const char *ov = std::getenv("SGW_KB_OVERLAP")) c->kb_overlap = std::atoi(ov) != 0;
     if (const char *zw = std::getenv("SGW_ZETA_SWEEP")) c->zeta_sweep = std::atoi(zw);
     if (const char *fv = std::getenv("SGW_FORCE_VARIANT")) {
       // "name=i,name=i": pin autotuned kernel variants (testing)
@@ -1198,7 +1214,7 @@ sgw_status sgw_sigma_estimate_states(sgw_ctx *ctx, const sgw_sigma_params *P, in
       // stream beside the TDH steps (the two meet only in the contraction),
       // and its overlaps d_m(t_j) are kept for every output step.
       const bool ovl = xi && ctx->overlap;
-      if (ovl && !ctx->aux) SGW_HIP(hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
+      if (ovl) ctx->make_aux();
       hipStream_t zs = ovl ? ctx->aux : ctx->stream;
       const char *zns = ovl ? "|z" : "";
       void *zacc, *zt;

@@ -163,6 +163,14 @@ struct sgw_ctx {
   // streams never share scratch memory.
   hipStream_t aux = nullptr;
   bool overlap = true;
+  // the Chebyshev terms' projector gathers run on `aux` beside the FFT passes
+  bool kb_overlap = true;
+  hipEvent_t kb_fork[2] = {nullptr, nullptr};
+  void make_aux() {
+    if (!aux) SGW_HIP(hipStreamCreateWithFlags(&aux, hipStreamNonBlocking));
+    for (auto &e : kb_fork)
+      if (!e) SGW_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
   int zeta_sweep = 8;   // zeta output steps per Chebyshev sweep (1 .. 8)
   std::string ns;
   ~sgw_ctx() {
@@ -171,6 +179,8 @@ struct sgw_ctx {
       (void)hipStreamSynchronize(aux);
       (void)hipStreamDestroy(aux);
     }
+    for (auto e : kb_fork)
+      if (e) (void)hipEventDestroy(e);
     for (auto &t : kt)
       for (auto e : t.events) (void)hipEventDestroy(e);
     for (auto &g : gexec) (void)hipGraphExecDestroy(g.second);

@@ -120,3 +120,41 @@ def test_propagator_si35h36_one_step_fp32(si35):
     assert norm_err(xd.cpu().numpy(), ref) < 1e-6
     assert row_max_err(xd.cpu().numpy(), ref) < 10 * 1e-6
     ctx.close()
+
+
+def test_filter_gather_overlap_changes_no_value(si35, monkeypatch):
+    """The Chebyshev terms' projector gathers run on the context's second
+    stream beside the FFT passes (SGW_KB_OVERLAP=1, the default): the filter
+    output is bitwise the one with everything on one stream, eagerly and from
+    replayed graphs (a 150-term series replays a captured pair of terms, a
+    40-term one the whole series), with eager work between the replays."""
+    s, _ = si35
+    st = torch.cuda.Stream()
+    rs = np.random.default_rng(21)
+    x = rs.standard_normal((40, s.grid.N)) + 1j * rs.standard_normal((40, s.grid.N))
+    out = {}
+    for ov in ("0", "1"):
+        monkeypatch.setenv("SGW_KB_OVERLAP", ov)
+        ctx = sgw.Context(s.grid.n, s.grid.h, s.v_loc, s.projectors, precision=sgw.SGW_C64,
+                          ecut=s.ecut, max_nvec=64, stream=st.cuda_stream)
+        lo, hi = ctx.bounds()
+        mu = lo + 0.3 * (hi - lo)
+        for n in (150, 40):
+            coef = sgw.sgw_fermi_coefficients(mu, 20.0 / (hi - lo), lo, hi, n)
+            for graphs in ((False,) if ov == "0" else (False, True, True, True)):
+                ctx.use_graphs(graphs)
+                with torch.cuda.stream(st):
+                    xd = to_dev(ctx, x)
+                    y = to_dev(ctx, x[:3])
+                    hy = torch.empty_like(y)
+                st.synchronize()
+                ctx.fermi_filter(xd, coef, lo, hi)
+                ctx.apply_H(y, hy)                      # eager work between replays
+                st.synchronize()
+                out.setdefault((n, ov), []).append(xd.cpu().numpy())
+        ctx.close()
+    for n in (150, 40):
+        ref = out[(n, "0")][0]
+        assert np.all(np.isfinite(ref)) and np.abs(ref).max() > 0
+        for y in out[(n, "1")]:
+            assert np.array_equal(y, ref)

@@ -216,12 +216,16 @@ def test_lanczos_bounds_si35h36_fp32(si35):
     assert hi - lo < 0.9 * (hw - lw)
 
 
-def test_kernel_timers(tiny8):
+def test_kernel_timers(tiny8, monkeypatch):
     """The launch timers of the Chebyshev plane pass and the KB scatter and
     gather count one launch of each per filter term and the points they cover
     (the 8^3 grid is one 512-point tile, which the projectors touch); the
-    projector layout sizes match that tile."""
+    projector layout sizes match that tile.  The gathers are timed on the
+    context's own stream: with SGW_KB_OVERLAP=0 the filter issues them there
+    (by default they run on the second stream, untimed, beside the FFT
+    passes)."""
     s, _ = tiny8
+    monkeypatch.setenv("SGW_KB_OVERLAP", "0")
     ctx = make_ctx(s, sgw.SGW_C64, max_nvec=32)
     N, nvec = s.grid.N, 5
     g = torch.Generator(device="cuda").manual_seed(3)
