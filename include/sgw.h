@@ -185,9 +185,10 @@ sgw_status sgw_gapped_coefficients(double e_homo, double e_lumo, double eps, dou
  * k < nvec, by the three-term recurrence.  The filter is real, so complex
  * vectors may carry two real orbitals each (real and imaginary parts).
  * coef: host [ncoef].  [emin, emax] must enclose spec(H); a recurrence that
- * grows anyway returns SGW_EDIVERGED (v is then undefined).  With projectors,
- * each term's projections of v_n are computed on a second stream of the
- * context beside the term's FFT passes (they only read v_n), and the stream
+ * grows anyway returns SGW_EDIVERGED (v is then undefined).  With projectors
+ * and batches of 16 vectors or more, each term's projections of v_n are
+ * computed on a second stream of the context beside the term's FFT passes
+ * (they only read v_n), and the stream
  * of the context waits for them before the projector update; the call thus
  * orders itself on the context's stream as before, and its results are
  * bitwise those of one stream, which SGW_KB_OVERLAP=0 at sgw_create selects

@@ -149,6 +149,35 @@ std::string num_key(std::initializer_list<double> xs) {
   return k;
 }
 
+// ------------------------------------------------------ projections beside
+// C = E B^T x (kb_gather_e) on the context's second stream, ordered after the
+// work issued so far on the context's stream; join_gather makes the context's
+// stream wait for it.  The gather is latency-bound and the FFT passes that
+// run meanwhile on the context's stream bandwidth-bound, so the two share the
+// device well; kbC must not be read on the context's stream in between.
+void fork_gather(sgw_ctx *ctx, const void *x, int64_t nvec, int64_t ld, void *kbC) {
+  SGW_HIP(hipEventRecord(ctx->kb_fork[0], ctx->stream));
+  SGW_HIP(hipStreamWaitEvent(ctx->aux, ctx->kb_fork[0], 0));
+  {
+    OnStream on(ctx, ctx->aux, "|k");
+    kb_gather_e(ctx, x, nvec, ld, kbC);
+  }
+  SGW_HIP(hipEventRecord(ctx->kb_fork[1], ctx->aux));
+}
+
+void join_gather(sgw_ctx *ctx) {
+  SGW_HIP(hipStreamWaitEvent(ctx->stream, ctx->kb_fork[1], 0));
+}
+
+// whether the projector gathers of a batch of nvec vectors go beside the FFT
+// passes (on the context's stream, with projectors, for batches that fill
+// more than a sliver of the device); creates the second stream on first use
+bool gather_beside(sgw_ctx *ctx, int64_t nvec) {
+  const bool ovl = ctx->has_kb && ctx->kb_overlap && ctx->ns.empty() && nvec >= 16;
+  if (ovl) ctx->make_aux();
+  return ovl;
+}
+
 // ---------------------------------------------------------------- Chebyshev
 // Term k of the fused recurrence on (cur = v_k, old = v_{k-1}):
 // old <- v_{k+1} (out <- v_{k+1} when out is given); acc_mode 1 / 2: acc = /
@@ -165,19 +194,10 @@ void cheb_term(sgw_ctx *ctx, void *cur, void *old, void *acc, void *tmp, void *k
                void *tmp2 = nullptr, bool rev = false, bool ovl = false) {
   const int64_t N = ctx->N;
   const double s2 = first ? 1.0 : 2.0;
-  if (ctx->has_kb && ovl) {
-    // the projections of v_n on the second stream, beside the FFT passes
-    // (both only read v_n); the scatter waits for them
-    SGW_HIP(hipEventRecord(ctx->kb_fork[0], ctx->stream));
-    SGW_HIP(hipStreamWaitEvent(ctx->aux, ctx->kb_fork[0], 0));
-    {
-      OnStream on(ctx, ctx->aux, "|k");
-      kb_gather_e(ctx, cur, nvec, N, kbC);
-    }
-    SGW_HIP(hipEventRecord(ctx->kb_fork[1], ctx->aux));
-  } else if (ctx->has_kb) {
-    kb_gather_e(ctx, cur, nvec, N, kbC);
-  }
+  // with ovl the projections of v_n go on the second stream, beside the FFT
+  // passes (both only read v_n), and the scatter waits for them
+  if (ctx->has_kb && ovl) fork_gather(ctx, cur, nvec, N, kbC);
+  else if (ctx->has_kb) kb_gather_e(ctx, cur, nvec, N, kbC);
   EpiArgs e;
   e.x = cur;
   e.vold = old;
@@ -194,7 +214,7 @@ void cheb_term(sgw_ctx *ctx, void *cur, void *old, void *acc, void *tmp, void *k
   e.coef_dev = coef_dev;
   e.term_dev = coef_dev ? ctx->d_counter.as<int>() : nullptr;
   fft3d_apply(ctx, cur, tmp, nullptr, nvec, N, MUL_KIN, 0.0, PLANE_INV_CHEB, e, 0, tmp2, rev);
-  if (ctx->has_kb && ovl) SGW_HIP(hipStreamWaitEvent(ctx->stream, ctx->kb_fork[1], 0));
+  if (ctx->has_kb && ovl) join_gather(ctx);
   if (ctx->has_kb) kb_scatter(ctx, kbC, nvec, out ? out : old, N, s2 * invR, 0.0, nullptr, 0.0, 0.0);
 }
 
@@ -220,8 +240,7 @@ void *cheb_series(sgw_ctx *ctx, void *v0, void *w1, void *acc, void *tmp, int64_
   void *kbC = nullptr;
   if (ctx->has_kb) kbC = ctx->buf("kbC", ctx->csize() * ctx->kb.nproj * nvec).p;
   void *tmp2 = ctx->buf("cheb_tmp2", ctx->csize() * N * nvec).p;
-  const bool ovl = ctx->has_kb && ctx->kb_overlap && ctx->ns.empty();
-  if (ovl) ctx->make_aux();
+  const bool ovl = gather_beside(ctx, nvec);
   auto cur_of = [&](int k) { return (k % 2 == 0) ? v0 : w1; };
   auto old_of = [&](int k) { return (k % 2 == 0) ? w1 : v0; };
   auto mode_of = [&](int k) { return k % 2 == 0 ? 0 : (k == 1 ? 1 : 2); };
