@@ -102,7 +102,21 @@ typedef struct {
  * (sgw_apply_H, sgw_fermi_filter, sgw_cheb_propagate process larger batches
  * in chunks of max_nvec); the context's scratch is sized from it.  All host
  * inputs are copied.  On failure *out is NULL and the message is available
- * from sgw_last_error(NULL). */
+ * from sgw_last_error(NULL).
+ * Switches read from the environment here (tuning and testing):
+ *   SGW_ZETA_OVERLAP=0  the zeta propagation of sgw_sigma_estimate runs after
+ *                       the TDH steps on the context's stream (bitwise the
+ *                       same results);
+ *   SGW_KB_OVERLAP=0    the Chebyshev terms' projector gathers stay on the
+ *                       context's stream (bitwise the same results);
+ *   SGW_ZETA_SWEEP=G    zeta output steps per Chebyshev sweep (1 .. 8);
+ *   SGW_KB_MASK=0       the projector kernels process every row of a touched
+ *                       tile (bitwise the same results);
+ *   SGW_FILTER_CHUNK=n  sgw_sigma_estimate filters n vectors at a time;
+ *   SGW_FORCE_VARIANT="name=i,..."  pins autotuned kernel variants (every
+ *                       variant of a kernel gives the same bits);
+ *   SGW_TUNE_CACHE=path keeps the autotuner's choices in a JSON file, read
+ *                       at the first tuning and rewritten after each new one. */
 sgw_status sgw_create(const sgw_grid *grid, const double *v_loc,
                       const sgw_projectors *projectors, sgw_precision prec,
                       void *hip_stream, int64_t max_nvec, sgw_ctx **out);
