@@ -873,8 +873,8 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported "
-              "(samples are independent; see the sharding note in DESIGN.md)",
-              file=sys.stderr)
+              "(the samples are independent, so several GPUs would each run their own "
+              "share of them and only the final sums would be combined)", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
