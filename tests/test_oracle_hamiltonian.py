@@ -70,6 +70,42 @@ def test_projector_shape_and_normalisation(tiny12):
     assert np.max(rad[nz]) <= 3.0 * 0.75 + 1e-12
 
 
+
+def test_projector_widths_from_second_moments():
+    """The projector shapes fix the second moments of beta^2: for an s
+    projector beta^2 is a Gaussian of variance rc^2/2 per axis, so
+    <|d|^2> = 3 rc^2 / 2; for p_x it is x^2 times that Gaussian, so
+    <x^2> = 3 rc^2 / 2 (fourth over second moment) and <y^2> = <z^2> =
+    rc^2 / 2.  On a fine grid with the cut at 5 rc the sums reach these
+    values to 1e-7 (the trapezoid rule is spectrally accurate here; what is
+    left is the tail beyond the cut)."""
+    g = Grid(32, h=0.25)
+    rc = 0.8
+    pos = np.array([[4.0, 4.0, 4.0]])
+    P = Projectors(g, pos, [0, 0], [0, 1], [0, 0], [rc, rc], [1.0, 1.0], rcut_over_rc=5.0)
+    d = g.min_image(g.coords() - pos[0])
+    B = P.B.toarray()
+    w_s, w_p = g.dV * B[:, 0] ** 2, g.dV * B[:, 1] ** 2
+    assert np.isclose(w_s.sum(), 1.0) and np.isclose(w_p.sum(), 1.0)
+    assert abs(np.sum(w_s * np.sum(d * d, axis=1)) - 1.5 * rc * rc) < 1e-7
+    assert abs(np.sum(w_p * d[:, 0] ** 2) - 1.5 * rc * rc) < 1e-7
+    for a in (1, 2):
+        assert abs(np.sum(w_p * d[:, a] ** 2) - 0.5 * rc * rc) < 1e-7
+
+
+def test_projector_support_includes_the_cut_sphere():
+    """The support is |d| <= rcut, boundary included: with the atom on a grid
+    point and rcut = 2 h the s projector covers the lattice points of the
+    ball of radius 2 in grid units, 1 + 6 + 12 + 8 + 6 = 33 (distances 0, 1,
+    sqrt 2, sqrt 3, 2), of which the last 6 lie on the sphere itself."""
+    g = Grid(12, h=0.5)
+    P = Projectors(g, np.array([[1.5, 2.0, 2.5]]), [0], [0], [0], [0.5], [1.0],
+                   rcut_over_rc=2.0)
+    assert P.B.nnz == 33
+    d = g.min_image(g.coords() - np.array([1.5, 2.0, 2.5]))
+    on_sphere = np.isclose(np.sum(d * d, axis=1), 1.0)
+    assert on_sphere.sum() == 6 and np.all(P.B.toarray()[on_sphere, 0] > 0)
+
 def test_nonlocal_matches_dense_sum(tiny8):
     s, H = tiny8
     g = H.grid

@@ -18,6 +18,31 @@ def test_single_pole_roots():
         assert np.isclose(Z, 1 / (1 + a * a / (eks - p) ** 2))
 
 
+
+def test_linear_sigma_solved_exactly():
+    """For Sigma(w) = s0 + s1 (w - eps_KS) the QP equation (Eq. 6) is linear:
+    eps = eps_KS + (X + s0 - v_xc) / (1 - s1).  One Newton step from eps_KS
+    solves it, so the linearised energy equals it, as does the root, and
+    Z = 1 / (1 - s1)."""
+    for eks, x, vxc, s0, s1 in ((-0.4, -0.1, 0.05, 0.2, -0.3), (0.5, 0.2, -0.1, -0.15, 0.4)):
+        sw = lambda w: s0 + s1 * (w - eks)
+        eg, el, Z = qp.qp_from_sigma_w(sw, lambda w: s1, eks, x, vxc)
+        exact = eks + (x + s0 - vxc) / (1.0 - s1)
+        assert abs(el - exact) < 1e-14 and abs(eg - exact) < 1e-9
+        assert np.isclose(Z, 1.0 / (1.0 - s1))
+
+
+def test_quadrature_exact_for_linear_sigma():
+    """Eq. 7 is integrated by the trapezoid rule on t_j = j dt,
+    j = -N_tau..N_tau, which is exact for a linear integrand: with no damping
+    (gamma = 0) and omega = 0, Sigma(t) = a + b t integrates to 2 a T,
+    T = N_tau dt, whatever b."""
+    dt, n_tau = 0.05, 40
+    t = dt * np.arange(-n_tau, n_tau + 1)
+    for a, b in ((1.0, 0.0), (0.3 - 0.2j, 1.7)):
+        val = qp.sigma_omega(a + b * t, dt, 0.0, 0.0)
+        assert abs(val - 2.0 * a * n_tau * dt) < 1e-12
+
 def test_damped_transform_of_single_pole():
     """Sigma(t) = -i a^2 e^{-i p t} theta(t) (Sigma(0) = half the limit):
     int_0^inf Sigma(t) e^{-g^2 t^2/2} e^{i w t} dt
