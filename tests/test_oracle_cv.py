@@ -154,6 +154,22 @@ def test_cv_unbiased_and_variance_ratio():
     assert 0.07 < ratio < 0.14, ratio
 
 
+
+def test_cv_exact_for_a_linear_relation():
+    """If y = a + b g holds exactly, the fit gives c = b, every residual
+    y - c g on B equals a, and the estimate is a + b mean_M(g) with the
+    variance of that term alone, b^2 Var_M(g) / M."""
+    rs = np.random.default_rng(8)
+    g = rs.standard_normal(300)
+    a, b = 1.25, -2.5
+    y = a + b * g
+    gm, gvar, M = 0.04, 0.9, 5000
+    r = cv.cv_estimate(y[:150], g[:150], y[150:], g[150:], gm, gvar, M)
+    assert np.isclose(r["c"], b, rtol=1e-12)
+    assert not r["fallback"]
+    assert abs(r["estimate"] - (a + b * gm)) < 1e-12
+    assert abs(r["sigma_cv"] - abs(b) * np.sqrt(gvar / M)) < 1e-9
+
 def test_cv_falls_back_on_a_biased_control_mean():
     rs = np.random.default_rng(7)
     u = rs.standard_normal(400)

@@ -32,3 +32,17 @@ def test_neutral_gaussian_pair_potential():
     ve += 2 * np.pi * q * (s1 ** 2 - s2 ** 2) / omega
     assert np.max(np.abs(v - ve)) < 1e-7
     assert abs(np.mean(v)) < 1e-12
+
+
+def test_uniform_charge_drops_out():
+    """With G = 0 dropped (a neutralising background), a uniform charge adds
+    nothing to v_H and a charged density's potential has zero mean: the
+    potentials of a single Gaussian and of that Gaussian plus a constant are
+    the same."""
+    g = Grid(24, h=0.5)
+    d = g.min_image(g.coords() - np.array(g.L) / 2)
+    rho = gauss3(np.sum(d * d, axis=1), 1.2)
+    v1 = hartree(g, rho)
+    v2 = hartree(g, rho + 0.37)
+    assert abs(np.mean(v1)) < 1e-12
+    assert np.max(np.abs(v1 - v2)) < 1e-12 * np.max(np.abs(v1))
