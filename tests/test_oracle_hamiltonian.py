@@ -146,6 +146,20 @@ def test_lanczos_bounds_enclose_and_converge(tiny8, tiny8_eig):
     assert lw <= lo and hi <= hw
 
 
+
+def test_lanczos_residual_widening_encloses(tiny8, tiny8_eig):
+    """Ritz values never leave the spectrum's hull, so it is the residual
+    term r = beta_k |y_last| that widens the interval to the extreme
+    eigenvalues: with no padding it encloses the 8^3 spectrum after 8, 10, 12
+    and 16 steps, while the extreme Ritz values alone stay inside it (after 5
+    steps it does not: the widening is a residual estimate, not a bound)."""
+    from oracle import eigen
+    s, H = tiny8
+    e, _ = tiny8_eig
+    for k in (8, 10, 12, 16):
+        lo, hi = eigen.lanczos_bounds(H, k, seed=3, pad=0.0)
+        assert lo <= e[0] and hi >= e[-1], k
+
 def test_lanczos_ritz_values_are_exact_for_a_diagonal_operator():
     """On a 3-level operator every Krylov space of dimension >= 3 holds the
     three eigenvectors' span: the Ritz values are the eigenvalues."""
